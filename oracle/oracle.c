@@ -1,0 +1,294 @@
+/*
+ * Plain CPU oracle for the QuEST gate path -- TEST INFRASTRUCTURE ONLY.
+ * Only the tests, the smoke check and the bench's CPU-baseline leg use it.
+ * Definitions and conventions are listed in oracle.h.
+ *
+ * Loops over independent amplitude pairs may run under OpenMP; every pair
+ * is still computed by the same expression, so the result does not depend
+ * on the thread count.  Sums are sequential and Neumaier-compensated.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+
+static uint64_t mask_of(const int* qs, int nq)
+{
+    uint64_t m = 0;
+    for (int k = 0; k < nq; ++k) m |= (uint64_t)1 << qs[k];
+    return m;
+}
+
+void or_init_basis(or_cplx* amp, uint64_t len, uint64_t index)
+{
+    for (uint64_t i = 0; i < len; ++i) amp[i] = 0;
+    amp[index] = 1;
+}
+
+/* Eq. 1 (Sec. II.B.1): for every i in [0, 2^(n-1)),
+ *   n_i = floor(i / 2^t) * 2^(t+1) + (i mod 2^t)
+ * and the pair (alpha_{n_i}, alpha_{n_i + 2^t}) is replaced by G times it.
+ * Multi-control generalisation: only pairs whose control bits are all 1. */
+void or_sv_unitary(or_cplx* amp, int n, const int* ctrls, int nctrl, int t,
+                   const or_cplx u[4])
+{
+    const uint64_t half = (uint64_t)1 << (n - 1);
+    const uint64_t step = (uint64_t)1 << t;
+    const uint64_t cmask = mask_of(ctrls, nctrl);
+    const or_cplx g00 = u[0], g01 = u[1], g10 = u[2], g11 = u[3];
+#pragma omp parallel for schedule(static) if (half >= 65536)
+    for (int64_t ii = 0; ii < (int64_t)half; ++ii) {
+        const uint64_t i = (uint64_t)ii;
+        const uint64_t ni = (i / step) * (2 * step) + (i % step);
+        if ((ni & cmask) != cmask) continue;
+        const or_cplx a = amp[ni];
+        const or_cplx b = amp[ni + step];
+        amp[ni] = g00 * a + g01 * b;
+        amp[ni + step] = g10 * a + g11 * b;
+    }
+}
+
+void or_sv_x(or_cplx* amp, int n, const int* ctrls, int nctrl, int t)
+{
+    const or_cplx x[4] = {0, 1, 1, 0};
+    or_sv_unitary(amp, n, ctrls, nctrl, t, x);
+}
+
+/* Diagonal multi-controlled phase: the amplitudes whose listed bits are all
+ * 1 are multiplied by exp(i angle); every other amplitude is unchanged. */
+void or_sv_phase(or_cplx* amp, int n, const int* qubits, int nq, double angle)
+{
+    const uint64_t len = (uint64_t)1 << n;
+    const uint64_t m = mask_of(qubits, nq);
+    const or_cplx f = cexp(I * angle);
+#pragma omp parallel for schedule(static) if (len >= 65536)
+    for (int64_t ii = 0; ii < (int64_t)len; ++ii) {
+        const uint64_t i = (uint64_t)ii;
+        if ((i & m) == m) amp[i] *= f;
+    }
+}
+
+/* Neumaier (improved Kahan-Babuska) summation, Z. Angew. Math. Mech. 54
+ * (1974) 39: carry the rounding error of every addition in c. */
+double or_neumaier_sum(const double* x, uint64_t len)
+{
+    double s = 0.0, c = 0.0;
+    for (uint64_t i = 0; i < len; ++i) {
+        const double t = s + x[i];
+        if (fabs(s) >= fabs(x[i])) c += (s - t) + x[i];
+        else c += (x[i] - t) + s;
+        s = t;
+    }
+    return s + c;
+}
+
+typedef struct { double s, c; } nsum;
+
+static void nsum_add(nsum* a, double v)
+{
+    const double t = a->s + v;
+    if (fabs(a->s) >= fabs(v)) a->c += (a->s - t) + v;
+    else a->c += (v - t) + a->s;
+    a->s = t;
+}
+
+static double abs2(or_cplx z) { return creal(z) * creal(z) + cimag(z) * cimag(z); }
+
+double or_sv_total_prob(const or_cplx* amp, int n)
+{
+    nsum acc = {0.0, 0.0};
+    const uint64_t len = (uint64_t)1 << n;
+    for (uint64_t i = 0; i < len; ++i) nsum_add(&acc, abs2(amp[i]));
+    return acc.s + acc.c;
+}
+
+double or_sv_prob_outcome(const or_cplx* amp, int n, int q, int outcome)
+{
+    nsum acc = {0.0, 0.0};
+    const uint64_t len = (uint64_t)1 << n;
+    for (uint64_t i = 0; i < len; ++i)
+        if ((int)((i >> q) & 1) == outcome) nsum_add(&acc, abs2(amp[i]));
+    return acc.s + acc.c;
+}
+
+/* Measurement of qubit q with the uniform draw r in [0, 1):
+ * p0 = P(q = 0) clamped to [0, 1]; outcome 0 iff r < p0; p = P(q = outcome)
+ * summed directly; kept amplitudes scaled by 1/sqrt(p), the rest zeroed. */
+int or_sv_measure(or_cplx* amp, int n, int q, double r, double* prob)
+{
+    double p0 = or_sv_prob_outcome(amp, n, q, 0);
+    if (p0 < 0.0) p0 = 0.0;
+    if (p0 > 1.0) p0 = 1.0;
+    const int outcome = (r < p0) ? 0 : 1;
+    const double p = or_sv_prob_outcome(amp, n, q, outcome);
+    const double scale = 1.0 / sqrt(p);
+    const uint64_t len = (uint64_t)1 << n;
+    for (uint64_t i = 0; i < len; ++i) {
+        if ((int)((i >> q) & 1) == outcome) amp[i] *= scale;
+        else amp[i] = 0;
+    }
+    if (prob) *prob = p;
+    return outcome;
+}
+
+/* ---- density matrices: rho as the 2N-qubit vector of Eq. 2 ----------- */
+
+/* G rho G^dagger as conj(G) on qubit t+N after G on qubit t (Sec. II.B.1);
+ * controls c act on rows in the first pass and as c+N on columns in the
+ * second. */
+void or_dm_unitary(or_cplx* rho, int N, const int* ctrls, int nctrl, int t,
+                   const or_cplx u[4])
+{
+    int* cshift = (int*)malloc(sizeof(int) * (nctrl > 0 ? nctrl : 1));
+    for (int k = 0; k < nctrl; ++k) cshift[k] = ctrls[k] + N;
+    const or_cplx uc[4] = {conj(u[0]), conj(u[1]), conj(u[2]), conj(u[3])};
+    or_sv_unitary(rho, 2 * N, ctrls, nctrl, t, u);
+    or_sv_unitary(rho, 2 * N, cshift, nctrl, t + N, uc);
+    free(cshift);
+}
+
+void or_dm_x(or_cplx* rho, int N, const int* ctrls, int nctrl, int t)
+{
+    const or_cplx x[4] = {0, 1, 1, 0};
+    or_dm_unitary(rho, N, ctrls, nctrl, t, x);
+}
+
+void or_dm_phase(or_cplx* rho, int N, const int* qubits, int nq, double angle)
+{
+    int* qshift = (int*)malloc(sizeof(int) * (nq > 0 ? nq : 1));
+    for (int k = 0; k < nq; ++k) qshift[k] = qubits[k] + N;
+    or_sv_phase(rho, 2 * N, qubits, nq, angle);
+    or_sv_phase(rho, 2 * N, qshift, nq, -angle);
+    free(qshift);
+}
+
+/* Kraus map on qubit t: every 2x2 block B of rho that varies only the row
+ * bit t and the column bit t is replaced by sum_m K_m B K_m^dagger, with
+ * plain 2x2 matrix products. */
+void or_dm_kraus(or_cplx* rho, int N, int t, const or_cplx* kraus, int nk)
+{
+    const uint64_t dim = (uint64_t)1 << N;
+    const uint64_t tb = (uint64_t)1 << t;
+#pragma omp parallel for schedule(static) if (dim >= 256)
+    for (int64_t jj = 0; jj < (int64_t)dim; ++jj) {
+        const uint64_t j = (uint64_t)jj;
+        if (j & tb) continue;
+        for (uint64_t k = 0; k < dim; ++k) {
+            if (k & tb) continue;
+            or_cplx B[2][2], S[2][2] = {{0, 0}, {0, 0}};
+            for (int r = 0; r < 2; ++r)
+                for (int c = 0; c < 2; ++c)
+                    B[r][c] = rho[(j | (r ? tb : 0)) + dim * (k | (c ? tb : 0))];
+            for (int m = 0; m < nk; ++m) {
+                const or_cplx* K = kraus + 4 * m;
+                or_cplx KB[2][2];
+                for (int r = 0; r < 2; ++r)
+                    for (int c = 0; c < 2; ++c)
+                        KB[r][c] = K[2 * r + 0] * B[0][c] + K[2 * r + 1] * B[1][c];
+                /* (K B K^dagger)[r][c] = sum_s (K B)[r][s] conj(K[c][s]) */
+                for (int r = 0; r < 2; ++r)
+                    for (int c = 0; c < 2; ++c)
+                        S[r][c] += KB[r][0] * conj(K[2 * c + 0]) + KB[r][1] * conj(K[2 * c + 1]);
+            }
+            for (int r = 0; r < 2; ++r)
+                for (int c = 0; c < 2; ++c)
+                    rho[(j | (r ? tb : 0)) + dim * (k | (c ? tb : 0))] = S[r][c];
+        }
+    }
+}
+
+/* Dephasing: rho -> (1-p) rho + p Z rho Z, Kraus {sqrt(1-p) I, sqrt(p) Z}. */
+void or_dm_dephasing(or_cplx* rho, int N, int t, double p)
+{
+    const double a = sqrt(1.0 - p), b = sqrt(p);
+    const or_cplx K[8] = {a, 0, 0, a,   b, 0, 0, -b};
+    or_dm_kraus(rho, N, t, K, 2);
+}
+
+/* Depolarising: rho -> (1-p) rho + (p/3)(X rho X + Y rho Y + Z rho Z). */
+void or_dm_depolarising(or_cplx* rho, int N, int t, double p)
+{
+    const double a = sqrt(1.0 - p), b = sqrt(p / 3.0);
+    const or_cplx K[16] = {a, 0, 0, a,
+                           0, b, b, 0,
+                           0, -I * b, I * b, 0,
+                           b, 0, 0, -b};
+    or_dm_kraus(rho, N, t, K, 4);
+}
+
+/* Amplitude damping: K0 = [[1, 0], [0, sqrt(1-g)]], K1 = [[0, sqrt(g)], [0, 0]]. */
+void or_dm_damping(or_cplx* rho, int N, int t, double gamma)
+{
+    const or_cplx K[8] = {1, 0, 0, sqrt(1.0 - gamma),   0, sqrt(gamma), 0, 0};
+    or_dm_kraus(rho, N, t, K, 2);
+}
+
+/* Total probability of a density matrix: its trace, sum_j Re rho[j][j]. */
+double or_dm_total_prob(const or_cplx* rho, int N)
+{
+    const uint64_t dim = (uint64_t)1 << N;
+    nsum acc = {0.0, 0.0};
+    for (uint64_t j = 0; j < dim; ++j) nsum_add(&acc, creal(rho[j + dim * j]));
+    return acc.s + acc.c;
+}
+
+double or_dm_prob_outcome(const or_cplx* rho, int N, int q, int outcome)
+{
+    const uint64_t dim = (uint64_t)1 << N;
+    nsum acc = {0.0, 0.0};
+    for (uint64_t j = 0; j < dim; ++j)
+        if ((int)((j >> q) & 1) == outcome) nsum_add(&acc, creal(rho[j + dim * j]));
+    return acc.s + acc.c;
+}
+
+/* Projective measurement of qubit q: rho -> P rho P / p with P the
+ * projector on the outcome; entries with row or column bit q != outcome
+ * vanish, the rest are divided by p. */
+int or_dm_measure(or_cplx* rho, int N, int q, double r, double* prob)
+{
+    double p0 = or_dm_prob_outcome(rho, N, q, 0);
+    if (p0 < 0.0) p0 = 0.0;
+    if (p0 > 1.0) p0 = 1.0;
+    const int outcome = (r < p0) ? 0 : 1;
+    const double p = or_dm_prob_outcome(rho, N, q, outcome);
+    const double scale = 1.0 / p;
+    const uint64_t dim = (uint64_t)1 << N;
+    for (uint64_t k = 0; k < dim; ++k)
+        for (uint64_t j = 0; j < dim; ++j) {
+            const int keep = ((int)((j >> q) & 1) == outcome) && ((int)((k >> q) & 1) == outcome);
+            if (keep) rho[j + dim * k] *= scale;
+            else rho[j + dim * k] = 0;
+        }
+    if (prob) *prob = p;
+    return outcome;
+}
+
+/* ---- single output amplitude ------------------------------------------ */
+
+static or_cplx amp_rec(int n, const or_cplx* v, const or_gate* g, int ng, uint64_t i)
+{
+    if (ng == 0) {
+        or_cplx a = 1;
+        for (int q = 0; q < n; ++q) a *= v[2 * q + (int)((i >> q) & 1)];
+        return a;
+    }
+    const or_gate* G = &g[ng - 1];
+    if (G->kind == OR_PHASE) {
+        const or_cplx a = amp_rec(n, v, g, ng - 1, i);
+        return ((i & G->mask) == G->mask) ? a * cexp(I * G->angle) : a;
+    }
+    if ((i & G->mask) != G->mask) return amp_rec(n, v, g, ng - 1, i);
+    const uint64_t tb = (uint64_t)1 << G->target;
+    if (G->kind == OR_X) return amp_rec(n, v, g, ng - 1, i ^ tb);
+    /* Eq. 1 read for one element: alpha'_i = G[b][0] alpha_{i, t=0} + G[b][1] alpha_{i, t=1} */
+    const int b = (int)((i >> G->target) & 1);
+    const or_cplx a0 = amp_rec(n, v, g, ng - 1, i & ~tb);
+    const or_cplx a1 = amp_rec(n, v, g, ng - 1, i | tb);
+    return G->u[2 * b + 0] * a0 + G->u[2 * b + 1] * a1;
+}
+
+or_cplx or_sv_amp_after(int n, const or_cplx* v, const or_gate* gates, int ng,
+                        uint64_t index)
+{
+    return amp_rec(n, v, gates, ng, index);
+}

@@ -1,0 +1,11 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the bench.
+
+This package generates inputs only: gate lists (random unitaries, angles, noise
+strengths), request streams and measurement draws.  It applies no gate, forms
+no probability and collapses nothing; the oracle and the HIP library each do
+that arithmetic on their own.
+"""
+from .circuits import (  # noqa: F401
+    Op, haar_unitary, layered_circuit, noisy_circuit, param_circuit,
+    measurement_draws, gate_counts, product_layer, X, H, ry, rz,
+)

@@ -1,0 +1,151 @@
+"""Seeded random circuits shaped like the paper's random-circuit benchmark.
+
+The paper (Sec. II.C) benchmarks random circuits whose gate count grows as
+O(n d), alternating single-qubit gates and controlled two-qubit gates on a
+linear topology.  The exact generator it cites is not reproduced here; the
+workloads below keep that shape with rules of their own:
+
+* ``layered_circuit``  -- per layer a Haar-random 2x2 unitary on every qubit
+  (ascending), then CNOT(q, q+1) on pairs starting at offset (layer mod 2);
+  optionally one multi-controlled phase per layer on 4 distinct random qubits.
+* ``noisy_circuit``    -- the same gates on an N-qubit density matrix; after
+  every gate each touched qubit (ascending) receives depolarising, dephasing
+  and amplitude damping, in that order.
+* ``param_circuit``    -- per layer RY(theta) then RZ(phi) on every qubit with
+  angles uniform in [0, 2 pi), then a CZ ladder on (q, q+1).
+
+Everything is drawn from ``numpy.random.Generator(PCG64(seed))`` so that the
+oracle and the GPU path receive identical gate lists.  Measurement draws use
+a Philox4x64-10 stream keyed by (seed, request id).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Fixed 2x2 matrices (row-major, element [r][c] multiplies the bit=c amplitude
+# into the bit=r amplitude, as in Eq. 1).
+X = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+H = np.array([[1, 1], [1, -1]], dtype=np.complex128) / math.sqrt(2.0)
+
+
+def ry(theta: float) -> np.ndarray:
+    """exp(-i theta Y / 2)."""
+    c, s = math.cos(theta / 2.0), math.sin(theta / 2.0)
+    return np.array([[c, -s], [s, c]], dtype=np.complex128)
+
+
+def rz(phi: float) -> np.ndarray:
+    """exp(-i phi Z / 2)."""
+    return np.array([[np.exp(-0.5j * phi), 0], [0, np.exp(0.5j * phi)]],
+                    dtype=np.complex128)
+
+
+@dataclass
+class Op:
+    """One circuit operation.
+
+    kind:
+      'u'            dense 2x2 ``u`` on ``target`` where every qubit in
+                     ``controls`` is 1
+      'x'            NOT on ``target`` where every control is 1 (CNOT, Toffoli)
+      'phase'        multiply by exp(i*angle) every amplitude whose bits in
+                     ``qubits`` are all 1 (CZ is angle = pi on two qubits)
+      'dephasing' / 'depolarising' / 'damping'
+                     single-qubit channel of strength ``p`` on ``target``
+    """
+    kind: str
+    target: int = -1
+    controls: tuple = ()
+    u: np.ndarray | None = None
+    qubits: tuple = ()
+    angle: float = 0.0
+    p: float = 0.0
+
+    def touched(self) -> tuple:
+        if self.kind == 'phase':
+            return tuple(sorted(self.qubits))
+        return tuple(sorted(set(self.controls) | {self.target}))
+
+
+def haar_unitary(rng: np.random.Generator) -> np.ndarray:
+    """Haar-random U(2): QR of a complex Gaussian matrix with the phases of
+    R's diagonal moved into Q (Mezzadri, Notices AMS 54 (2007) 592)."""
+    z = (rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))) / math.sqrt(2.0)
+    q, r = np.linalg.qr(z)
+    d = np.diagonal(r)
+    lam = d / np.abs(d)
+    return np.ascontiguousarray(q * lam[None, :], dtype=np.complex128)
+
+
+def layered_circuit(n: int, depth: int, seed: int, mcphase: bool = False) -> list[Op]:
+    """Haar layer + CNOT brick (+ one 4-qubit multi-controlled phase)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ops: list[Op] = []
+    for layer in range(depth):
+        for q in range(n):
+            ops.append(Op('u', target=q, u=haar_unitary(rng)))
+        q = layer % 2
+        while q + 1 < n:
+            ops.append(Op('x', target=q + 1, controls=(q,)))
+            q += 2
+        if mcphase:
+            picks = [int(v) for v in rng.choice(n, size=4, replace=False)]
+            phi = float(rng.uniform(0.0, 2.0 * math.pi))
+            ops.append(Op('phase', qubits=tuple(picks), angle=phi,
+                          controls=tuple(picks[:3]), target=picks[3]))
+    return ops
+
+
+def noisy_circuit(N: int, depth: int, seed: int, p_depol: float = 1e-3,
+                  p_deph: float = 1e-3, gamma: float = 2e-3) -> list[Op]:
+    """Layered circuit on an N-qubit density matrix with per-gate noise."""
+    ops: list[Op] = []
+    for g in layered_circuit(N, depth, seed):
+        ops.append(g)
+        for q in g.touched():
+            ops.append(Op('depolarising', target=q, p=p_depol))
+            ops.append(Op('dephasing', target=q, p=p_deph))
+            ops.append(Op('damping', target=q, p=gamma))
+    return ops
+
+
+def param_circuit(n: int, depth: int, seed: int) -> list[Op]:
+    """RY/RZ rotations on every qubit then a CZ ladder, per layer."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ops: list[Op] = []
+    for _ in range(depth):
+        for q in range(n):
+            theta, phi = rng.uniform(0.0, 2.0 * math.pi, size=2)
+            ops.append(Op('u', target=q, u=ry(float(theta))))
+            ops.append(Op('u', target=q, u=rz(float(phi))))
+        for q in range(n - 1):
+            ops.append(Op('phase', qubits=(q, q + 1), angle=math.pi,
+                          controls=(q,), target=q + 1))
+    return ops
+
+
+def product_layer(n: int, seed: int) -> list[Op]:
+    """One Haar unitary per qubit (a product state when applied to |0..0>)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return [Op('u', target=q, u=haar_unitary(rng)) for q in range(n)]
+
+
+def measurement_draws(seed: int, request_id: int, count: int) -> np.ndarray:
+    """Uniform [0, 1) doubles from Philox4x64-10 keyed by (seed, request id).
+
+    numpy forms each double as (x >> 11) * 2**-53 from one 64-bit output."""
+    gen = np.random.Generator(np.random.Philox(key=[seed & (2**64 - 1), request_id & (2**64 - 1)]))
+    return gen.random(count)
+
+
+def gate_counts(ops: list[Op]) -> dict:
+    out: dict = {}
+    for o in ops:
+        key = o.kind
+        if o.kind == 'u' and o.controls:
+            key = 'cu'
+        out[key] = out.get(key, 0) + 1
+    return out
