@@ -1,0 +1,202 @@
+"""Throughput of the gate path on one MI355X.
+
+Workload: one 32-qubit complex128 state vector (64 GiB) and a depth-10
+layered random circuit (per layer: a Haar-random unitary on every qubit, a
+CNOT brick, one phase gate with 3 controls + 1 target), 485 gates.  One step
+= init |0..0> + the whole circuit (fused into HBM round trips of 2^13-
+amplitude tiles) + total probability + probability of an outcome + one
+measurement.  Inputs are seeded and synthetic; the register is resident in
+HBM before the timed region starts.
+
+Prints one JSON line (metric, value = gates/s, roofline of the dominant
+kernel measured with HIP events around each of its launches, CPU oracle
+baseline on a bounded sample).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f'[bench] {msg}', file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(ops, n, elem):
+    """One-pass-per-gate byte model: a gate reads and writes every amplitude
+    it may change (2 E per amplitude)."""
+    total = 0
+    for o in ops:
+        if o.kind == 'u':
+            total += 2 * elem * (1 << (n - len(o.controls)))
+        elif o.kind == 'x':
+            total += 2 * elem * (1 << (n - len(o.controls)))
+        elif o.kind == 'phase':
+            total += 2 * elem * (1 << (n - len(o.qubits)))
+    return total
+
+
+def cpu_baseline(ops_full, n_full, sample_qubits=28, budget_s=12.0):
+    """Oracle (plain CPU code) applying the same circuit's gates to a
+    sample_qubits register until ~budget_s elapses; scaled to n_full by the
+    2^(n_full - sample_qubits) amplitude ratio (the cost per gate is linear
+    in the number of amplitudes)."""
+    import oracle as O
+    n = sample_qubits
+    amp = O.zero_state(n)
+    ops = [o for o in ops_full if max(o.touched()) < n][:200]
+    t0 = time.perf_counter()
+    done = 0
+    for op in ops:
+        O.apply_sv(amp, n, op)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    per_gate_full = dt / done * (1 << (n_full - n))
+    threads = int(os.environ.get('OMP_NUM_THREADS', os.cpu_count() or 1))
+    return {
+        'value': 1.0 / per_gate_full,
+        'unit': 'gates/s',
+        'cores': threads,
+        'kind': 'oracle',
+        'sample': f'first {done} gates of the same circuit on a {n}-qubit complex128 register '
+                  f'({dt:.1f} s), scaled by 2^{n_full - n} to {n_full} qubits',
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--gpus', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=5)
+    ap.add_argument('--warmup', type=int, default=1)
+    ap.add_argument('--qubits', type=int, default=32)
+    ap.add_argument('--depth', type=int, default=10)
+    ap.add_argument('--fusion', type=int, default=13)
+    ap.add_argument('--no-extras', action='store_true', help='skip unfused / per-target / CPU legs')
+    args = ap.parse_args()
+    if args.gpus != 1:
+        sys.exit('bench.py measures one GPU only: the method runs on one MI355X with the whole '
+                 'state resident; --gpus above 1 is not supported.')
+
+    import torch
+    import paper_1802_08032_amd as q
+    from workloads import layered_circuit, measurement_draws
+
+    n, depth, K = args.qubits, args.depth, args.fusion
+    elem = 16
+    ops = layered_circuit(n, depth, seed=1, mcphase=True)
+    gates = len(ops)
+    log(f'{n} qubits c128, depth {depth}, {gates} gates, fusion k={K}')
+    env = q.Env(0)
+    reg = q.Register(env, n, q.STATEVEC, q.C128)
+    circ = q.Circuit(ops)
+    draws = measurement_draws(1, 0, args.warmup + args.steps)
+
+    def step(i):
+        reg.init_zero()
+        passes = circ.run(reg, K)
+        reg.calc_total_prob()
+        reg.calc_prob_of_outcome(n - 1, 0)
+        reg.measure(0, float(draws[i]))
+        return passes
+
+    passes = 0
+    for i in range(args.warmup):
+        passes = step(i)
+        log(f'warmup {i} done ({passes} fused passes)')
+    torch.cuda.synchronize()
+    env.profile(True)
+    env.profile_reset()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i)
+        log(f'step {i} done')
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    launches, fused_ms = env.profile_read(q.qstate.K_FUSED)
+    env.profile(False)
+    ms_per_step = dt / args.steps * 1e3
+
+    # dominant kernel: the fused tile pass, one HBM read + write of the state
+    bytes_per_launch = 2 * elem * (1 << n)
+    avg_ms = fused_ms / max(1, launches)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+
+    step_bytes = (algorithmic_bytes(ops, n, elem) + elem * (1 << n) * (1 + 1 + 0.5 + 2.5))
+    eff_gbs = step_bytes * args.steps / dt / 1e9
+
+    out = {
+        'metric': 'gates/s & effective HBM GB/s (% peak), 32q SV; circuits/s + p99 latency',
+        'value': gates * args.steps / dt,
+        'unit': 'gates/s',
+        'n_gpus': 1,
+        'steps': args.steps,
+        'warmup': args.warmup,
+        'ms_per_step': ms_per_step,
+        'higher_is_better': True,
+        'scaling': 'weak',
+        'vs_baseline': None,
+        'dtype': 'f64',
+        'data': 'synthetic',
+        'config': {
+            'workload': f'{n}-qubit complex128 state vector, depth-{depth} layered random circuit '
+                        f'(Haar 1q layer + CNOT brick + 3-control phase per layer), fused k={K}',
+            'qubits': n, 'depth': depth, 'gates_per_step': gates, 'fusion_qubits': K,
+            'fused_passes_per_step': passes, 'parallelism': 'single GPU',
+        },
+        'circuits_per_s': args.steps / dt,
+        'effective_gbps': eff_gbs,
+        'effective_pct_peak': 100.0 * eff_gbs / HBM_PEAK_GBS,
+        'roofline': {
+            'bound': 'hbm', 'achieved': achieved, 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
+            'frac': achieved / HBM_PEAK_GBS, 'traffic': None,
+            'kernel': 'k_fused<double,8,5>', 'launches': launches, 'avg_ms': avg_ms,
+        },
+    }
+
+    if not args.no_extras:
+        # unfused circuit (one kernel per gate, the paper's one pass per gate)
+        log('unfused circuit')
+        reg.init_zero()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        circ.run(reg, 0)
+        torch.cuda.synchronize()
+        t_unf = time.perf_counter() - t1
+        out['unfused_gates_per_s'] = gates / t_unf
+        out['unfused_effective_gbps'] = algorithmic_bytes(ops, n, elem) / t_unf / 1e9
+        out['fused_pass_speedup'] = t_unf / (fused_ms / max(1, launches) * passes * 1e-3)
+        # per-target effective bandwidth of one dense gate (median of 5)
+        log('per-target sweep')
+        u = ops[0].u
+        per_t = []
+        for t in range(n):
+            times = []
+            for _ in range(5):
+                s = torch.cuda.Event(enable_timing=True)
+                e = torch.cuda.Event(enable_timing=True)
+                s.record()
+                reg.unitary(t, u)
+                e.record()
+                e.synchronize()
+                times.append(s.elapsed_time(e))
+            per_t.append(round(2 * elem * (1 << n) / (sorted(times)[2] * 1e-3) / 1e9, 1))
+        out['per_target_gbps'] = per_t
+        log('cpu baseline')
+        out['cpu_baseline'] = cpu_baseline(ops, n)
+    circ.close()
+    reg.close()
+    env.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == '__main__':
+    main()

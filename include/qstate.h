@@ -1,0 +1,184 @@
+/*
+ * qstate -- C ABI of the MI355X (gfx950) state-vector / density-matrix gate
+ * engine.  It implements the gate-application method of "QuEST and High
+ * Performance Simulation of Quantum Computers" (Jones, Brown, Bush, Benjamin,
+ * arXiv:1802.08032):
+ *   - Sec. II.B.1, Eq. 1: a single-qubit gate G on qubit q updates every
+ *     amplitude pair (alpha_a, alpha_{a + 2^q}) with bit q of a clear, in place;
+ *     multi-controlled gates restrict this to pairs whose control bits are 1;
+ *   - Sec. II.B.1, Eq. 2: an N-qubit density matrix rho is stored as a
+ *     2N-qubit vector, rho[j][k] at index j + 2^N k, and G rho G^dagger is
+ *     applied as G on qubit q and conj(G) on qubit q + N;
+ *   - the decoherence channels named in the abstract and Sec. II.B.1
+ *     (dephasing, depolarising) plus amplitude damping, as Kraus maps;
+ *   - total probability, outcome probability and projective measurement.
+ *
+ * Conventions
+ *   - Qubit q is bit q of the amplitude index (little endian).
+ *   - Amplitudes are interleaved complex numbers in device memory:
+ *     QS_C128 = two doubles (16 B), QS_C64 = two floats (8 B).  A register
+ *     of n qubits holds 2^n amplitudes (QS_STATEVEC) or 4^n (QS_DENSITY).
+ *   - Host-side 2x2 matrices are row-major qs_cplx[4] in double precision:
+ *     u[2r + c] multiplies the bit=c amplitude into the bit=r amplitude.
+ *     For QS_C64 registers the matrix is rounded to float once per call.
+ *   - Every call returns a qs_status; QS_OK == 0.  Arguments are validated
+ *     on the host before anything is launched, so a failed call leaves the
+ *     register unchanged.  qs_last_error() gives the calling thread's last
+ *     message.  Nothing in the library exits or aborts the process.
+ *   - Gates, channels and initialisation are asynchronous on the register's
+ *     HIP stream.  qs_calc_*, qs_measure* and qs_get_amps synchronise it.
+ *   - The library is thread-safe across different registers; calls on one
+ *     register must not overlap.
+ */
+#ifndef QSTATE_H
+#define QSTATE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qs_env_s* qs_env;         /* device + profiling state            */
+typedef struct qs_reg_s* qs_reg;         /* one quantum register (Qureg)        */
+typedef struct qs_circuit_s* qs_circuit; /* recorded gate list + fusion plan    */
+
+typedef enum { QS_STATEVEC = 0, QS_DENSITY = 1 } qs_kind;
+typedef enum { QS_C64 = 1, QS_C128 = 2 } qs_prec;
+typedef struct { double re, im; } qs_cplx;
+
+typedef enum {
+    QS_OK = 0,
+    QS_E_ARG = -1,         /* qubit out of range, duplicate qubits, bad probability, ... */
+    QS_E_KIND = -2,        /* operation not defined for this register kind               */
+    QS_E_OOM = -3,         /* device allocation failed                                   */
+    QS_E_DEVICE = -4,      /* a HIP call failed; qs_last_error() has hipGetErrorString   */
+    QS_E_HANDLE = -5,      /* null, destroyed or foreign handle                          */
+    QS_E_NOT_UNITARY = -6  /* max |U U^dagger - I| > 1e-10                               */
+} qs_status;
+
+/* Channel kinds for qs_circuit_add_channel. */
+typedef enum { QS_DEPHASING = 0, QS_DEPOLARISING = 1, QS_DAMPING = 2 } qs_channel;
+
+/* Kernel classes for the per-launch profiler. */
+typedef enum {
+    QS_K_INIT = 0, QS_K_GATE = 1, QS_K_GATE_LOW = 2, QS_K_NOT = 3, QS_K_PHASE = 4,
+    QS_K_DM_GATE = 5, QS_K_DM_CHANNEL = 6, QS_K_REDUCE = 7, QS_K_COLLAPSE = 8,
+    QS_K_FUSED = 9, QS_K_COUNT = 10
+} qs_kernel_class;
+
+/* ---- environment ------------------------------------------------------- */
+
+/* Bind HIP device `device` (createQuESTEnv, Sec. III.B.2).  *out is owned
+ * by the caller and released with qs_env_destroy. */
+qs_status qs_env_create(int device, qs_env* out);
+qs_status qs_env_destroy(qs_env env);
+/* Wait until all work on every register of this environment has finished
+ * (syncQuESTEnv, Sec. III.B.2). */
+qs_status qs_env_sync(qs_env env);
+/* Text of the calling thread's most recent error (never NULL). */
+const char* qs_last_error(void);
+
+/* Per-launch timing: when enabled, every kernel launch is bracketed by two
+ * HIP events on the register's stream.  qs_profile_read synchronises the
+ * device, folds the recorded pairs into per-class totals and returns the
+ * launch count and summed milliseconds of class `klass` since the last
+ * reset. */
+qs_status qs_profile_enable(qs_env env, int enable);
+qs_status qs_profile_read(qs_env env, int klass, uint64_t* launches, double* total_ms);
+qs_status qs_profile_reset(qs_env env);
+
+/* ---- registers --------------------------------------------------------- */
+
+/* Bytes of amplitude storage: (8 or 16) * 2^n for a state vector, * 4^n
+ * for a density matrix (Sec. II.B.1: 16 x 2^n B in double precision).
+ * Returns 0 for invalid arguments or sizes that overflow size_t. */
+size_t qs_reg_bytes(int n, int kind, int prec);
+
+/* Allocate a register of n qubits (1 <= n <= 40 for state vectors,
+ * 1 <= n <= 20 for density matrices) on `hip_stream` (a hipStream_t, NULL
+ * for the default stream).  Contents are undefined until an init call.
+ * The library owns the memory; qs_reg_destroy frees it. */
+qs_status qs_reg_create(qs_env env, int n, int kind, int prec, void* hip_stream, qs_reg* out);
+/* As qs_reg_create, over caller-owned device memory `dev_ptr` of at least
+ * qs_reg_bytes(n, kind, prec) bytes, 16-byte aligned.  The memory must
+ * outlive the handle and is not freed by qs_reg_destroy. */
+qs_status qs_reg_wrap(qs_env env, int n, int kind, int prec, void* dev_ptr, size_t bytes,
+                      void* hip_stream, qs_reg* out);
+qs_status qs_reg_destroy(qs_reg r);
+/* Read back the register's shape; any output pointer may be NULL. */
+qs_status qs_reg_info(qs_reg r, int* n, int* kind, int* prec, void** dev_ptr, void** hip_stream);
+
+/* |0..0> (initZeroState, Sec. III.B.2), or |index><index| for a density matrix. */
+qs_status qs_init_zero(qs_reg r);
+/* Basis state |index>, 0 <= index < 2^n. */
+qs_status qs_init_basis(qs_reg r, uint64_t index);
+/* Direct amplitude access (Sec. II.B.1): copy `count` amplitudes starting
+ * at raw vector index `start` (for a density matrix, index j + 2^N k) to or
+ * from host memory.  Synchronous. */
+qs_status qs_get_amps(qs_reg r, uint64_t start, uint64_t count, qs_cplx* host_out);
+qs_status qs_set_amps(qs_reg r, uint64_t start, uint64_t count, const qs_cplx* host_in);
+
+/* ---- gates (Eq. 1; on a density matrix, Eq. 2 with conj(u) on q + N) ---- */
+
+/* Dense single-qubit unitary `u` on `target`. */
+qs_status qs_unitary(qs_reg r, int target, const qs_cplx u[4]);
+qs_status qs_controlled_unitary(qs_reg r, int control, int target, const qs_cplx u[4]);
+/* Apply `u` on `target` to the pairs whose `n_controls` control bits are
+ * all 1.  Controls must be distinct and differ from the target. */
+qs_status qs_multi_controlled_unitary(qs_reg r, const int* controls, int n_controls,
+                                      int target, const qs_cplx u[4]);
+/* Multi-controlled NOT (CNOT for one control): a permutation of pairs. */
+qs_status qs_multi_controlled_not(qs_reg r, const int* controls, int n_controls, int target);
+/* Diagonal phase: amplitudes whose bits in `qubits` are all 1 are
+ * multiplied by exp(i angle) (CZ is angle = pi on two qubits). */
+qs_status qs_multi_controlled_phase(qs_reg r, const int* qubits, int n_qubits, double angle);
+
+/* ---- decoherence channels (density matrices only) ---------------------- */
+
+/* rho -> (1-p) rho + p Z rho Z,                       0 <= p <= 1/2 */
+qs_status qs_mix_dephasing(qs_reg r, int target, double p);
+/* rho -> (1-p) rho + (p/3)(X rho X + Y rho Y + Z rho Z), 0 <= p <= 3/4 */
+qs_status qs_mix_depolarising(qs_reg r, int target, double p);
+/* Kraus {[[1,0],[0,sqrt(1-g)]], [[0,sqrt(g)],[0,0]]},   0 <= g <= 1 */
+qs_status qs_mix_damping(qs_reg r, int target, double gamma);
+
+/* ---- probabilities and measurement -------------------------------------- */
+
+/* sum |alpha|^2 (state vector) or trace (density matrix), accumulated in
+ * double precision with compensated sums.  Synchronous. */
+qs_status qs_calc_total_prob(qs_reg r, double* out);
+/* Probability that `qubit` reads `outcome` (0 or 1).  Synchronous. */
+qs_status qs_calc_prob_of_outcome(qs_reg r, int qubit, int outcome, double* out);
+/* Projective measurement with the caller's uniform draw u01 in [0, 1):
+ * p0 = P(qubit = 0) clamped to [0, 1]; outcome = (u01 < p0) ? 0 : 1; the
+ * other branch is zeroed and the kept one scaled by 1/sqrt(p) (state
+ * vector) or 1/p (density matrix), with the scale formed in double
+ * precision.  *prob receives P(outcome).  Synchronous. */
+qs_status qs_measure(qs_reg r, int qubit, double u01, int* outcome, double* prob);
+
+/* ---- circuits: recorded gate lists with optional gate fusion ------------ */
+
+qs_status qs_circuit_create(qs_circuit* out);
+qs_status qs_circuit_destroy(qs_circuit c);
+qs_status qs_circuit_add_unitary(qs_circuit c, const int* controls, int n_controls, int target,
+                                 const qs_cplx u[4]);
+qs_status qs_circuit_add_not(qs_circuit c, const int* controls, int n_controls, int target);
+qs_status qs_circuit_add_phase(qs_circuit c, const int* qubits, int n_qubits, double angle);
+qs_status qs_circuit_add_channel(qs_circuit c, int channel, int target, double p);
+/* Number of recorded operations. */
+qs_status qs_circuit_size(qs_circuit c, int* n_ops);
+/* Apply the circuit to `r`.  fusion_qubits = 0 launches one kernel per
+ * operation (the one-pass-per-gate method of Sec. II.B.1).  fusion_qubits
+ * = k > 0 groups consecutive gates whose qubits fit in a set of at most k
+ * qubits and applies each group in one read and one write of the state
+ * (gate fusion, Sec. II.B).  *n_passes (may be NULL) receives the number
+ * of full-state kernel passes launched. */
+qs_status qs_circuit_run(qs_reg r, qs_circuit c, int fusion_qubits, int* n_passes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QSTATE_H */

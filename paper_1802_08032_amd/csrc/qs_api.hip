@@ -1,0 +1,766 @@
+// The qstate C ABI: handle management, host-side validation and dispatch to
+// the gfx950 kernels.  Validation always completes before the first launch,
+// so a call that fails leaves the register as it was.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <unordered_set>
+
+#include "qs_host.h"
+
+namespace {
+
+constexpr uint32_t kEnvMagic = 0x51454e56u;  // "QENV"
+constexpr uint32_t kRegMagic = 0x51524547u;  // "QREG"
+constexpr uint32_t kCircMagic = 0x51435243u; // "QCRC"
+
+thread_local std::string g_error = "no error";
+
+std::mutex g_handles_mu;
+std::unordered_set<const void*> g_handles;
+
+void handle_add(const void* p)
+{
+    std::lock_guard<std::mutex> g(g_handles_mu);
+    g_handles.insert(p);
+}
+
+bool handle_remove(const void* p)
+{
+    std::lock_guard<std::mutex> g(g_handles_mu);
+    return g_handles.erase(p) == 1;
+}
+
+bool handle_live(const void* p)
+{
+    std::lock_guard<std::mutex> g(g_handles_mu);
+    return g_handles.count(p) == 1;
+}
+
+// QS_FAULT_ALLOC=k makes the k-th device allocation of the process fail
+// (host-forced out-of-memory for the error-path tests).
+std::mutex g_alloc_mu;
+long g_alloc_count = 0;
+
+hipError_t dev_alloc(void** p, size_t bytes)
+{
+    {
+        std::lock_guard<std::mutex> g(g_alloc_mu);
+        ++g_alloc_count;
+        const char* f = getenv("QS_FAULT_ALLOC");
+        if (f && atol(f) == g_alloc_count) return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+bool valid_env(qs_env e) { return e && handle_live(e) && e->magic == kEnvMagic; }
+bool valid_reg(qs_reg r) { return r && handle_live(r) && r->magic == kRegMagic; }
+bool valid_circ(qs_circuit c) { return c && handle_live(c) && c->magic == kCircMagic; }
+
+#define QS_CHECK_REG(r) \
+    if (!valid_reg(r)) return qs::set_error(QS_E_HANDLE, "invalid register handle")
+
+#define QS_HIP(call)                                             \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return qs::hip_error(e_, #call);   \
+    } while (0)
+
+qs::Launch launch_of(qs_reg r) { return qs::Launch{r->stream, r->env->device}; }
+
+// Qubit list checks: each in [0, n), all distinct, none equal to `exclude`.
+qs_status check_qubits(const int* qs_, int count, int n, int exclude, const char* what)
+{
+    if (count < 0 || count > 62) return qs::set_error(QS_E_ARG, std::string(what) + ": bad count");
+    if (count > 0 && !qs_) return qs::set_error(QS_E_ARG, std::string(what) + ": NULL list");
+    uint64_t seen = 0;
+    for (int k = 0; k < count; ++k) {
+        const int q = qs_[k];
+        if (q < 0 || q >= n)
+            return qs::set_error(QS_E_ARG, std::string(what) + ": qubit " + std::to_string(q) +
+                                               " outside [0, " + std::to_string(n) + ")");
+        if (q == exclude)
+            return qs::set_error(QS_E_ARG, std::string(what) + ": control equals the target");
+        if ((seen >> q) & 1) return qs::set_error(QS_E_ARG, std::string(what) + ": duplicate qubit");
+        seen |= 1ull << q;
+    }
+    return QS_OK;
+}
+
+qs_status check_target(int t, int n)
+{
+    if (t < 0 || t >= n)
+        return qs::set_error(QS_E_ARG, "target qubit " + std::to_string(t) + " outside [0, " +
+                                           std::to_string(n) + ")");
+    return QS_OK;
+}
+
+qs_status check_unitary(const qs_cplx* u)
+{
+    if (!u) return qs::set_error(QS_E_ARG, "NULL matrix");
+    for (int k = 0; k < 4; ++k)
+        if (!isfinite(u[k].re) || !isfinite(u[k].im)) return qs::set_error(QS_E_ARG, "non-finite matrix");
+    // (U U^dagger)[r][c] = sum_s U[r][s] conj(U[c][s])
+    double worst = 0.0;
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) {
+            double re = 0.0, im = 0.0;
+            for (int s = 0; s < 2; ++s) {
+                const qs_cplx a = u[2 * r + s], b = u[2 * c + s];
+                re += a.re * b.re + a.im * b.im;
+                im += a.im * b.re - a.re * b.im;
+            }
+            if (r == c) re -= 1.0;
+            worst = std::max(worst, std::max(fabs(re), fabs(im)));
+        }
+    if (worst > 1e-10) return qs::set_error(QS_E_NOT_UNITARY, "matrix is not unitary");
+    return QS_OK;
+}
+
+template <typename T>
+qs::Mat2<T> to_mat(const double* u8)
+{
+    qs::Mat2<T> m;
+    for (int k = 0; k < 8; ++k) m.m[k] = (T)u8[k];
+    return m;
+}
+
+size_t elem_bytes(int prec) { return prec == QS_C128 ? 16 : 8; }
+
+qs_status sync_stream(qs_reg r)
+{
+    QS_HIP(hipStreamSynchronize(r->stream));
+    return QS_OK;
+}
+
+// --- per-operation dispatch -------------------------------------------------
+
+template <typename T>
+qs_status do_dense(qs_reg r, const int* ctrls, int nc, int t, const double* u8)
+{
+    const qs::Mat2<T> m = to_mat<T>(u8);
+    const qs::Launch L = launch_of(r);
+    if (r->kind == QS_DENSITY)
+        return qs::profiled(r, QS_K_DM_GATE, [&](int*) {
+            return qs::launch_dm_gate<T>(L, r->amp, r->n, t, ctrls, nc, m);
+        });
+    return qs::profiled(r, QS_K_GATE, [&](int* klass) {
+        return qs::launch_gate<T>(L, r->amp, r->nbits, t, ctrls, nc, m, klass);
+    });
+}
+
+template <typename T>
+qs_status do_not(qs_reg r, const int* ctrls, int nc, int t)
+{
+    const qs::Launch L = launch_of(r);
+    if (r->kind == QS_DENSITY) {
+        const double x[8] = {0, 0, 1, 0, 1, 0, 0, 0};
+        const qs::Mat2<T> m = to_mat<T>(x);
+        return qs::profiled(r, QS_K_DM_GATE, [&](int*) {
+            return qs::launch_dm_gate<T>(L, r->amp, r->n, t, ctrls, nc, m);
+        });
+    }
+    return qs::profiled(r, QS_K_NOT, [&](int*) {
+        return qs::launch_not<T>(L, r->amp, r->nbits, t, ctrls, nc);
+    });
+}
+
+template <typename T>
+qs_status do_phase(qs_reg r, const int* qubits, int nq, double angle)
+{
+    const qs::Launch L = launch_of(r);
+    uint64_t mask = 0;
+    for (int k = 0; k < nq; ++k) mask |= 1ull << qubits[k];
+    const double c = cos(angle), s = sin(angle);
+    if (r->kind == QS_DENSITY) {
+        // rows with all bits set gain exp(i a), columns with all bits set
+        // gain exp(-i a); entries with both keep their value.
+        const uint64_t cmask = mask << r->n;
+        qs_status st = qs::profiled(r, QS_K_PHASE, [&](int*) {
+            return qs::launch_phase<T>(L, r->amp, r->nbits, mask, cmask, c, s);
+        });
+        if (st != QS_OK) return st;
+        return qs::profiled(r, QS_K_PHASE, [&](int*) {
+            return qs::launch_phase<T>(L, r->amp, r->nbits, cmask, mask, c, -s);
+        });
+    }
+    return qs::profiled(r, QS_K_PHASE, [&](int*) {
+        return qs::launch_phase<T>(L, r->amp, r->nbits, mask, 0, c, s);
+    });
+}
+
+template <typename T>
+qs_status do_channel(qs_reg r, int channel, int t, double p)
+{
+    const qs::Launch L = launch_of(r);
+    return qs::profiled(r, QS_K_DM_CHANNEL, [&](int*) {
+        return qs::launch_dm_channel<T>(L, r->amp, r->n, t, channel, p);
+    });
+}
+
+qs_status check_channel(qs_reg r, int channel, int t, double p)
+{
+    if (r->kind != QS_DENSITY) return qs::set_error(QS_E_KIND, "channels need a density matrix");
+    qs_status s = check_target(t, r->n);
+    if (s) return s;
+    double hi = 1.0;
+    if (channel == QS_DEPHASING) hi = 0.5;
+    else if (channel == QS_DEPOLARISING) hi = 0.75;
+    else if (channel != QS_DAMPING) return qs::set_error(QS_E_ARG, "unknown channel");
+    if (!(p >= 0.0 && p <= hi)) return qs::set_error(QS_E_ARG, "channel strength out of range");
+    return QS_OK;
+}
+
+// Probabilities: out[0] = sum over bit q == 0, out[1] = bit q == 1 (q < 0:
+// total in out[0]).  Synchronous.
+qs_status probs(qs_reg r, int q, double out[2])
+{
+    const qs::Launch L = launch_of(r);
+    double* partials = r->scratch;
+    double* dev_out = r->scratch + 4 * qs::kReduceBlocks;
+    qs_status st = qs::profiled(r, QS_K_REDUCE, [&](int*) {
+        if (r->kind == QS_DENSITY)
+            return r->prec == QS_C128 ? qs::launch_prob_dm<double>(L, r->amp, r->n, q, partials, dev_out)
+                                      : qs::launch_prob_dm<float>(L, r->amp, r->n, q, partials, dev_out);
+        return r->prec == QS_C128 ? qs::launch_prob_sv<double>(L, r->amp, r->nbits, q, partials, dev_out)
+                                  : qs::launch_prob_sv<float>(L, r->amp, r->nbits, q, partials, dev_out);
+    });
+    if (st) return st;
+    QS_HIP(hipMemcpyAsync(r->host_res, dev_out, 2 * sizeof(double), hipMemcpyDeviceToHost, r->stream));
+    if ((st = sync_stream(r))) return st;
+    out[0] = r->host_res[0];
+    out[1] = r->host_res[1];
+    return QS_OK;
+}
+
+}  // namespace
+
+namespace qs {
+
+qs_status set_error(qs_status s, const std::string& msg)
+{
+    g_error = msg;
+    return s;
+}
+
+qs_status hip_error(hipError_t e, const char* what)
+{
+    g_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? QS_E_OOM : QS_E_DEVICE;
+}
+
+qs_status apply_op(qs_reg r, const OpRec& op)
+{
+    const bool dbl = r->prec == QS_C128;
+    const int* c = op.ctrls.data();
+    const int nc = (int)op.ctrls.size();
+    switch (op.kind) {
+    case 0: return dbl ? do_dense<double>(r, c, nc, op.target, op.u) : do_dense<float>(r, c, nc, op.target, op.u);
+    case 1: return dbl ? do_not<double>(r, c, nc, op.target) : do_not<float>(r, c, nc, op.target);
+    case 2: return dbl ? do_phase<double>(r, c, nc, op.angle) : do_phase<float>(r, c, nc, op.angle);
+    default:
+        return dbl ? do_channel<double>(r, op.channel, op.target, op.p)
+                   : do_channel<float>(r, op.channel, op.target, op.p);
+    }
+}
+
+}  // namespace qs
+
+// ===========================================================================
+extern "C" {
+
+const char* qs_last_error(void) { return g_error.c_str(); }
+
+qs_status qs_env_create(int device, qs_env* out)
+{
+    if (!out) return qs::set_error(QS_E_ARG, "NULL output");
+    int count = 0;
+    QS_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return qs::set_error(QS_E_ARG, "no such device");
+    QS_HIP(hipSetDevice(device));
+    qs_env e = new qs_env_s();
+    e->magic = kEnvMagic;
+    e->device = device;
+    e->profile = false;
+    for (int k = 0; k < QS_K_COUNT; ++k) {
+        e->launches[k] = 0;
+        e->ms[k] = 0.0;
+    }
+    handle_add(e);
+    *out = e;
+    return QS_OK;
+}
+
+qs_status qs_env_destroy(qs_env env)
+{
+    if (!valid_env(env) || !handle_remove(env)) return qs::set_error(QS_E_HANDLE, "invalid environment handle");
+    hipSetDevice(env->device);
+    for (auto& rec : env->recs) {
+        hipEventDestroy(rec.a);
+        hipEventDestroy(rec.b);
+    }
+    env->magic = 0;
+    delete env;
+    return QS_OK;
+}
+
+qs_status qs_env_sync(qs_env env)
+{
+    if (!valid_env(env)) return qs::set_error(QS_E_HANDLE, "invalid environment handle");
+    QS_HIP(hipSetDevice(env->device));
+    QS_HIP(hipDeviceSynchronize());
+    return QS_OK;
+}
+
+qs_status qs_profile_enable(qs_env env, int enable)
+{
+    if (!valid_env(env)) return qs::set_error(QS_E_HANDLE, "invalid environment handle");
+    env->profile = enable != 0;
+    return QS_OK;
+}
+
+static qs_status fold_profile(qs_env env)
+{
+    QS_HIP(hipSetDevice(env->device));
+    QS_HIP(hipDeviceSynchronize());
+    std::lock_guard<std::mutex> g(env->mu);
+    for (auto& rec : env->recs) {
+        float ms = 0.0f;
+        QS_HIP(hipEventElapsedTime(&ms, rec.a, rec.b));
+        env->launches[rec.klass] += 1;
+        env->ms[rec.klass] += ms;
+        hipEventDestroy(rec.a);
+        hipEventDestroy(rec.b);
+    }
+    env->recs.clear();
+    return QS_OK;
+}
+
+qs_status qs_profile_read(qs_env env, int klass, uint64_t* launches, double* total_ms)
+{
+    if (!valid_env(env)) return qs::set_error(QS_E_HANDLE, "invalid environment handle");
+    if (klass < 0 || klass >= QS_K_COUNT) return qs::set_error(QS_E_ARG, "unknown kernel class");
+    qs_status s = fold_profile(env);
+    if (s) return s;
+    if (launches) *launches = env->launches[klass];
+    if (total_ms) *total_ms = env->ms[klass];
+    return QS_OK;
+}
+
+qs_status qs_profile_reset(qs_env env)
+{
+    if (!valid_env(env)) return qs::set_error(QS_E_HANDLE, "invalid environment handle");
+    qs_status s = fold_profile(env);
+    if (s) return s;
+    for (int k = 0; k < QS_K_COUNT; ++k) {
+        env->launches[k] = 0;
+        env->ms[k] = 0.0;
+    }
+    return QS_OK;
+}
+
+size_t qs_reg_bytes(int n, int kind, int prec)
+{
+    if (prec != QS_C64 && prec != QS_C128) return 0;
+    int bits;
+    if (kind == QS_STATEVEC) {
+        if (n < 1 || n > 40) return 0;
+        bits = n;
+    } else if (kind == QS_DENSITY) {
+        if (n < 1 || n > 20) return 0;
+        bits = 2 * n;
+    } else {
+        return 0;
+    }
+    return elem_bytes(prec) << bits;
+}
+
+static qs_status reg_common(qs_env env, int n, int kind, int prec, void* stream, qs_reg* out,
+                            void* dev_ptr, size_t bytes)
+{
+    if (!valid_env(env)) return qs::set_error(QS_E_HANDLE, "invalid environment handle");
+    if (!out) return qs::set_error(QS_E_ARG, "NULL output");
+    const size_t need = qs_reg_bytes(n, kind, prec);
+    if (need == 0) return qs::set_error(QS_E_ARG, "invalid qubit count, kind or precision");
+    if (dev_ptr && bytes < need) return qs::set_error(QS_E_ARG, "wrapped buffer too small");
+    if (dev_ptr && ((uintptr_t)dev_ptr & 15)) return qs::set_error(QS_E_ARG, "wrapped buffer not 16-byte aligned");
+    QS_HIP(hipSetDevice(env->device));
+    void* amp = dev_ptr;
+    if (!amp) {
+        const hipError_t e = dev_alloc(&amp, need);
+        if (e != hipSuccess) {
+            hipGetLastError();
+            return qs::set_error(QS_E_OOM, "cannot allocate " + std::to_string(need) + " bytes");
+        }
+    }
+    void* scratch = nullptr;
+    const size_t sbytes = (4 * qs::kReduceBlocks + 2) * sizeof(double);
+    hipError_t e = dev_alloc(&scratch, sbytes);
+    void* hres = nullptr;
+    if (e == hipSuccess) e = hipHostMalloc(&hres, 2 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        hipGetLastError();
+        if (scratch) hipFree(scratch);
+        if (!dev_ptr) hipFree(amp);
+        return qs::set_error(QS_E_OOM, "cannot allocate register scratch");
+    }
+    qs_reg r = new qs_reg_s();
+    r->magic = kRegMagic;
+    r->env = env;
+    r->n = n;
+    r->nbits = kind == QS_DENSITY ? 2 * n : n;
+    r->kind = kind;
+    r->prec = prec;
+    r->amp = amp;
+    r->bytes = need;
+    r->owned = dev_ptr == nullptr;
+    r->stream = (hipStream_t)stream;
+    r->scratch = (double*)scratch;
+    r->host_res = (double*)hres;
+    handle_add(r);
+    *out = r;
+    return QS_OK;
+}
+
+qs_status qs_reg_create(qs_env env, int n, int kind, int prec, void* hip_stream, qs_reg* out)
+{
+    return reg_common(env, n, kind, prec, hip_stream, out, nullptr, 0);
+}
+
+qs_status qs_reg_wrap(qs_env env, int n, int kind, int prec, void* dev_ptr, size_t bytes,
+                      void* hip_stream, qs_reg* out)
+{
+    if (!dev_ptr) return qs::set_error(QS_E_ARG, "NULL device pointer");
+    return reg_common(env, n, kind, prec, hip_stream, out, dev_ptr, bytes);
+}
+
+qs_status qs_reg_destroy(qs_reg r)
+{
+    if (!valid_reg(r) || !handle_remove(r)) return qs::set_error(QS_E_HANDLE, "invalid register handle");
+    hipSetDevice(r->env->device);
+    hipStreamSynchronize(r->stream);
+    if (r->owned) hipFree(r->amp);
+    hipFree(r->scratch);
+    hipHostFree(r->host_res);
+    r->magic = 0;
+    delete r;
+    return QS_OK;
+}
+
+qs_status qs_reg_info(qs_reg r, int* n, int* kind, int* prec, void** dev_ptr, void** hip_stream)
+{
+    QS_CHECK_REG(r);
+    if (n) *n = r->n;
+    if (kind) *kind = r->kind;
+    if (prec) *prec = r->prec;
+    if (dev_ptr) *dev_ptr = r->amp;
+    if (hip_stream) *hip_stream = (void*)r->stream;
+    return QS_OK;
+}
+
+qs_status qs_init_basis(qs_reg r, uint64_t index)
+{
+    QS_CHECK_REG(r);
+    if (r->n < 64 && index >= (1ull << r->n)) return qs::set_error(QS_E_ARG, "basis index out of range");
+    const uint64_t len = 1ull << r->nbits;
+    const uint64_t pos = r->kind == QS_DENSITY ? index + (index << r->n) : index;
+    const qs::Launch L = launch_of(r);
+    return qs::profiled(r, QS_K_INIT, [&](int*) {
+        return r->prec == QS_C128 ? qs::launch_init_basis<double>(L, r->amp, len, pos)
+                                  : qs::launch_init_basis<float>(L, r->amp, len, pos);
+    });
+}
+
+qs_status qs_init_zero(qs_reg r) { return qs_init_basis(r, 0); }
+
+qs_status qs_get_amps(qs_reg r, uint64_t start, uint64_t count, qs_cplx* host_out)
+{
+    QS_CHECK_REG(r);
+    const uint64_t len = 1ull << r->nbits;
+    if (start > len || count > len - start) return qs::set_error(QS_E_ARG, "amplitude range outside the register");
+    if (count == 0) return QS_OK;
+    if (!host_out) return qs::set_error(QS_E_ARG, "NULL host buffer");
+    if (r->prec == QS_C128) {
+        QS_HIP(hipMemcpyAsync(host_out, (char*)r->amp + 16 * start, 16 * count, hipMemcpyDeviceToHost, r->stream));
+        return sync_stream(r);
+    }
+    std::vector<float> tmp(2 * count);
+    QS_HIP(hipMemcpyAsync(tmp.data(), (char*)r->amp + 8 * start, 8 * count, hipMemcpyDeviceToHost, r->stream));
+    qs_status s = sync_stream(r);
+    if (s) return s;
+    for (uint64_t i = 0; i < count; ++i) {
+        host_out[i].re = tmp[2 * i];
+        host_out[i].im = tmp[2 * i + 1];
+    }
+    return QS_OK;
+}
+
+qs_status qs_set_amps(qs_reg r, uint64_t start, uint64_t count, const qs_cplx* host_in)
+{
+    QS_CHECK_REG(r);
+    const uint64_t len = 1ull << r->nbits;
+    if (start > len || count > len - start) return qs::set_error(QS_E_ARG, "amplitude range outside the register");
+    if (count == 0) return QS_OK;
+    if (!host_in) return qs::set_error(QS_E_ARG, "NULL host buffer");
+    if (r->prec == QS_C128) {
+        QS_HIP(hipMemcpyAsync((char*)r->amp + 16 * start, host_in, 16 * count, hipMemcpyHostToDevice, r->stream));
+        return sync_stream(r);
+    }
+    std::vector<float> tmp(2 * count);
+    for (uint64_t i = 0; i < count; ++i) {
+        tmp[2 * i] = (float)host_in[i].re;
+        tmp[2 * i + 1] = (float)host_in[i].im;
+    }
+    QS_HIP(hipMemcpyAsync((char*)r->amp + 8 * start, tmp.data(), 8 * count, hipMemcpyHostToDevice, r->stream));
+    return sync_stream(r);
+}
+
+qs_status qs_multi_controlled_unitary(qs_reg r, const int* controls, int n_controls, int target,
+                                      const qs_cplx u[4])
+{
+    QS_CHECK_REG(r);
+    qs_status s = check_target(target, r->n);
+    if (!s) s = check_qubits(controls, n_controls, r->n, target, "controls");
+    if (!s) s = check_unitary(u);
+    if (s) return s;
+    double u8[8];
+    for (int k = 0; k < 4; ++k) {
+        u8[2 * k] = u[k].re;
+        u8[2 * k + 1] = u[k].im;
+    }
+    return r->prec == QS_C128 ? do_dense<double>(r, controls, n_controls, target, u8)
+                              : do_dense<float>(r, controls, n_controls, target, u8);
+}
+
+qs_status qs_unitary(qs_reg r, int target, const qs_cplx u[4])
+{
+    return qs_multi_controlled_unitary(r, nullptr, 0, target, u);
+}
+
+qs_status qs_controlled_unitary(qs_reg r, int control, int target, const qs_cplx u[4])
+{
+    return qs_multi_controlled_unitary(r, &control, 1, target, u);
+}
+
+qs_status qs_multi_controlled_not(qs_reg r, const int* controls, int n_controls, int target)
+{
+    QS_CHECK_REG(r);
+    qs_status s = check_target(target, r->n);
+    if (!s) s = check_qubits(controls, n_controls, r->n, target, "controls");
+    if (s) return s;
+    return r->prec == QS_C128 ? do_not<double>(r, controls, n_controls, target)
+                              : do_not<float>(r, controls, n_controls, target);
+}
+
+qs_status qs_multi_controlled_phase(qs_reg r, const int* qubits, int n_qubits, double angle)
+{
+    QS_CHECK_REG(r);
+    if (n_qubits < 1) return qs::set_error(QS_E_ARG, "phase needs at least one qubit");
+    qs_status s = check_qubits(qubits, n_qubits, r->n, -1, "qubits");
+    if (s) return s;
+    if (!isfinite(angle)) return qs::set_error(QS_E_ARG, "non-finite angle");
+    return r->prec == QS_C128 ? do_phase<double>(r, qubits, n_qubits, angle)
+                              : do_phase<float>(r, qubits, n_qubits, angle);
+}
+
+static qs_status mix(qs_reg r, int channel, int target, double p)
+{
+    QS_CHECK_REG(r);
+    qs_status s = check_channel(r, channel, target, p);
+    if (s) return s;
+    return r->prec == QS_C128 ? do_channel<double>(r, channel, target, p)
+                              : do_channel<float>(r, channel, target, p);
+}
+
+qs_status qs_mix_dephasing(qs_reg r, int target, double p) { return mix(r, QS_DEPHASING, target, p); }
+qs_status qs_mix_depolarising(qs_reg r, int target, double p) { return mix(r, QS_DEPOLARISING, target, p); }
+qs_status qs_mix_damping(qs_reg r, int target, double gamma) { return mix(r, QS_DAMPING, target, gamma); }
+
+qs_status qs_calc_total_prob(qs_reg r, double* out)
+{
+    QS_CHECK_REG(r);
+    if (!out) return qs::set_error(QS_E_ARG, "NULL output");
+    double v[2];
+    qs_status s = probs(r, -1, v);
+    if (s) return s;
+    *out = v[0] + v[1];
+    return QS_OK;
+}
+
+qs_status qs_calc_prob_of_outcome(qs_reg r, int qubit, int outcome, double* out)
+{
+    QS_CHECK_REG(r);
+    if (!out) return qs::set_error(QS_E_ARG, "NULL output");
+    qs_status s = check_target(qubit, r->n);
+    if (s) return s;
+    if (outcome != 0 && outcome != 1) return qs::set_error(QS_E_ARG, "outcome must be 0 or 1");
+    double v[2];
+    if ((s = probs(r, qubit, v))) return s;
+    *out = v[outcome];
+    return QS_OK;
+}
+
+qs_status qs_measure(qs_reg r, int qubit, double u01, int* outcome, double* prob)
+{
+    QS_CHECK_REG(r);
+    qs_status s = check_target(qubit, r->n);
+    if (s) return s;
+    if (!(u01 >= 0.0 && u01 < 1.0)) return qs::set_error(QS_E_ARG, "draw must lie in [0, 1)");
+    double v[2];
+    if ((s = probs(r, qubit, v))) return s;
+    double p0 = v[0];
+    if (p0 < 0.0) p0 = 0.0;
+    if (p0 > 1.0) p0 = 1.0;
+    const int o = (u01 < p0) ? 0 : 1;
+    const double p = v[o];
+    if (!(p > 0.0)) return qs::set_error(QS_E_ARG, "selected outcome has zero probability");
+    const qs::Launch L = launch_of(r);
+    if (r->kind == QS_DENSITY) {
+        const double scale = 1.0 / p;
+        s = qs::profiled(r, QS_K_COLLAPSE, [&](int*) {
+            return r->prec == QS_C128 ? qs::launch_collapse_dm<double>(L, r->amp, r->n, qubit, o, scale)
+                                      : qs::launch_collapse_dm<float>(L, r->amp, r->n, qubit, o, scale);
+        });
+    } else {
+        const double scale = 1.0 / sqrt(p);
+        s = qs::profiled(r, QS_K_COLLAPSE, [&](int*) {
+            return r->prec == QS_C128 ? qs::launch_collapse_sv<double>(L, r->amp, r->nbits, qubit, o, scale)
+                                      : qs::launch_collapse_sv<float>(L, r->amp, r->nbits, qubit, o, scale);
+        });
+    }
+    if (s) return s;
+    if (outcome) *outcome = o;
+    if (prob) *prob = p;
+    return QS_OK;
+}
+
+// --- circuits ----------------------------------------------------------------
+
+qs_status qs_circuit_create(qs_circuit* out)
+{
+    if (!out) return qs::set_error(QS_E_ARG, "NULL output");
+    qs_circuit c = new qs_circuit_s();
+    c->magic = kCircMagic;
+    handle_add(c);
+    *out = c;
+    return QS_OK;
+}
+
+qs_status qs_circuit_destroy(qs_circuit c)
+{
+    if (!valid_circ(c) || !handle_remove(c)) return qs::set_error(QS_E_HANDLE, "invalid circuit handle");
+    c->magic = 0;
+    delete c;
+    return QS_OK;
+}
+
+qs_status qs_circuit_size(qs_circuit c, int* n_ops)
+{
+    if (!valid_circ(c)) return qs::set_error(QS_E_HANDLE, "invalid circuit handle");
+    if (!n_ops) return qs::set_error(QS_E_ARG, "NULL output");
+    *n_ops = (int)c->ops.size();
+    return QS_OK;
+}
+
+// Qubit ranges are checked again against the register at run time.
+static qs_status circ_common(qs_circuit c, const int* qs_, int nq, int target, OpRec& op)
+{
+    if (!valid_circ(c)) return qs::set_error(QS_E_HANDLE, "invalid circuit handle");
+    qs_status s = check_qubits(qs_, nq, 64, target, "qubits");
+    if (s) return s;
+    op.ctrls.assign(qs_, qs_ + nq);
+    op.target = target;
+    return QS_OK;
+}
+
+qs_status qs_circuit_add_unitary(qs_circuit c, const int* controls, int n_controls, int target,
+                                 const qs_cplx u[4])
+{
+    OpRec op{};
+    qs_status s = circ_common(c, controls, n_controls, target, op);
+    if (!s && target < 0) s = qs::set_error(QS_E_ARG, "negative target");
+    if (!s) s = check_unitary(u);
+    if (s) return s;
+    op.kind = 0;
+    for (int k = 0; k < 4; ++k) {
+        op.u[2 * k] = u[k].re;
+        op.u[2 * k + 1] = u[k].im;
+    }
+    c->ops.push_back(op);
+    return QS_OK;
+}
+
+qs_status qs_circuit_add_not(qs_circuit c, const int* controls, int n_controls, int target)
+{
+    OpRec op{};
+    qs_status s = circ_common(c, controls, n_controls, target, op);
+    if (!s && target < 0) s = qs::set_error(QS_E_ARG, "negative target");
+    if (s) return s;
+    op.kind = 1;
+    c->ops.push_back(op);
+    return QS_OK;
+}
+
+qs_status qs_circuit_add_phase(qs_circuit c, const int* qubits, int n_qubits, double angle)
+{
+    OpRec op{};
+    if (n_qubits < 1) return qs::set_error(QS_E_ARG, "phase needs at least one qubit");
+    qs_status s = circ_common(c, qubits, n_qubits, -1, op);
+    if (!s && !isfinite(angle)) s = qs::set_error(QS_E_ARG, "non-finite angle");
+    if (s) return s;
+    op.kind = 2;
+    op.angle = angle;
+    c->ops.push_back(op);
+    return QS_OK;
+}
+
+qs_status qs_circuit_add_channel(qs_circuit c, int channel, int target, double p)
+{
+    if (!valid_circ(c)) return qs::set_error(QS_E_HANDLE, "invalid circuit handle");
+    double hi = channel == QS_DEPHASING ? 0.5 : channel == QS_DEPOLARISING ? 0.75 : 1.0;
+    if (channel < QS_DEPHASING || channel > QS_DAMPING) return qs::set_error(QS_E_ARG, "unknown channel");
+    if (target < 0) return qs::set_error(QS_E_ARG, "negative target");
+    if (!(p >= 0.0 && p <= hi)) return qs::set_error(QS_E_ARG, "channel strength out of range");
+    OpRec op{};
+    op.kind = 3;
+    op.channel = channel;
+    op.target = target;
+    op.p = p;
+    c->ops.push_back(op);
+    return QS_OK;
+}
+
+qs_status qs_circuit_run(qs_reg r, qs_circuit c, int fusion_qubits, int* n_passes)
+{
+    QS_CHECK_REG(r);
+    if (!valid_circ(c)) return qs::set_error(QS_E_HANDLE, "invalid circuit handle");
+    if (fusion_qubits < 0) return qs::set_error(QS_E_ARG, "negative fusion width");
+    // Validate every op against this register before launching anything.
+    for (const OpRec& op : c->ops) {
+        if (op.kind == 3) {
+            qs_status s = check_channel(r, op.channel, op.target, op.p);
+            if (s) return s;
+            continue;
+        }
+        if (op.kind != 2) {
+            qs_status s = check_target(op.target, r->n);
+            if (s) return s;
+        }
+        for (int q : op.ctrls)
+            if (q >= r->n) return qs::set_error(QS_E_ARG, "circuit qubit outside the register");
+    }
+    if (fusion_qubits > 0 && r->kind == QS_STATEVEC)
+        return qs::run_fused_sv(r, c->ops, fusion_qubits, n_passes);
+    for (const OpRec& op : c->ops) {
+        qs_status s = qs::apply_op(r, op);
+        if (s) return s;
+    }
+    if (n_passes) *n_passes = (int)c->ops.size();
+    return QS_OK;
+}
+
+}  // extern "C"

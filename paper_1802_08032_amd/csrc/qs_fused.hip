@@ -1,0 +1,601 @@
+// Gate fusion for state vectors: a run of gates whose targets lie in a set S
+// of K qubits is applied to every 2^K-amplitude tile (all amplitudes that
+// agree on the qubits outside S) in one read and one write of HBM -- the
+// GPU form of the cache blocking / gate fusion described in Sec. II.B.
+//
+// Tile layout.  A workgroup of 2^TB threads holds a tile of 2^K = 2^(TB+RB)
+// amplitudes in registers, 2^RB per thread.  At any moment each local qubit
+// of the tile is either a "thread bit" (selects the thread) or a "register
+// bit" (selects the register inside the thread).  A gate whose target is a
+// register bit is applied by every thread to its own registers; controls and
+// diagonal phases may sit anywhere, since a thread knows the value of its
+// thread bits and of the qubits outside S (fixed per tile).  When the next
+// gates target thread bits, the tile is re-laid out through LDS (one write
+// and one read of 2^K amplitudes) so that those qubits become register
+// bits.  Lanes 0..63 always cover global qubits 0..5 when the tile is read
+// from or written to HBM, so every global access is a contiguous 64-element
+// run per wavefront.
+//
+// LDS addresses are a linear map over GF(2) of the local index (an XOR
+// swizzle chosen per re-layout so that the 8 lanes of a 128-byte LDS cycle
+// hit distinct banks in both the writing and the reading layout).  Each
+// layout is handed to the kernel as the images of single thread / register
+// bits, so the kernel only XORs precomputed values.
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "qs_device.h"
+#include "qs_host.h"
+
+namespace qs {
+namespace {
+
+constexpr int kTBMax = 10;
+constexpr int kRBMax = 5;
+constexpr int kPhMax = 24;
+
+struct FPhase {
+    uint32_t wthr[kTBMax], wreg[kRBMax];  // LDS images of the layout being left
+    uint32_t rthr[kTBMax], rreg[kRBMax];  // LDS images of the layout entered
+    int op_begin, op_end;
+};
+
+struct FPass {
+    int nphases;
+    int final_transpose;  // 1: re-lay out to the store layout before storing
+    uint64_t ld_thr[kTBMax], ld_reg[kRBMax];  // HBM offsets of the load layout
+    uint64_t st_thr[kTBMax], st_reg[kRBMax];  // HBM offsets of the store layout
+    BitInsert outside;                        // inserts zeros at the tile's qubits
+    FPhase ph[kPhMax];
+    FPhase fin;
+};
+
+struct FOp {
+    int kind;        // 0 dense, 1 not, 2 phase
+    int rb;          // target register bit (dense / not)
+    uint32_t rmask;  // register bits that must be 1
+    uint32_t tmask;  // thread-index bits that must be 1
+    uint64_t gmask;  // global qubits outside the tile that must be 1
+    double m[8];     // dense matrix, or phase factor in m[0], m[1]
+};
+
+template <typename T, int RB, int RBIT>
+__device__ __forceinline__ void dense_rb(typename C2<T>::type (&v)[1 << RB], const FOp& op)
+{
+    using V = typename C2<T>::type;
+    T m[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) m[k] = (T)op.m[k];
+    const uint32_t rmask = op.rmask;
+#pragma unroll
+    for (int r0 = 0; r0 < (1 << RB); ++r0) {
+        if (r0 & (1 << RBIT)) continue;
+        if (((uint32_t)r0 & rmask) != rmask) continue;
+        apply2<T, V>(m, v[r0], v[r0 | (1 << RBIT)]);
+    }
+}
+
+template <typename T, int RB, int RBIT>
+__device__ __forceinline__ void not_rb(typename C2<T>::type (&v)[1 << RB], const FOp& op)
+{
+    using V = typename C2<T>::type;
+    const uint32_t rmask = op.rmask;
+#pragma unroll
+    for (int r0 = 0; r0 < (1 << RB); ++r0) {
+        if (r0 & (1 << RBIT)) continue;
+        if (((uint32_t)r0 & rmask) != rmask) continue;
+        const V t = v[r0];
+        v[r0] = v[r0 | (1 << RBIT)];
+        v[r0 | (1 << RBIT)] = t;
+    }
+}
+
+template <typename T, int RB>
+__device__ __forceinline__ void phase_op(typename C2<T>::type (&v)[1 << RB], const FOp& op)
+{
+    using V = typename C2<T>::type;
+    const T fr = (T)op.m[0], fi = (T)op.m[1];
+    const uint32_t rmask = op.rmask;
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) {
+        if (((uint32_t)r & rmask) != rmask) continue;
+        v[r] = cmul<T, V>(fr, fi, v[r]);
+    }
+}
+
+template <typename T, int RB>
+__device__ __forceinline__ void apply_op(typename C2<T>::type (&v)[1 << RB], const FOp& op)
+{
+    if (op.kind == 2) {
+        phase_op<T, RB>(v, op);
+        return;
+    }
+    if (op.kind == 0) {
+        switch (op.rb) {
+        case 0: dense_rb<T, RB, 0>(v, op); break;
+        case 1: if constexpr (RB > 1) dense_rb<T, RB, 1>(v, op); break;
+        case 2: if constexpr (RB > 2) dense_rb<T, RB, 2>(v, op); break;
+        case 3: if constexpr (RB > 3) dense_rb<T, RB, 3>(v, op); break;
+        case 4: if constexpr (RB > 4) dense_rb<T, RB, 4>(v, op); break;
+        }
+        return;
+    }
+    switch (op.rb) {
+    case 0: not_rb<T, RB, 0>(v, op); break;
+    case 1: if constexpr (RB > 1) not_rb<T, RB, 1>(v, op); break;
+    case 2: if constexpr (RB > 2) not_rb<T, RB, 2>(v, op); break;
+    case 3: if constexpr (RB > 3) not_rb<T, RB, 3>(v, op); break;
+    case 4: if constexpr (RB > 4) not_rb<T, RB, 4>(v, op); break;
+    }
+}
+
+// XOR of img[b] over the set bits b of x (x < 2^NB).
+template <int NB, typename U>
+__device__ __forceinline__ U span(uint32_t x, const U* img)
+{
+    U s = 0;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+        if ((x >> b) & 1) s ^= img[b];
+    return s;
+}
+
+template <int NB, typename U>
+__device__ __forceinline__ U span_sum(uint32_t x, const U* img)
+{
+    U s = 0;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+        if ((x >> b) & 1) s += img[b];
+    return s;
+}
+
+template <typename T, int TB, int RB>
+__device__ __forceinline__ void relayout(typename C2<T>::type (&v)[1 << RB],
+                                         typename C2<T>::type* lds, const FPhase& F, uint32_t tid)
+{
+    const uint32_t tw = span<TB, uint32_t>(tid, F.wthr);
+    const uint32_t tr = span<TB, uint32_t>(tid, F.rthr);
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) lds[tw ^ span<RB, uint32_t>((uint32_t)r, F.wreg)] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) v[r] = lds[tr ^ span<RB, uint32_t>((uint32_t)r, F.rreg)];
+    __syncthreads();
+}
+
+template <typename T, int TB, int RB>
+__global__ __launch_bounds__(1 << TB) void k_fused(typename C2<T>::type* __restrict__ amp,
+                                                   const FPass* __restrict__ P,
+                                                   const FOp* __restrict__ ops, uint64_t ntiles)
+{
+    using V = typename C2<T>::type;
+    constexpr int E = 1 << RB;
+    __shared__ V lds[1 << (TB + RB)];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t ld_t = span_sum<TB, uint64_t>(tid, P->ld_thr);
+    const uint64_t st_t = span_sum<TB, uint64_t>(tid, P->st_thr);
+    const int nph = P->nphases;
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t base = expand(tile, P->outside);
+        V v[E];
+#pragma unroll
+        for (int r = 0; r < E; ++r) v[r] = amp[base + ld_t + span_sum<RB, uint64_t>((uint32_t)r, P->ld_reg)];
+        for (int ph = 0; ph < nph; ++ph) {
+            const FPhase& F = P->ph[ph];
+            if (ph > 0) relayout<T, TB, RB>(v, lds, F, tid);
+            for (int o = F.op_begin; o < F.op_end; ++o) {
+                const FOp& op = ops[o];
+                const bool tok = ((tid & op.tmask) == op.tmask) && ((base & op.gmask) == op.gmask);
+                if (tok) apply_op<T, RB>(v, op);
+            }
+        }
+        if (P->final_transpose) relayout<T, TB, RB>(v, lds, P->fin, tid);
+#pragma unroll
+        for (int r = 0; r < E; ++r) amp[base + st_t + span_sum<RB, uint64_t>((uint32_t)r, P->st_reg)] = v[r];
+    }
+}
+
+// ===========================================================================
+// Host planner
+
+struct Layout {
+    std::vector<int> thr;  // local qubit of thread bit b (b = 0..TB-1)
+    std::vector<int> reg;  // local qubit of register bit b
+};
+
+struct PhasePlan {
+    Layout lay;
+    std::vector<int> ops;  // indices into the pass's op list
+};
+
+struct PassPlan {
+    std::vector<int> S;        // global qubits, ascending (local j <-> S[j])
+    std::vector<int> ops;      // indices into the circuit, in application order
+    std::vector<PhasePlan> phases;
+    Layout store;
+};
+
+uint64_t qubit_mask(const OpRec& op)
+{
+    uint64_t m = 0;
+    for (int q : op.ctrls) m |= 1ull << q;
+    if (op.kind != 2) m |= 1ull << op.target;
+    return m;
+}
+
+// Coalesced layouts have local qubits 0..5 (= global 0..5) on lanes 0..63.
+bool coalesced(const Layout& L)
+{
+    for (int b = 0; b < 6; ++b)
+        if (L.thr[b] != b) return false;
+    return true;
+}
+
+Layout make_layout(int TB, int RB, const std::vector<int>& regs)
+{
+    const int K = TB + RB;
+    Layout L;
+    L.reg = regs;
+    for (int j = 0; j < K; ++j)
+        if (std::find(regs.begin(), regs.end(), j) == regs.end()) L.thr.push_back(j);
+    (void)RB;
+    return L;
+}
+
+// Choose `RB` register qubits: first the given preferred targets (in order),
+// then fill from `fill` order; never local 0..5 when `coalesce` is set.
+std::vector<int> pick_regs(int TB, int RB, const std::vector<int>& pref, bool coalesce)
+{
+    const int K = TB + RB;
+    std::vector<int> regs;
+    auto ok = [&](int j) {
+        if (coalesce && j < 6) return false;
+        return std::find(regs.begin(), regs.end(), j) == regs.end();
+    };
+    for (int j : pref) {
+        if ((int)regs.size() == RB) break;
+        if (ok(j)) regs.push_back(j);
+    }
+    for (int j = K - 1; j >= 0 && (int)regs.size() < RB; --j)
+        if (ok(j)) regs.push_back(j);
+    return regs;
+}
+
+// Assign the pass's ops to register layouts in dependency order.  Returns
+// false if more than kPhMax phases would be needed; then `keep` receives how
+// many of the pass ops (a dependency-closed prefix set) fit.
+void plan_phases(PassPlan& P, const std::vector<OpRec>& all, int TB, int RB, int max_phases)
+{
+    const int K = TB + RB;
+    std::vector<int> local(64, -1);
+    for (int j = 0; j < K; ++j) local[P.S[j]] = j;
+    auto lmask = [&](const OpRec& op) {
+        uint32_t m = 0;
+        for (int q : op.ctrls)
+            if (local[q] >= 0) m |= 1u << local[q];
+        if (op.kind != 2) m |= 1u << local[op.target];
+        return m;
+    };
+    std::vector<int> rem = P.ops;
+    std::vector<int> kept;
+    // next preferred register targets from the remaining ops
+    auto preferred = [&](const std::vector<int>& ops_left) {
+        std::vector<int> pref;
+        uint32_t blocked = 0;
+        for (int idx : ops_left) {
+            const OpRec& op = all[idx];
+            const uint32_t m = lmask(op);
+            if (op.kind != 2 && !(m & blocked)) pref.push_back(local[op.target]);
+            blocked |= m;
+        }
+        for (int idx : ops_left)
+            if (all[idx].kind != 2) pref.push_back(local[all[idx].target]);
+        return pref;
+    };
+    bool first = true;
+    while (!rem.empty()) {
+        if ((int)P.phases.size() == max_phases) break;
+        PhasePlan ph;
+        ph.lay = make_layout(TB, RB, pick_regs(TB, RB, preferred(rem), first));
+        first = false;
+        uint32_t regm = 0;
+        for (int j : ph.lay.reg) regm |= 1u << j;
+        uint32_t blocked = 0;
+        std::vector<int> next;
+        for (int idx : rem) {
+            const OpRec& op = all[idx];
+            const uint32_t m = lmask(op);
+            const bool ready = !(m & blocked);
+            const bool fits = op.kind == 2 || ((regm >> local[op.target]) & 1);
+            if (ready && fits) {
+                ph.ops.push_back(idx);
+            } else {
+                blocked |= m;
+                next.push_back(idx);
+            }
+        }
+        for (int idx : ph.ops) kept.push_back(idx);
+        P.phases.push_back(ph);
+        rem.swap(next);
+    }
+    P.ops = kept;  // anything left goes back to the pool
+    // store layout: the last phase if it is coalesced, else the first one
+    P.store = coalesced(P.phases.back().lay) ? P.phases.back().lay : P.phases.front().lay;
+}
+
+// Greedy pass partition: walk the remaining ops in order; take an op when
+// no earlier untaken op shares a qubit with it and its target fits in S.
+std::vector<PassPlan> plan_passes(const std::vector<OpRec>& all, int n, int TB, int RB, int max_phases,
+                                  int max_ops)
+{
+    const int K = TB + RB;
+    std::vector<PassPlan> passes;
+    std::vector<char> done(all.size(), 0);
+    size_t ndone = 0, first = 0;
+    while (ndone < all.size()) {
+        while (done[first]) ++first;
+        uint64_t S = (1ull << 6) - 1;  // lanes: global qubits 0..5
+        int ssize = 6;
+        uint64_t blocked = 0;
+        std::vector<int> take;
+        for (size_t i = first; i < all.size() && (int)take.size() < max_ops; ++i) {
+            if (done[i]) continue;
+            const OpRec& op = all[i];
+            const uint64_t m = qubit_mask(op);
+            if (m & blocked) {
+                blocked |= m;
+                continue;
+            }
+            if (op.kind == 2) {
+                take.push_back((int)i);
+                continue;
+            }
+            const uint64_t tb = 1ull << op.target;
+            if (S & tb) {
+                take.push_back((int)i);
+            } else if (ssize < K) {
+                S |= tb;
+                ++ssize;
+                take.push_back((int)i);
+            } else {
+                blocked |= m;
+            }
+        }
+        // fill S up to K qubits with the lowest unused ones
+        for (int q = 0; q < n && ssize < K; ++q)
+            if (!((S >> q) & 1)) {
+                S |= 1ull << q;
+                ++ssize;
+            }
+        PassPlan P;
+        for (int q = 0; q < n; ++q)
+            if ((S >> q) & 1) P.S.push_back(q);
+        P.ops = take;
+        plan_phases(P, all, TB, RB, max_phases);
+        for (int idx : P.ops) {
+            done[idx] = 1;
+            ++ndone;
+        }
+        passes.push_back(std::move(P));
+    }
+    return passes;
+}
+
+// GF(2)-linear LDS address map for a re-layout from A to B.  Local bit j
+// maps to 1 << j, XORed in its low 3 bits with c_j (j >= 3), so the map is
+// invertible.  c_j is chosen so that thread bits 0..2 of both layouts span
+// the 8 low values (the 8 lanes sharing one 128-byte LDS cycle).
+std::vector<uint32_t> swizzle(const Layout& A, const Layout& B, int K)
+{
+    std::vector<uint32_t> c(K, 0);
+    auto low = [&](int j) -> uint32_t { return j < 3 ? (1u << j) : c[j]; };
+    auto independent = [&](const Layout& L) {
+        const uint32_t a = low(L.thr[0]), b = low(L.thr[1]), d = low(L.thr[2]);
+        const uint32_t vals[7] = {a, b, d, a ^ b, a ^ d, b ^ d, a ^ b ^ d};
+        for (uint32_t v : vals)
+            if (v == 0) return false;
+        return true;
+    };
+    // assign free bits greedily; try all 8 values for each unset bit used by A or B
+    std::vector<int> cand;
+    for (int b = 0; b < 3; ++b) {
+        if (A.thr[b] >= 3) cand.push_back(A.thr[b]);
+        if (B.thr[b] >= 3) cand.push_back(B.thr[b]);
+    }
+    std::sort(cand.begin(), cand.end());
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    // exhaustive search over at most 6 bits x 8 values is cheap
+    const int nc = (int)cand.size();
+    uint64_t total = 1;
+    for (int k = 0; k < nc; ++k) total *= 8;
+    for (uint64_t code = 0; code < total; ++code) {
+        uint64_t x = code;
+        for (int k = 0; k < nc; ++k) {
+            c[cand[k]] = (uint32_t)(x & 7);
+            x >>= 3;
+        }
+        if (independent(A) && independent(B)) break;
+    }
+    std::vector<uint32_t> img(K);
+    for (int j = 0; j < K; ++j) img[j] = (1u << j) ^ (j >= 3 ? c[j] : 0u);
+    return img;
+}
+
+void fill_phase(FPhase& F, const Layout& from, const Layout& to, int K)
+{
+    const std::vector<uint32_t> img = swizzle(from, to, K);
+    memset(F.wthr, 0, sizeof(F.wthr));
+    memset(F.wreg, 0, sizeof(F.wreg));
+    memset(F.rthr, 0, sizeof(F.rthr));
+    memset(F.rreg, 0, sizeof(F.rreg));
+    for (size_t b = 0; b < from.thr.size(); ++b) F.wthr[b] = img[from.thr[b]];
+    for (size_t b = 0; b < from.reg.size(); ++b) F.wreg[b] = img[from.reg[b]];
+    for (size_t b = 0; b < to.thr.size(); ++b) F.rthr[b] = img[to.thr[b]];
+    for (size_t b = 0; b < to.reg.size(); ++b) F.rreg[b] = img[to.reg[b]];
+}
+
+FOp encode_op(const OpRec& op, const PassPlan& P, const Layout& L)
+{
+    FOp f;
+    memset(&f, 0, sizeof(f));
+    std::vector<int> local(64, -1);
+    for (size_t j = 0; j < P.S.size(); ++j) local[P.S[j]] = (int)j;
+    auto classify = [&](int q) {
+        const int j = local[q];
+        if (j < 0) {
+            f.gmask |= 1ull << q;
+            return;
+        }
+        for (size_t b = 0; b < L.reg.size(); ++b)
+            if (L.reg[b] == j) {
+                f.rmask |= 1u << b;
+                return;
+            }
+        for (size_t b = 0; b < L.thr.size(); ++b)
+            if (L.thr[b] == j) {
+                f.tmask |= 1u << b;
+                return;
+            }
+    };
+    for (int q : op.ctrls) classify(q);
+    f.kind = op.kind;
+    if (op.kind == 2) {
+        f.m[0] = cos(op.angle);
+        f.m[1] = sin(op.angle);
+        return f;
+    }
+    const int jt = local[op.target];
+    for (size_t b = 0; b < L.reg.size(); ++b)
+        if (L.reg[b] == jt) f.rb = (int)b;
+    if (op.kind == 0)
+        for (int k = 0; k < 8; ++k) f.m[k] = op.u[k];
+    return f;
+}
+
+struct Config {
+    int TB, RB;
+};
+
+Config pick_config(int prec, int k, int n)
+{
+    // K = TB + RB <= min(k, n); LDS = 2^K * element bytes <= 128 KiB
+    int K = std::min(k, n);
+    const int kmax = prec == QS_C128 ? 13 : 14;
+    K = std::min(K, kmax);
+    if (K < 9) return Config{0, 0};
+    if (K == 14) return Config{9, 5};
+    if (K == 13) return Config{8, 5};
+    if (K == 12) return Config{8, 4};
+    if (K == 11) return Config{8, 3};
+    if (K == 10) return Config{7, 3};
+    return Config{6, 3};
+}
+
+template <typename T, int TB, int RB>
+hipError_t launch_cfg(hipStream_t s, void* amp, const FPass* P, const FOp* ops, uint64_t ntiles)
+{
+    using V = typename C2<T>::type;
+    uint64_t grid = ntiles;
+    const uint64_t cap = 256ull * 8;
+    if (grid > cap) grid = cap;
+    hipLaunchKernelGGL((k_fused<T, TB, RB>), dim3((unsigned)grid), dim3(1 << TB), 0, s, (V*)amp, P, ops, ntiles);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fused_pass(hipStream_t s, const Config& c, void* amp, const FPass* P, const FOp* ops,
+                             uint64_t ntiles)
+{
+    if constexpr (sizeof(T) == 4)
+        if (c.TB == 9 && c.RB == 5) return launch_cfg<T, 9, 5>(s, amp, P, ops, ntiles);
+    if (c.TB == 8 && c.RB == 5) return launch_cfg<T, 8, 5>(s, amp, P, ops, ntiles);
+    if (c.TB == 8 && c.RB == 4) return launch_cfg<T, 8, 4>(s, amp, P, ops, ntiles);
+    if (c.TB == 8 && c.RB == 3) return launch_cfg<T, 8, 3>(s, amp, P, ops, ntiles);
+    if (c.TB == 7 && c.RB == 3) return launch_cfg<T, 7, 3>(s, amp, P, ops, ntiles);
+    return launch_cfg<T, 6, 3>(s, amp, P, ops, ntiles);
+}
+
+}  // namespace
+
+qs_status run_fused_sv(qs_reg r, const std::vector<OpRec>& ops, int k, int* passes_out)
+{
+    const Config cfg = pick_config(r->prec, k, r->n);
+    if (cfg.TB == 0) {  // too small to tile: one kernel per op
+        for (const OpRec& op : ops) {
+            qs_status s = apply_op(r, op);
+            if (s) return s;
+        }
+        if (passes_out) *passes_out = (int)ops.size();
+        return QS_OK;
+    }
+    const int TB = cfg.TB, RB = cfg.RB, K = TB + RB;
+    std::vector<PassPlan> plan = plan_passes(ops, r->n, TB, RB, kPhMax, 1 << 12);
+
+    // serialise passes + ops
+    std::vector<FPass> hp(plan.size());
+    std::vector<FOp> hops;
+    for (size_t p = 0; p < plan.size(); ++p) {
+        const PassPlan& P = plan[p];
+        FPass& F = hp[p];
+        memset(&F, 0, sizeof(F));
+        F.nphases = (int)P.phases.size();
+        F.outside = make_insert(P.S.data(), (int)P.S.size(), 0);
+        const Layout& L0 = P.phases.front().lay;
+        for (int b = 0; b < TB; ++b) {
+            F.ld_thr[b] = 1ull << P.S[L0.thr[b]];
+            F.st_thr[b] = 1ull << P.S[P.store.thr[b]];
+        }
+        for (int b = 0; b < RB; ++b) {
+            F.ld_reg[b] = 1ull << P.S[L0.reg[b]];
+            F.st_reg[b] = 1ull << P.S[P.store.reg[b]];
+        }
+        for (size_t ph = 0; ph < P.phases.size(); ++ph) {
+            FPhase& Fp = F.ph[ph];
+            const Layout& prev = ph ? P.phases[ph - 1].lay : P.phases[ph].lay;
+            fill_phase(Fp, prev, P.phases[ph].lay, K);
+            Fp.op_begin = (int)hops.size();
+            for (int idx : P.phases[ph].ops) hops.push_back(encode_op(ops[idx], P, P.phases[ph].lay));
+            Fp.op_end = (int)hops.size();
+        }
+        const Layout& last = P.phases.back().lay;
+        F.final_transpose = (last.reg == P.store.reg && last.thr == P.store.thr) ? 0 : 1;
+        fill_phase(F.fin, last, P.store, K);
+        F.fin.op_begin = F.fin.op_end = 0;
+    }
+    if (hops.empty()) hops.push_back(FOp{});
+
+    const size_t pbytes = hp.size() * sizeof(FPass), obytes = hops.size() * sizeof(FOp);
+    std::vector<char> host(pbytes + obytes);
+    memcpy(host.data(), hp.data(), pbytes);
+    memcpy(host.data() + pbytes, hops.data(), obytes);
+    void* dbuf = nullptr;
+    hipError_t e = hipMalloc(&dbuf, pbytes + obytes);
+    if (e != hipSuccess) return hip_error(e, "plan buffer");
+    e = hipMemcpy(dbuf, host.data(), pbytes + obytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(dbuf);
+        return hip_error(e, "plan upload");
+    }
+    const FPass* dP = (const FPass*)dbuf;
+    const FOp* dO = (const FOp*)((char*)dbuf + pbytes);
+    const uint64_t ntiles = 1ull << (r->n - K);
+    qs_status st = QS_OK;
+    for (size_t p = 0; p < hp.size() && st == QS_OK; ++p) {
+        st = profiled(r, QS_K_FUSED, [&](int*) {
+            return r->prec == QS_C128 ? launch_fused_pass<double>(r->stream, cfg, r->amp, dP + p, dO, ntiles)
+                                      : launch_fused_pass<float>(r->stream, cfg, r->amp, dP + p, dO, ntiles);
+        });
+    }
+    // the plan buffer is released once the passes that read it have finished
+    e = hipStreamSynchronize(r->stream);
+    hipFree(dbuf);
+    if (st) return st;
+    if (e != hipSuccess) return hip_error(e, "fused passes");
+    if (passes_out) *passes_out = (int)hp.size();
+    return QS_OK;
+}
+
+}  // namespace qs

@@ -1,0 +1,92 @@
+// Host-side structures behind the opaque C-ABI handles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "qs_internal.h"
+#include "qstate.h"
+
+struct qs_env_s {
+    uint32_t magic;
+    int device;
+    bool profile;
+    struct Rec {
+        int klass;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    uint64_t launches[QS_K_COUNT];
+    double ms[QS_K_COUNT];
+    std::mutex mu;
+};
+
+struct qs_reg_s {
+    uint32_t magic;
+    qs_env env;
+    int n;         // qubits (N for a density matrix)
+    int nbits;     // index bits: n (state vector) or 2n (density matrix)
+    int kind;
+    int prec;
+    void* amp;
+    size_t bytes;
+    bool owned;
+    hipStream_t stream;
+    double* scratch;     // device: reduction partials + 2 results
+    double* host_res;    // pinned host: 2 doubles
+};
+
+// One recorded circuit operation.
+struct OpRec {
+    int kind;            // 0 dense, 1 not, 2 phase, 3 channel
+    int target;
+    int channel;
+    std::vector<int> ctrls;  // controls (dense/not) or all qubits (phase)
+    double u[8];
+    double angle;
+    double p;
+};
+
+struct qs_circuit_s {
+    uint32_t magic;
+    std::vector<OpRec> ops;
+};
+
+namespace qs {
+
+qs_status set_error(qs_status s, const std::string& msg);
+qs_status hip_error(hipError_t e, const char* what);
+
+// Launch `f` on the register's stream, bracketed by profiling events when
+// the environment profiles.  f(int* klass) returns hipError_t and may
+// overwrite the kernel class.
+template <class F>
+qs_status profiled(qs_reg r, int klass, F&& f)
+{
+    qs_env env = r->env;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (env->profile) {
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+            return hip_error(hipGetLastError(), "hipEventCreate");
+        (void)hipEventRecord(a, r->stream);
+    }
+    const hipError_t e = f(&klass);
+    if (env->profile) {
+        (void)hipEventRecord(b, r->stream);
+        std::lock_guard<std::mutex> g(env->mu);
+        env->recs.push_back({klass, a, b});
+    }
+    if (e != hipSuccess) return hip_error(e, "kernel launch");
+    return QS_OK;
+}
+
+// Fused execution of a state-vector circuit (qs_fused.hip).
+qs_status run_fused_sv(qs_reg r, const std::vector<OpRec>& ops, int k, int* passes);
+// Per-operation execution of one recorded op (qs_api.hip).
+qs_status apply_op(qs_reg r, const OpRec& op);
+
+}  // namespace qs

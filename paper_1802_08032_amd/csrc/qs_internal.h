@@ -1,0 +1,93 @@
+// Internal declarations shared by the C-ABI layer and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qstate.h"
+
+namespace qs {
+
+// Up to 64 bit positions to insert into a compact loop index, ascending.
+// After insertion the bits in `ones` are set (controls), the rest are 0.
+struct BitInsert {
+    int count;
+    int pos[63];
+    uint64_t ones;
+};
+
+// 2x2 complex matrix, row-major, real/imag interleaved.
+template <typename T>
+struct Mat2 {
+    T m[8];
+};
+
+// 4x4 complex matrix acting on the 4-group (rho00, rho10, rho01, rho11) of a
+// density matrix (row bit t, column bit t+N), row-major, interleaved.
+template <typename T>
+struct Mat4 {
+    T m[32];
+};
+
+struct Launch {
+    hipStream_t stream;
+    int device;
+};
+
+// Builds the insertion spec for the given positions (any order) and ones mask.
+BitInsert make_insert(const int* positions, int count, uint64_t ones);
+
+// --- state-vector kernels -------------------------------------------------
+template <typename T> hipError_t launch_init_basis(const Launch& L, void* amp, uint64_t len, uint64_t index);
+template <typename T> hipError_t launch_gate(const Launch& L, void* amp, int nbits, int t,
+                                             const int* ctrls, int nc, const Mat2<T>& u, int* klass);
+template <typename T> hipError_t launch_not(const Launch& L, void* amp, int nbits, int t,
+                                            const int* ctrls, int nc);
+// Multiply by f every amplitude with all bits of `mask` set, except those
+// that also have all bits of `skip` set (skip == 0: no exception).
+template <typename T> hipError_t launch_phase(const Launch& L, void* amp, int nbits, uint64_t mask,
+                                              uint64_t skip, double fre, double fim);
+
+// --- density-matrix kernels ------------------------------------------------
+template <typename T> hipError_t launch_dm_gate(const Launch& L, void* rho, int N, int t,
+                                                const int* ctrls, int nc, const Mat2<T>& u);
+template <typename T> hipError_t launch_dm_channel(const Launch& L, void* rho, int N, int t,
+                                                   int channel, double p);
+
+// --- reductions and collapse ----------------------------------------------
+// Sum of |alpha|^2 split by bit q (q < 0: one total sum in out[0]).  Writes
+// {sum over bit q == 0, sum over bit q == 1} as doubles to `dev_out`.
+// `partials` must hold 2 * 2 * kReduceBlocks doubles.
+constexpr int kReduceBlocks = 1024;
+template <typename T> hipError_t launch_prob_sv(const Launch& L, const void* amp, int nbits, int q,
+                                                double* partials, double* dev_out);
+template <typename T> hipError_t launch_prob_dm(const Launch& L, const void* rho, int N, int q,
+                                                double* partials, double* dev_out);
+template <typename T> hipError_t launch_collapse_sv(const Launch& L, void* amp, int nbits, int q,
+                                                    int outcome, double scale);
+template <typename T> hipError_t launch_collapse_dm(const Launch& L, void* rho, int N, int q,
+                                                    int outcome, double scale);
+
+// --- fused tile pass ---------------------------------------------------------
+// One op inside a fused pass, on local (tile) qubit indices.
+struct TileOp {
+    int kind;         // 0 dense, 1 not, 2 phase (diagonal on all-ones of mask)
+    int target;       // local target
+    uint32_t cmask;   // local control mask (dense/not) or phase mask
+    uint32_t pad;
+    double u[8];      // dense matrix (or phase re/im in u[0], u[1])
+};
+
+constexpr int kMaxTileQubits = 14;
+constexpr int kMaxTileOps = 256;
+
+struct TilePlan {
+    int k;                       // tile qubits
+    int qubits[kMaxTileQubits];  // global qubit of local bit j, ascending
+    int nops;
+};
+
+template <typename T> hipError_t launch_fused(const Launch& L, void* amp, int nbits, const TilePlan& plan,
+                                              const TileOp* dev_ops);
+
+}  // namespace qs

@@ -1,0 +1,622 @@
+// gfx950 kernels for one operation per pass: the amplitude-pair update of
+// Eq. 1 (Sec. II.B.1) for state vectors, the 4-element group update that
+// fuses the two passes of Eq. 2 for density matrices, the channel updates,
+// probability reductions and measurement collapse.
+//
+// Layout: interleaved complex (double2 / float2), qubit q = bit q of the
+// index.  Every kernel is a grid-stride loop over 64-bit indices with a
+// grid capped at 16 blocks per CU.
+#include <algorithm>
+
+#include "qs_device.h"
+
+namespace qs {
+
+BitInsert make_insert(const int* positions, int count, uint64_t ones)
+{
+    BitInsert b;
+    b.count = count;
+    int tmp[64];
+    for (int k = 0; k < count; ++k) tmp[k] = positions[k];
+    std::sort(tmp, tmp + count);
+    for (int k = 0; k < count; ++k) b.pos[k] = tmp[k];
+    b.ones = ones;
+    return b;
+}
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Initialisation: every amplitude 0 except `index`, which is 1.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_init_basis(typename C2<T>::type* __restrict__ amp,
+                                                       uint64_t len, uint64_t index)
+{
+    using V = typename C2<T>::type;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < len; i += stride) {
+        V v;
+        v.x = (i == index) ? T(1) : T(0);
+        v.y = T(0);
+        amp[i] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Eq. 1 pair update for targets whose pair partner lies in another wavefront
+// row (t >= 6): each lane owns a pair (a, a + 2^t); 64 consecutive lanes
+// touch two contiguous 1 KiB (c128) runs.  `ins` inserts a 0 at t and a 1
+// at every control.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gate_pair(typename C2<T>::type* __restrict__ amp,
+                                                      uint64_t npairs, uint64_t tb, BitInsert ins,
+                                                      Mat2<T> u)
+{
+    using V = typename C2<T>::type;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (; i + stride < npairs; i += 2 * stride) {
+        const uint64_t a0 = expand(i, ins);
+        const uint64_t a1 = expand(i + stride, ins);
+        V x0 = amp[a0], y0 = amp[a0 + tb];
+        V x1 = amp[a1], y1 = amp[a1 + tb];
+        apply2<T, V>(u.m, x0, y0);
+        apply2<T, V>(u.m, x1, y1);
+        amp[a0] = x0;
+        amp[a0 + tb] = y0;
+        amp[a1] = x1;
+        amp[a1 + tb] = y1;
+    }
+    if (i < npairs) {
+        const uint64_t a = expand(i, ins);
+        V x = amp[a], y = amp[a + tb];
+        apply2<T, V>(u.m, x, y);
+        amp[a] = x;
+        amp[a + tb] = y;
+    }
+}
+
+// Cross-lane exchange with lane ^ 2^TT inside a wavefront of 64 lanes:
+// DPP quad permutes for 1 and 2, ds_swizzle bit mode for 4, 8, 16 and a
+// backwards permute for 32.  All lanes must be active.
+template <int TT>
+__device__ __forceinline__ int lane_xor(int v, int lane)
+{
+    if constexpr (TT == 0) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+    else if constexpr (TT == 1) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    else if constexpr (TT == 2) return __builtin_amdgcn_ds_swizzle(v, 0x101F);
+    else if constexpr (TT == 3) return __builtin_amdgcn_ds_swizzle(v, 0x201F);
+    else if constexpr (TT == 4) return __builtin_amdgcn_ds_swizzle(v, 0x401F);
+    else return __builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, v);
+}
+
+template <int TT>
+__device__ __forceinline__ double xchg(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = lane_xor<TT>((int)(b & 0xffffffffll), lane);
+    const int hi = lane_xor<TT>((int)(b >> 32), lane);
+    return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+template <int TT>
+__device__ __forceinline__ float xchg(float v, int lane)
+{
+    return __int_as_float(lane_xor<TT>(__float_as_int(v), lane));
+}
+
+// Eq. 1 for targets t < 6: each lane loads ONE amplitude of a contiguous
+// 64-amplitude chunk, fetches its pair partner from lane ^ 2^t in registers
+// and writes its own new value, so loads and stores stay fully contiguous.
+// Controls at bits >= 6 are folded into the chunk index (`hi`); controls at
+// bits < 6 become a lane mask.
+template <typename T, int TT>
+__global__ __launch_bounds__(kBlock) void k_gate_low(typename C2<T>::type* __restrict__ amp,
+                                                     uint64_t nchunks, BitInsert hi,
+                                                     uint32_t lowmask, Mat2<T> u)
+{
+    using V = typename C2<T>::type;
+    const int lane = threadIdx.x & 63;
+    const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const uint64_t nw = ((uint64_t)gridDim.x * kBlock) >> 6;
+    const bool up = (lane >> TT) & 1;
+    const bool ok = ((uint32_t)lane & lowmask) == lowmask;
+    // new = s * self + p * partner
+    const T sr = up ? u.m[6] : u.m[0], si = up ? u.m[7] : u.m[1];
+    const T pr = up ? u.m[4] : u.m[2], pi = up ? u.m[5] : u.m[3];
+    constexpr int U = 4;
+    uint64_t c = wave;
+    for (; c + (U - 1) * nw < nchunks; c += U * nw) {
+        V v[U];
+        uint64_t e[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            e[j] = (expand(c + j * nw, hi) << 6) | (uint64_t)lane;
+            v[j] = amp[e[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            V p;
+            p.x = xchg<TT>(v[j].x, lane);
+            p.y = xchg<TT>(v[j].y, lane);
+            const V r = cmac2<T, V>(sr, si, v[j], pr, pi, p);
+            if (ok) amp[e[j]] = r;
+        }
+    }
+    for (; c < nchunks; c += nw) {
+        const uint64_t e = (expand(c, hi) << 6) | (uint64_t)lane;
+        const V v = amp[e];
+        V p;
+        p.x = xchg<TT>(v.x, lane);
+        p.y = xchg<TT>(v.y, lane);
+        const V r = cmac2<T, V>(sr, si, v, pr, pi, p);
+        if (ok) amp[e] = r;
+    }
+}
+
+// Multi-controlled NOT: swap each pair whose controls are set.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_not(typename C2<T>::type* __restrict__ amp,
+                                                uint64_t npairs, uint64_t tb, BitInsert ins)
+{
+    using V = typename C2<T>::type;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < npairs; i += stride) {
+        const uint64_t a = expand(i, ins);
+        const V x = amp[a], y = amp[a + tb];
+        amp[a] = y;
+        amp[a + tb] = x;
+    }
+}
+
+// Diagonal phase on the amplitudes whose `ins.ones` bits are all set,
+// except those that also have every bit of `skip` set (skip != 0).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_phase(typename C2<T>::type* __restrict__ amp,
+                                                  uint64_t count, BitInsert ins, uint64_t skip,
+                                                  T fr, T fi)
+{
+    using V = typename C2<T>::type;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) {
+        const uint64_t e = expand(i, ins);
+        if (skip != 0 && (e & skip) == skip) continue;
+        amp[e] = cmul<T, V>(fr, fi, amp[e]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Density matrix, Eq. 2 fused into one pass.  A group is the four entries
+// (rho[r][c]) with row bit t = r and column bit t+N = c; the gate is
+// rho -> (R ? U : I) rho (C ? U^dagger : I), R / C = row / column controls
+// all set.  Columns multiplied by U^dagger is conj(U) on the column qubit.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dm_gate(typename C2<T>::type* __restrict__ rho,
+                                                    uint64_t ngroups, uint64_t tb, uint64_t cb,
+                                                    BitInsert ins, uint64_t rmask, uint64_t cmask,
+                                                    Mat2<T> u)
+{
+    using V = typename C2<T>::type;
+    T uc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) uc[k] = (k & 1) ? -u.m[k] : u.m[k];
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x; g < ngroups; g += stride) {
+        const uint64_t b = expand(g, ins);
+        const bool R = (b & rmask) == rmask;
+        const bool Cc = (b & cmask) == cmask;
+        if (!R && !Cc) continue;
+        V m00 = rho[b], m10 = rho[b + tb], m01 = rho[b + cb], m11 = rho[b + tb + cb];
+        if (R) {  // U on the row index, for each column
+            apply2<T, V>(u.m, m00, m10);
+            apply2<T, V>(u.m, m01, m11);
+        }
+        if (Cc) {  // conj(U) on the column index, for each row
+            apply2<T, V>(uc, m00, m01);
+            apply2<T, V>(uc, m10, m11);
+        }
+        rho[b] = m00;
+        rho[b + tb] = m10;
+        rho[b + cb] = m01;
+        rho[b + tb + cb] = m11;
+    }
+}
+
+// Channel closed forms on each 4-group (arithmetic in double).
+//   dephasing p:     off-diagonals * (1 - 2p)
+//   depolarising p:  r00 <- (1-2p/3) r00 + (2p/3) r11, r11 symmetric,
+//                    off-diagonals * (1 - 4p/3)
+//   damping g:       r00 <- r00 + g r11, r11 <- (1-g) r11,
+//                    off-diagonals * sqrt(1-g)
+// a, b: diagonal mixing (r00' = a r00 + b r11 ... per channel), f: off-diagonal factor.
+template <typename T, int CH>
+__global__ __launch_bounds__(kBlock) void k_dm_channel(typename C2<T>::type* __restrict__ rho,
+                                                       uint64_t ngroups, uint64_t tb, uint64_t cb,
+                                                       BitInsert ins, double p0, double p1, double f)
+{
+    using V = typename C2<T>::type;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x; g < ngroups; g += stride) {
+        const uint64_t b = expand(g, ins);
+        V m10 = rho[b + tb], m01 = rho[b + cb];
+        m10.x = (T)(f * (double)m10.x);
+        m10.y = (T)(f * (double)m10.y);
+        m01.x = (T)(f * (double)m01.x);
+        m01.y = (T)(f * (double)m01.y);
+        rho[b + tb] = m10;
+        rho[b + cb] = m01;
+        if constexpr (CH != QS_DEPHASING) {
+            V m00 = rho[b], m11 = rho[b + tb + cb];
+            const double a0 = m00.x, a1 = m00.y, d0 = m11.x, d1 = m11.y;
+            V n00, n11;
+            if constexpr (CH == QS_DEPOLARISING) {  // p0 = 1 - 2p/3, p1 = 2p/3
+                n00.x = (T)(p0 * a0 + p1 * d0);
+                n00.y = (T)(p0 * a1 + p1 * d1);
+                n11.x = (T)(p0 * d0 + p1 * a0);
+                n11.y = (T)(p0 * d1 + p1 * a1);
+            } else {  // damping: p0 = gamma, p1 = 1 - gamma
+                n00.x = (T)(a0 + p0 * d0);
+                n00.y = (T)(a1 + p0 * d1);
+                n11.x = (T)(p1 * d0);
+                n11.y = (T)(p1 * d1);
+            }
+            rho[b] = n00;
+            rho[b + tb + cb] = n11;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reductions: per-thread Neumaier sums in double, merged across the wave
+// with cross-lane shuffles and across the block through LDS; one partial
+// per block, folded by k_reduce_final.
+__device__ __forceinline__ NSum wave_merge(NSum a)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        NSum o;
+        o.s = __shfl_xor(a.s, off, 64);
+        o.c = __shfl_xor(a.c, off, 64);
+        a = nmerge(a, o);
+    }
+    return a;
+}
+
+__device__ __forceinline__ void block_store2(NSum s0, NSum s1, double* partials)
+{
+    __shared__ double sh[4][kBlock / 64];
+    s0 = wave_merge(s0);
+    s1 = wave_merge(s1);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][w] = s0.s;
+        sh[1][w] = s0.c;
+        sh[2][w] = s1.s;
+        sh[3][w] = s1.c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        NSum a = {sh[0][0], sh[1][0]}, b = {sh[2][0], sh[3][0]};
+        for (int k = 1; k < kBlock / 64; ++k) {
+            a = nmerge(a, NSum{sh[0][k], sh[1][k]});
+            b = nmerge(b, NSum{sh[2][k], sh[3][k]});
+        }
+        partials[4 * blockIdx.x + 0] = a.s;
+        partials[4 * blockIdx.x + 1] = a.c;
+        partials[4 * blockIdx.x + 2] = b.s;
+        partials[4 * blockIdx.x + 3] = b.c;
+    }
+}
+
+// Sum |alpha_i|^2 split by bit q of i (q < 0: everything in the first sum).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prob_sv(const typename C2<T>::type* __restrict__ amp,
+                                                    uint64_t len, int q, double* partials)
+{
+    using V = typename C2<T>::type;
+    NSum s0 = {0.0, 0.0}, s1 = {0.0, 0.0};
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < len; i += stride) {
+        const V a = amp[i];
+        const double p = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+        const bool one = (q >= 0) && ((i >> q) & 1);
+        nadd(s0, one ? 0.0 : p);
+        nadd(s1, one ? p : 0.0);
+    }
+    block_store2(s0, s1, partials);
+}
+
+// Sum Re rho[j][j] split by bit q of j (the diagonal is entry j (2^N + 1)).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prob_dm(const typename C2<T>::type* __restrict__ rho,
+                                                    uint64_t dim, int q, double* partials)
+{
+    NSum s0 = {0.0, 0.0}, s1 = {0.0, 0.0};
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < dim; j += stride) {
+        const double p = (double)rho[j * (dim + 1)].x;
+        const bool one = (q >= 0) && ((j >> q) & 1);
+        nadd(s0, one ? 0.0 : p);
+        nadd(s1, one ? p : 0.0);
+    }
+    block_store2(s0, s1, partials);
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_final(const double* __restrict__ partials,
+                                                         int nblocks, double* out)
+{
+    NSum s0 = {0.0, 0.0}, s1 = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+        s0 = nmerge(s0, NSum{partials[4 * b + 0], partials[4 * b + 1]});
+        s1 = nmerge(s1, NSum{partials[4 * b + 2], partials[4 * b + 3]});
+    }
+    __shared__ double tmp[4 * 4];
+    s0 = wave_merge(s0);
+    s1 = wave_merge(s1);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        tmp[4 * w + 0] = s0.s;
+        tmp[4 * w + 1] = s0.c;
+        tmp[4 * w + 2] = s1.s;
+        tmp[4 * w + 3] = s1.c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        NSum a = {tmp[0], tmp[1]}, b = {tmp[2], tmp[3]};
+        for (int k = 1; k < kBlock / 64; ++k) {
+            a = nmerge(a, NSum{tmp[4 * k + 0], tmp[4 * k + 1]});
+            b = nmerge(b, NSum{tmp[4 * k + 2], tmp[4 * k + 3]});
+        }
+        out[0] = a.s + a.c;
+        out[1] = b.s + b.c;
+    }
+}
+
+// Collapse: keep amplitudes with bit q == outcome (scaled in double), zero
+// the rest without reading them.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_collapse_sv(typename C2<T>::type* __restrict__ amp,
+                                                        uint64_t len, int q, int outcome, double scale)
+{
+    using V = typename C2<T>::type;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < len; i += stride) {
+        const bool keep = (int)((i >> q) & 1) == outcome;
+        V v;
+        v.x = T(0);
+        v.y = T(0);
+        if (keep) {
+            const V a = amp[i];
+            v.x = (T)(scale * (double)a.x);
+            v.y = (T)(scale * (double)a.y);
+        }
+        amp[i] = v;
+    }
+}
+
+// Density-matrix collapse: keep rho[j][k] when bit q of j and of k both
+// equal the outcome (bits q and q+N of the vector index), scaled by 1/p.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_collapse_dm(typename C2<T>::type* __restrict__ rho,
+                                                        uint64_t len, int q, int N, int outcome,
+                                                        double scale)
+{
+    using V = typename C2<T>::type;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < len; i += stride) {
+        const bool keep = (int)((i >> q) & 1) == outcome && (int)((i >> (q + N)) & 1) == outcome;
+        V v;
+        v.x = T(0);
+        v.y = T(0);
+        if (keep) {
+            const V a = rho[i];
+            v.x = (T)(scale * (double)a.x);
+            v.y = (T)(scale * (double)a.y);
+        }
+        rho[i] = v;
+    }
+}
+
+}  // namespace
+
+// ===========================================================================
+// Launchers
+
+template <typename T>
+hipError_t launch_init_basis(const Launch& L, void* amp, uint64_t len, uint64_t index)
+{
+    using V = typename C2<T>::type;
+    hipLaunchKernelGGL(k_init_basis<T>, dim3(grid_for(len, 4)), dim3(kBlock), 0, L.stream,
+                       (V*)amp, len, index);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gate(const Launch& L, void* amp, int nbits, int t, const int* ctrls, int nc,
+                       const Mat2<T>& u, int* klass)
+{
+    using V = typename C2<T>::type;
+    if (t < 6 && nbits >= 6) {
+        // chunk index = amplitude index >> 6; controls >= 6 are inserted as ones
+        int hp[64];
+        int nh = 0;
+        uint64_t ones = 0;
+        uint32_t lowmask = 0;
+        for (int k = 0; k < nc; ++k) {
+            if (ctrls[k] >= 6) {
+                hp[nh++] = ctrls[k] - 6;
+                ones |= 1ull << (ctrls[k] - 6);
+            } else {
+                lowmask |= 1u << ctrls[k];
+            }
+        }
+        const BitInsert hi = make_insert(hp, nh, ones);
+        const uint64_t nchunks = 1ull << (nbits - 6 - nh);
+        // one wave per chunk, 4 chunks per wave per iteration
+        const int grid = grid_for(nchunks * 64, 4);
+        switch (t) {
+#define QS_LOW(TT) case TT: hipLaunchKernelGGL((k_gate_low<T, TT>), dim3(grid), dim3(kBlock), 0, L.stream, \
+                                         (V*)amp, nchunks, hi, lowmask, u); break;
+            QS_LOW(0) QS_LOW(1) QS_LOW(2) QS_LOW(3) QS_LOW(4) QS_LOW(5)
+#undef QS_LOW
+        }
+        if (klass) *klass = QS_K_GATE_LOW;
+        return hipGetLastError();
+    }
+    int pos[64];
+    uint64_t ones = 0;
+    for (int k = 0; k < nc; ++k) {
+        pos[k] = ctrls[k];
+        ones |= 1ull << ctrls[k];
+    }
+    pos[nc] = t;
+    const BitInsert ins = make_insert(pos, nc + 1, ones);
+    const uint64_t npairs = 1ull << (nbits - 1 - nc);
+    hipLaunchKernelGGL(k_gate_pair<T>, dim3(grid_for(npairs, 2)), dim3(kBlock), 0, L.stream,
+                       (V*)amp, npairs, 1ull << t, ins, u);
+    if (klass) *klass = QS_K_GATE;
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_not(const Launch& L, void* amp, int nbits, int t, const int* ctrls, int nc)
+{
+    using V = typename C2<T>::type;
+    int pos[64];
+    uint64_t ones = 0;
+    for (int k = 0; k < nc; ++k) {
+        pos[k] = ctrls[k];
+        ones |= 1ull << ctrls[k];
+    }
+    pos[nc] = t;
+    const BitInsert ins = make_insert(pos, nc + 1, ones);
+    const uint64_t npairs = 1ull << (nbits - 1 - nc);
+    hipLaunchKernelGGL(k_not<T>, dim3(grid_for(npairs, 2)), dim3(kBlock), 0, L.stream,
+                       (V*)amp, npairs, 1ull << t, ins);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_phase(const Launch& L, void* amp, int nbits, uint64_t mask, uint64_t skip,
+                        double fre, double fim)
+{
+    using V = typename C2<T>::type;
+    int pos[64];
+    int np = 0;
+    for (int q = 0; q < nbits; ++q)
+        if ((mask >> q) & 1) pos[np++] = q;
+    const BitInsert ins = make_insert(pos, np, mask);
+    const uint64_t count = 1ull << (nbits - np);
+    hipLaunchKernelGGL(k_phase<T>, dim3(grid_for(count, 2)), dim3(kBlock), 0, L.stream,
+                       (V*)amp, count, ins, skip, (T)fre, (T)fim);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dm_gate(const Launch& L, void* rho, int N, int t, const int* ctrls, int nc,
+                          const Mat2<T>& u)
+{
+    using V = typename C2<T>::type;
+    const int pos[2] = {t, t + N};
+    const BitInsert ins = make_insert(pos, 2, 0);
+    uint64_t rmask = 0;
+    for (int k = 0; k < nc; ++k) rmask |= 1ull << ctrls[k];
+    const uint64_t ngroups = 1ull << (2 * N - 2);
+    hipLaunchKernelGGL(k_dm_gate<T>, dim3(grid_for(ngroups, 2)), dim3(kBlock), 0, L.stream,
+                       (V*)rho, ngroups, 1ull << t, 1ull << (t + N), ins, rmask, rmask << N, u);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dm_channel(const Launch& L, void* rho, int N, int t, int channel, double p)
+{
+    using V = typename C2<T>::type;
+    const int pos[2] = {t, t + N};
+    const BitInsert ins = make_insert(pos, 2, 0);
+    const uint64_t ngroups = 1ull << (2 * N - 2);
+    const dim3 grid(grid_for(ngroups, 2)), block(kBlock);
+    const uint64_t tb = 1ull << t, cb = 1ull << (t + N);
+    switch (channel) {
+    case QS_DEPHASING:
+        hipLaunchKernelGGL((k_dm_channel<T, QS_DEPHASING>), grid, block, 0, L.stream, (V*)rho,
+                           ngroups, tb, cb, ins, 0.0, 0.0, 1.0 - 2.0 * p);
+        break;
+    case QS_DEPOLARISING:
+        hipLaunchKernelGGL((k_dm_channel<T, QS_DEPOLARISING>), grid, block, 0, L.stream, (V*)rho,
+                           ngroups, tb, cb, ins, 1.0 - 2.0 * p / 3.0, 2.0 * p / 3.0,
+                           1.0 - 4.0 * p / 3.0);
+        break;
+    default:
+        hipLaunchKernelGGL((k_dm_channel<T, QS_DAMPING>), grid, block, 0, L.stream, (V*)rho,
+                           ngroups, tb, cb, ins, p, 1.0 - p, sqrt(1.0 - p));
+        break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prob_sv(const Launch& L, const void* amp, int nbits, int q, double* partials,
+                          double* dev_out)
+{
+    using V = typename C2<T>::type;
+    const uint64_t len = 1ull << nbits;
+    int grid = grid_for(len, 8);
+    if (grid > kReduceBlocks) grid = kReduceBlocks;
+    hipLaunchKernelGGL(k_prob_sv<T>, dim3(grid), dim3(kBlock), 0, L.stream, (const V*)amp, len, q,
+                       partials);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, L.stream, partials, grid, dev_out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prob_dm(const Launch& L, const void* rho, int N, int q, double* partials,
+                          double* dev_out)
+{
+    using V = typename C2<T>::type;
+    const uint64_t dim = 1ull << N;
+    int grid = grid_for(dim, 1);
+    if (grid > kReduceBlocks) grid = kReduceBlocks;
+    hipLaunchKernelGGL(k_prob_dm<T>, dim3(grid), dim3(kBlock), 0, L.stream, (const V*)rho, dim, q,
+                       partials);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, L.stream, partials, grid, dev_out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_collapse_sv(const Launch& L, void* amp, int nbits, int q, int outcome, double scale)
+{
+    using V = typename C2<T>::type;
+    const uint64_t len = 1ull << nbits;
+    hipLaunchKernelGGL(k_collapse_sv<T>, dim3(grid_for(len, 4)), dim3(kBlock), 0, L.stream, (V*)amp,
+                       len, q, outcome, scale);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_collapse_dm(const Launch& L, void* rho, int N, int q, int outcome, double scale)
+{
+    using V = typename C2<T>::type;
+    const uint64_t len = 1ull << (2 * N);
+    hipLaunchKernelGGL(k_collapse_dm<T>, dim3(grid_for(len, 4)), dim3(kBlock), 0, L.stream, (V*)rho,
+                       len, q, N, outcome, scale);
+    return hipGetLastError();
+}
+
+#define QS_INSTANTIATE(T)                                                                              \
+    template hipError_t launch_init_basis<T>(const Launch&, void*, uint64_t, uint64_t);                \
+    template hipError_t launch_gate<T>(const Launch&, void*, int, int, const int*, int, const Mat2<T>&, \
+                                       int*);                                                          \
+    template hipError_t launch_not<T>(const Launch&, void*, int, int, const int*, int);                \
+    template hipError_t launch_phase<T>(const Launch&, void*, int, uint64_t, uint64_t, double, double); \
+    template hipError_t launch_dm_gate<T>(const Launch&, void*, int, int, const int*, int,             \
+                                          const Mat2<T>&);                                             \
+    template hipError_t launch_dm_channel<T>(const Launch&, void*, int, int, int, double);             \
+    template hipError_t launch_prob_sv<T>(const Launch&, const void*, int, int, double*, double*);     \
+    template hipError_t launch_prob_dm<T>(const Launch&, const void*, int, int, double*, double*);     \
+    template hipError_t launch_collapse_sv<T>(const Launch&, void*, int, int, int, double);            \
+    template hipError_t launch_collapse_dm<T>(const Launch&, void*, int, int, int, double);
+
+QS_INSTANTIATE(double)
+QS_INSTANTIATE(float)
+
+}  // namespace qs

@@ -1,0 +1,311 @@
+"""Thin Python binding over the qstate C ABI (include/qstate.h).
+
+Argument marshalling only: every operation runs in the HIP kernels of
+libqstate.so.  PyTorch provides device memory (registers wrap a torch
+tensor) and the HIP stream (the current torch stream); it is imported
+before the library so that both share one HIP runtime.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, 'libqstate.so')
+
+STATEVEC, DENSITY = 0, 1
+C64, C128 = 1, 2
+DEPHASING, DEPOLARISING, DAMPING = 0, 1, 2
+K_INIT, K_GATE, K_GATE_LOW, K_NOT, K_PHASE, K_DM_GATE, K_DM_CHANNEL, K_REDUCE, K_COLLAPSE, K_FUSED = range(10)
+KERNEL_CLASSES = ['init', 'gate', 'gate_low', 'not', 'phase', 'dm_gate', 'dm_channel', 'reduce',
+                  'collapse', 'fused']
+
+_STATUS = {0: 'QS_OK', -1: 'QS_E_ARG', -2: 'QS_E_KIND', -3: 'QS_E_OOM', -4: 'QS_E_DEVICE',
+           -5: 'QS_E_HANDLE', -6: 'QS_E_NOT_UNITARY'}
+
+
+class QStateError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f'{_STATUS.get(status, status)}: {message}')
+        self.status = status
+        self.name = _STATUS.get(status, str(status))
+
+
+class Cplx(C.Structure):
+    _fields_ = [('re', C.c_double), ('im', C.c_double)]
+
+
+_lib = None
+
+# name -> (restype, argtypes); every qs_status function returns c_int
+_vp, _i, _d, _u64, _sz = C.c_void_p, C.c_int, C.c_double, C.c_uint64, C.c_size_t
+_PI, _PD, _PU64 = C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_uint64)
+SIGNATURES = {
+    'qs_env_create': (_i, [_i, C.POINTER(_vp)]),
+    'qs_env_destroy': (_i, [_vp]),
+    'qs_env_sync': (_i, [_vp]),
+    'qs_last_error': (C.c_char_p, []),
+    'qs_profile_enable': (_i, [_vp, _i]),
+    'qs_profile_read': (_i, [_vp, _i, _PU64, _PD]),
+    'qs_profile_reset': (_i, [_vp]),
+    'qs_reg_bytes': (_sz, [_i, _i, _i]),
+    'qs_reg_create': (_i, [_vp, _i, _i, _i, _vp, C.POINTER(_vp)]),
+    'qs_reg_wrap': (_i, [_vp, _i, _i, _i, _vp, _sz, _vp, C.POINTER(_vp)]),
+    'qs_reg_destroy': (_i, [_vp]),
+    'qs_reg_info': (_i, [_vp, _PI, _PI, _PI, C.POINTER(_vp), C.POINTER(_vp)]),
+    'qs_init_zero': (_i, [_vp]),
+    'qs_init_basis': (_i, [_vp, _u64]),
+    'qs_get_amps': (_i, [_vp, _u64, _u64, _vp]),
+    'qs_set_amps': (_i, [_vp, _u64, _u64, _vp]),
+    'qs_unitary': (_i, [_vp, _i, _vp]),
+    'qs_controlled_unitary': (_i, [_vp, _i, _i, _vp]),
+    'qs_multi_controlled_unitary': (_i, [_vp, _vp, _i, _i, _vp]),
+    'qs_multi_controlled_not': (_i, [_vp, _vp, _i, _i]),
+    'qs_multi_controlled_phase': (_i, [_vp, _vp, _i, _d]),
+    'qs_mix_dephasing': (_i, [_vp, _i, _d]),
+    'qs_mix_depolarising': (_i, [_vp, _i, _d]),
+    'qs_mix_damping': (_i, [_vp, _i, _d]),
+    'qs_calc_total_prob': (_i, [_vp, _PD]),
+    'qs_calc_prob_of_outcome': (_i, [_vp, _i, _i, _PD]),
+    'qs_measure': (_i, [_vp, _i, _d, _PI, _PD]),
+    'qs_circuit_create': (_i, [C.POINTER(_vp)]),
+    'qs_circuit_destroy': (_i, [_vp]),
+    'qs_circuit_add_unitary': (_i, [_vp, _vp, _i, _i, _vp]),
+    'qs_circuit_add_not': (_i, [_vp, _vp, _i, _i]),
+    'qs_circuit_add_phase': (_i, [_vp, _vp, _i, _d]),
+    'qs_circuit_add_channel': (_i, [_vp, _i, _i, _d]),
+    'qs_circuit_size': (_i, [_vp, _PI]),
+    'qs_circuit_run': (_i, [_vp, _vp, _i, _PI]),
+}
+
+
+def lib():
+    """Load libqstate.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f'{LIB_PATH} is missing: build it with '
+                              f'`python -m paper_1802_08032_amd.build`')
+        L = C.CDLL(LIB_PATH, mode=C.RTLD_GLOBAL)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise QStateError(status, lib().qs_last_error().decode())
+
+
+def _ints(xs):
+    xs = [int(x) for x in xs]
+    arr = (C.c_int * max(1, len(xs)))(*xs)
+    return arr, len(xs)
+
+
+def _mat(u):
+    m = np.asarray(u, dtype=np.complex128).reshape(4)
+    return (Cplx * 4)(*[Cplx(float(z.real), float(z.imag)) for z in m])
+
+
+def reg_bytes(n: int, kind: int = STATEVEC, prec: int = C128) -> int:
+    return lib().qs_reg_bytes(n, kind, prec)
+
+
+class Env:
+    """A device (createQuESTEnv)."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        _check(lib().qs_env_create(device, C.byref(h)))
+        self.h = h
+        self.device = device
+
+    def sync(self):
+        _check(lib().qs_env_sync(self.h))
+
+    def profile(self, enable: bool = True):
+        _check(lib().qs_profile_enable(self.h, int(enable)))
+
+    def profile_read(self, klass: int):
+        n, ms = C.c_uint64(), C.c_double()
+        _check(lib().qs_profile_read(self.h, klass, C.byref(n), C.byref(ms)))
+        return n.value, ms.value
+
+    def profile_reset(self):
+        _check(lib().qs_profile_reset(self.h))
+
+    def close(self):
+        if self.h:
+            _check(lib().qs_env_destroy(self.h))
+            self.h = None
+
+
+class Register:
+    """A register of n qubits (state vector or density matrix).
+
+    By default the amplitudes live in a torch tensor on this device (wrapped
+    through qs_reg_wrap) and work is issued on the current torch stream;
+    ``owned=True`` lets the library allocate instead."""
+
+    def __init__(self, env: Env, n: int, kind: int = STATEVEC, prec: int = C128,
+                 owned: bool = False, stream=None):
+        self.env, self.n, self.kind, self.prec = env, n, kind, prec
+        nbits = 2 * n if kind == DENSITY else n
+        self.nbits = nbits
+        if stream is None:
+            stream = torch.cuda.current_stream(env.device)
+        self.stream = stream
+        sptr = C.c_void_p(stream.cuda_stream)
+        h = C.c_void_p()
+        self.tensor = None
+        if owned:
+            _check(lib().qs_reg_create(env.h, n, kind, prec, sptr, C.byref(h)))
+        else:
+            nbytes = reg_bytes(n, kind, prec)
+            if nbytes == 0:
+                raise QStateError(-1, 'invalid qubit count, kind or precision')
+            dt = torch.complex128 if prec == C128 else torch.complex64
+            self.tensor = torch.empty(1 << nbits, dtype=dt, device=f'cuda:{env.device}')
+            _check(lib().qs_reg_wrap(env.h, n, kind, prec, C.c_void_p(self.tensor.data_ptr()),
+                                     nbytes, sptr, C.byref(h)))
+        self.h = h
+
+    # -- lifecycle --------------------------------------------------------
+    def close(self):
+        if self.h:
+            _check(lib().qs_reg_destroy(self.h))
+            self.h = None
+            self.tensor = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- state --------------------------------------------------------------
+    def init_zero(self):
+        _check(lib().qs_init_zero(self.h))
+
+    def init_basis(self, index: int):
+        _check(lib().qs_init_basis(self.h, index))
+
+    def get_amps(self, start: int = 0, count: int | None = None) -> np.ndarray:
+        if count is None:
+            count = (1 << self.nbits) - start
+        out = np.empty(count, dtype=np.complex128)
+        _check(lib().qs_get_amps(self.h, start, count, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def set_amps(self, amps, start: int = 0):
+        a = np.ascontiguousarray(np.asarray(amps, dtype=np.complex128))
+        _check(lib().qs_set_amps(self.h, start, a.size, a.ctypes.data_as(C.c_void_p)))
+
+    # -- gates --------------------------------------------------------------
+    def unitary(self, target: int, u):
+        _check(lib().qs_unitary(self.h, target, _mat(u)))
+
+    def controlled_unitary(self, control: int, target: int, u):
+        _check(lib().qs_controlled_unitary(self.h, control, target, _mat(u)))
+
+    def multi_controlled_unitary(self, controls, target: int, u):
+        arr, k = _ints(controls)
+        _check(lib().qs_multi_controlled_unitary(self.h, arr, k, target, _mat(u)))
+
+    def multi_controlled_not(self, controls, target: int):
+        arr, k = _ints(controls)
+        _check(lib().qs_multi_controlled_not(self.h, arr, k, target))
+
+    def multi_controlled_phase(self, qubits, angle: float):
+        arr, k = _ints(qubits)
+        _check(lib().qs_multi_controlled_phase(self.h, arr, k, float(angle)))
+
+    def mix_dephasing(self, target: int, p: float):
+        _check(lib().qs_mix_dephasing(self.h, target, float(p)))
+
+    def mix_depolarising(self, target: int, p: float):
+        _check(lib().qs_mix_depolarising(self.h, target, float(p)))
+
+    def mix_damping(self, target: int, gamma: float):
+        _check(lib().qs_mix_damping(self.h, target, float(gamma)))
+
+    def apply(self, op):
+        """Apply one workloads.Op."""
+        if op.kind == 'u':
+            self.multi_controlled_unitary(op.controls, op.target, op.u)
+        elif op.kind == 'x':
+            self.multi_controlled_not(op.controls, op.target)
+        elif op.kind == 'phase':
+            self.multi_controlled_phase(op.qubits, op.angle)
+        elif op.kind == 'dephasing':
+            self.mix_dephasing(op.target, op.p)
+        elif op.kind == 'depolarising':
+            self.mix_depolarising(op.target, op.p)
+        elif op.kind == 'damping':
+            self.mix_damping(op.target, op.p)
+        else:
+            raise ValueError(op.kind)
+
+    # -- probabilities --------------------------------------------------------
+    def calc_total_prob(self) -> float:
+        v = C.c_double()
+        _check(lib().qs_calc_total_prob(self.h, C.byref(v)))
+        return v.value
+
+    def calc_prob_of_outcome(self, qubit: int, outcome: int) -> float:
+        v = C.c_double()
+        _check(lib().qs_calc_prob_of_outcome(self.h, qubit, outcome, C.byref(v)))
+        return v.value
+
+    def measure(self, qubit: int, u01: float):
+        o, p = C.c_int(), C.c_double()
+        _check(lib().qs_measure(self.h, qubit, float(u01), C.byref(o), C.byref(p)))
+        return o.value, p.value
+
+
+class Circuit:
+    """A recorded operation list, run with or without gate fusion."""
+
+    def __init__(self, ops=None):
+        h = C.c_void_p()
+        _check(lib().qs_circuit_create(C.byref(h)))
+        self.h = h
+        for op in ops or []:
+            self.add(op)
+
+    def add(self, op):
+        L = lib()
+        if op.kind == 'u':
+            arr, k = _ints(op.controls)
+            _check(L.qs_circuit_add_unitary(self.h, arr, k, op.target, _mat(op.u)))
+        elif op.kind == 'x':
+            arr, k = _ints(op.controls)
+            _check(L.qs_circuit_add_not(self.h, arr, k, op.target))
+        elif op.kind == 'phase':
+            arr, k = _ints(op.qubits)
+            _check(L.qs_circuit_add_phase(self.h, arr, k, float(op.angle)))
+        else:
+            ch = {'dephasing': DEPHASING, 'depolarising': DEPOLARISING, 'damping': DAMPING}[op.kind]
+            _check(L.qs_circuit_add_channel(self.h, ch, op.target, float(op.p)))
+
+    def __len__(self):
+        n = C.c_int()
+        _check(lib().qs_circuit_size(self.h, C.byref(n)))
+        return n.value
+
+    def run(self, reg: Register, fusion_qubits: int = 0) -> int:
+        passes = C.c_int()
+        _check(lib().qs_circuit_run(reg.h, self.h, fusion_qubits, C.byref(passes)))
+        return passes.value
+
+    def close(self):
+        if self.h:
+            _check(lib().qs_circuit_destroy(self.h))
+            self.h = None

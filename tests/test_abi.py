@@ -1,0 +1,55 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol that
+include/qstate.h declares, and its byte accounting follows the paper's
+16 x 2^n B per double-precision state vector (Sec. II.B.1).  No kernels run."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, 'include', 'qstate.h')
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r'/\*.*?\*/', '', text, flags=re.S)
+    return sorted(set(re.findall(r'\b(qs_[a-z0-9_]+)\s*\(', text)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1802_08032_amd as q
+    L = q.lib()
+    names = declared_functions()
+    assert len(names) >= 30
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    # the binding declares a signature for every exported call
+    from paper_1802_08032_amd.qstate import SIGNATURES
+    assert sorted(SIGNATURES) == names
+
+
+def test_reg_bytes_formula():
+    import paper_1802_08032_amd as q
+    for n in (1, 5, 16, 32, 40):
+        assert q.reg_bytes(n, q.STATEVEC, q.C128) == 16 << n
+        assert q.reg_bytes(n, q.STATEVEC, q.C64) == 8 << n
+    for n in (1, 8, 14, 20):
+        assert q.reg_bytes(n, q.DENSITY, q.C128) == 16 << (2 * n)
+    for bad in ((0, 0, 2), (41, 0, 2), (21, 1, 2), (5, 2, 2), (5, 0, 3), (-1, 0, 1)):
+        assert q.reg_bytes(*bad) == 0
+
+
+def test_paper_memory_figures():
+    import paper_1802_08032_amd as q
+    rows = [l.split() for l in open(os.path.join(ROOT, 'tests', 'golden', 'paper_memory.txt'))
+            if l.strip() and not l.startswith('#')]
+    assert len(rows) == 8
+    for r in rows:
+        n, rel, limit, copies = int(r[0]), r[1], int(r[2]), int(r[3])
+        need = copies * q.reg_bytes(n, q.STATEVEC, q.C128)
+        if rel == 'fits':
+            assert need <= limit, r
+        elif rel == 'exceeds':
+            assert need > limit, r
+        else:
+            assert need == limit, r

@@ -1,0 +1,127 @@
+"""Density-matrix parity: Eq. 2 gates, channels, probabilities and
+measurement through the C ABI against the oracle, plus the 14-qubit
+(28-bit vector) workload checked by invariants and against the oracle's
+state vector for the noise-free circuit."""
+import numpy as np
+import pytest
+
+import oracle as O
+from tests.gpu_util import fidelity_deficit, log, max_abs, run_gpu
+from workloads import (Op, haar_unitary, layered_circuit, measurement_draws, noisy_circuit,
+                       random_gate_ops)
+
+pytestmark = pytest.mark.gpu
+TOL128 = 1e-12
+
+
+@pytest.fixture(scope='module')
+def q():
+    import paper_1802_08032_amd as q
+    return q
+
+
+@pytest.fixture(scope='module')
+def env(q):
+    e = q.Env(0)
+    yield e
+    e.close()
+
+
+def rand_rho_vec(N, seed):
+    rng = np.random.default_rng(seed)
+    dim = 1 << N
+    A = rng.standard_normal((dim, 3)) + 1j * rng.standard_normal((dim, 3))
+    rho = A @ A.conj().T
+    rho /= np.trace(rho).real
+    return np.ascontiguousarray(rho.T).reshape(-1)
+
+
+@pytest.mark.parametrize('N', [1, 2, 4, 7])
+def test_dm_gates_match_oracle(q, env, N):
+    ops = random_gate_ops(N, 60, seed=N, max_controls=min(3, N - 1))
+    vec = rand_rho_vec(N, N)
+    ref = vec.copy()
+    for op in ops:
+        O.apply_dm(ref, N, op)
+    log(f'dm gates N={N}')
+    got = run_gpu(q, env, N, ops, kind=q.DENSITY, state=vec)
+    assert max_abs(got, ref) <= TOL128
+
+
+@pytest.mark.parametrize('N', [1, 3, 6])
+def test_channels_every_target(q, env, N):
+    vec = rand_rho_vec(N, 10 + N)
+    ops = []
+    for t in range(N):
+        ops += [Op('dephasing', target=t, p=0.17), Op('depolarising', target=t, p=0.31),
+                Op('damping', target=t, p=0.43)]
+    ops += [Op('dephasing', target=0, p=0.5), Op('depolarising', target=N - 1, p=0.75),
+            Op('damping', target=N - 1, p=1.0)]
+    ref = vec.copy()
+    for op in ops:
+        O.apply_dm(ref, N, op)
+    log(f'channels N={N}')
+    assert max_abs(run_gpu(q, env, N, ops, kind=q.DENSITY, state=vec), ref) <= TOL128
+
+
+def test_noisy_circuit_n10_depth10(q, env):
+    N = 10
+    ops = noisy_circuit(N, 10, 2)
+    ref = O.run_dm(N, ops)
+    got, reg = run_gpu(q, env, N, ops, kind=q.DENSITY, keep=True)
+    assert max_abs(got, ref) <= TOL128
+    assert abs(reg.calc_total_prob() - 1.0) <= TOL128
+    for qb in range(N):
+        assert abs(reg.calc_prob_of_outcome(qb, 0) - O.dm_prob_outcome(ref, N, qb, 0)) <= TOL128
+    draws = measurement_draws(2, 0, N)
+    for qb in range(N):
+        o, p = reg.measure(qb, draws[qb])
+        o_ref, p_ref = O.dm_measure(ref, N, qb, draws[qb])
+        assert o == o_ref and abs(p - p_ref) <= TOL128
+    assert max_abs(reg.get_amps(), ref) <= TOL128
+    reg.close()
+
+
+def test_dm_complex64(q, env):
+    N = 8
+    ops = noisy_circuit(N, 4, 3, p_depol=0.01, p_deph=0.02, gamma=0.03)
+    ref = O.run_dm(N, ops)
+    got = run_gpu(q, env, N, ops, kind=q.DENSITY, prec=q.C64)
+    assert max_abs(got, ref) <= 1e-5
+    assert abs(np.sum(np.diag(O.dm_matrix(got, N))).real - 1.0) <= 1e-5
+
+
+def test_full_size_dm_14_qubits(q, env):
+    """The 14-qubit density matrix (2^28 entries, 4 GiB): noise-free run is
+    |psi><psi| of the oracle's state vector, entry by entry; the noisy run
+    keeps trace 1, Hermiticity and consistent outcome probabilities."""
+    N = 14
+    dim = 1 << N
+    gates = layered_circuit(N, 10, 2)
+    psi = O.run_sv(N, gates)
+    log('dm14 noise-free')
+    reg = q.Register(env, N, q.DENSITY)
+    reg.init_zero()
+    for op in gates:
+        reg.apply(op)
+    err = 0.0
+    for blk in range(0, dim, 1024):  # columns k in [blk, blk + 1024)
+        got = reg.get_amps(blk * dim, 1024 * dim).reshape(1024, dim)   # [k][j]
+        ref = np.outer(psi.conj()[blk:blk + 1024], psi)                 # rho[j][k] at [k][j]
+        err = max(err, float(np.max(np.abs(got - ref))))
+    assert err <= TOL128
+    log('dm14 noisy')
+    reg.init_zero()
+    for op in noisy_circuit(N, 10, 2):
+        reg.apply(op)
+    assert abs(reg.calc_total_prob() - 1.0) <= 1e-12
+    for qb in range(N):
+        p0, p1 = reg.calc_prob_of_outcome(qb, 0), reg.calc_prob_of_outcome(qb, 1)
+        assert abs(p0 + p1 - 1.0) <= 1e-12 and p0 >= 0 and p1 >= 0
+    rng = np.random.default_rng(0)
+    for _ in range(64):
+        j, k = (int(v) for v in rng.integers(0, dim, 2))
+        a = reg.get_amps(j + dim * k, 1)[0]
+        b = reg.get_amps(k + dim * j, 1)[0]
+        assert abs(a - np.conj(b)) <= 1e-15
+    reg.close()

@@ -1,0 +1,105 @@
+"""Full-size state vectors in the bench's launch configuration: 32 qubits
+complex128 (64 GiB) and 33 qubits complex64 (64 GiB), fused at the widest
+tile.  Outputs the oracle can produce one by one are sampled: a product
+state (one Haar gate on every target) followed by CNOTs, phases and a few
+controlled dense gates; and a random circuit followed by its inverse must
+return to |0..0>."""
+import gc
+
+import numpy as np
+import pytest
+
+import oracle as O
+from tests.gpu_util import log
+from workloads import Op, haar_unitary, inverse, layered_circuit, product_layer
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope='module')
+def q():
+    import paper_1802_08032_amd as q
+    return q
+
+
+@pytest.fixture(scope='module')
+def env(q):
+    e = q.Env(0)
+    yield e
+    e.close()
+
+
+def release():
+    import torch
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def tail_ops(n, seed):
+    rng = np.random.default_rng(seed)
+    ops = [Op('x', target=q + 1, controls=(q,)) for q in range(0, n - 1, 2)]
+    ops.append(Op('phase', qubits=(1, 9, 20, n - 1), angle=1.234))
+    # a few dense gates on low, middle and top targets, some controlled
+    for t, ctrls in ((0, ()), (3, (n - 2,)), (7, ()), (n - 1, (2, 5)), (17, ()), (31 % n, (0,))):
+        ops.append(Op('u', target=t, controls=ctrls, u=haar_unitary(rng)))
+    ops.append(Op('x', target=4, controls=(n - 1, 12)))
+    return ops
+
+
+def sample_indices(n, count, seed):
+    rng = np.random.default_rng(seed)
+    idx = list(rng.integers(0, 1 << n, count, dtype=np.uint64))
+    idx += [0, (1 << n) - 1, 1 << (n - 1), (1 << 6) - 1]
+    return [int(i) for i in idx]
+
+
+@pytest.mark.parametrize('n,prec_name,fusion,tol', [(32, 'C128', 13, 1e-12), (33, 'C64', 14, None)])
+def test_product_state_and_tail_sampled(q, env, n, prec_name, fusion, tol):
+    prec = getattr(q, prec_name)
+    prod = product_layer(n, 40 + n)
+    tail = tail_ops(n, n)
+    vecs = np.array([op.u[:, 0] for op in prod])
+    idx = sample_indices(n, 2048, n)
+    ref = O.amps_after(n, vecs, tail, idx)
+    for mode in (fusion, None):
+        log(f'large n={n} {prec_name} fusion={mode}')
+        reg = q.Register(env, n, q.STATEVEC, prec)
+        reg.init_zero()
+        c = q.Circuit(prod + tail)
+        c.run(reg, mode or 0)
+        c.close()
+        got = np.array([reg.get_amps(i, 1)[0] for i in idx])
+        scale = 2.0 ** (-n / 2)
+        if tol is not None:
+            assert np.max(np.abs(got - ref)) <= tol
+        else:  # complex64: relative error of the sampled amplitudes
+            assert np.sqrt(np.sum(np.abs(got - ref) ** 2) / np.sum(np.abs(ref) ** 2)) <= 1e-5
+        p = reg.calc_total_prob()
+        assert abs(p - 1.0) <= (1e-12 if tol else 1e-5)
+        reg.close()
+        del reg
+        release()
+        assert scale > 0
+
+
+def test_circuit_then_inverse_returns_to_zero_32q(q, env):
+    n = 32
+    ops = layered_circuit(n, 2, 9, mcphase=True)
+    ops = ops + inverse(ops)
+    log('large inverse n=32 fusion=13')
+    reg = q.Register(env, n)
+    reg.init_zero()
+    c = q.Circuit(ops)
+    passes = c.run(reg, 13)
+    c.close()
+    assert passes < len(ops)
+    a0 = reg.get_amps(0, 1)[0]
+    assert abs(a0 - 1.0) <= 1e-12
+    rest = reg.get_amps(1, 4095)
+    assert np.max(np.abs(rest)) <= 1e-12
+    assert abs(reg.calc_total_prob() - 1.0) <= 1e-12
+    assert abs(reg.calc_prob_of_outcome(n - 1, 0) - 1.0) <= 1e-12
+    reg.close()
+    del reg
+    release()

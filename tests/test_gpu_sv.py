@@ -1,0 +1,223 @@
+"""State-vector parity: the HIP path through the C ABI against the oracle,
+element by element.  Tolerance: 1e-12 max absolute amplitude error in
+complex128; 1e-5 fidelity deficit in complex64; measurement outcomes exact."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from tests.gpu_util import fidelity_deficit, log, max_abs, run_gpu
+from workloads import (H, Op, haar_unitary, layered_circuit, measurement_draws, param_circuit,
+                       random_gate_ops, random_state)
+
+pytestmark = pytest.mark.gpu
+TOL128 = 1e-12
+TOL64_FID = 1e-5
+
+
+@pytest.fixture(scope='module')
+def q():
+    import paper_1802_08032_amd as q
+    return q
+
+
+@pytest.fixture(scope='module')
+def env(q):
+    e = q.Env(0)
+    yield e
+    e.close()
+
+
+def oracle_run(n, ops, state=None, init=0):
+    if state is None:
+        return O.run_sv(n, ops, init_index=init)
+    a = state.copy()
+    for op in ops:
+        O.apply_sv(a, n, op)
+    return a
+
+
+@pytest.mark.parametrize('seed', [0, 1, 2, 3, 4])
+def test_c0_random_circuit_per_gate_and_fused(q, env, seed):
+    """16 qubits, depth 20, Haar layers + CNOT bricks: amplitudes and total
+    probability, unfused and fused."""
+    n, depth = 16, 20
+    ops = layered_circuit(n, depth, seed)
+    ref = O.run_sv(n, ops)
+    for fusion in (None, 13, 11, 9):
+        log(f'c0 seed={seed} fusion={fusion}')
+        got, reg = run_gpu(q, env, n, ops, fusion=fusion, keep=True)
+        assert max_abs(got, ref) <= TOL128, fusion
+        assert abs(reg.calc_total_prob() - O.sv_total_prob(ref, n)) <= TOL128
+        reg.close()
+
+
+@pytest.mark.parametrize('n', [6, 9, 13])
+def test_every_op_every_target(q, env, n):
+    """Each gate kind on each target, with random controls, from a random
+    state; compared after every op (several tiles and the low-target path)."""
+    rng = np.random.default_rng(n)
+    state = random_state(n, 100 + n)
+    reg = q.Register(env, n)
+    reg.set_amps(state)
+    ref = state.copy()
+    for t in range(n):
+        for kind in ('u', 'x', 'phase'):
+            k = int(rng.integers(0, min(3, n - 1) + 1))
+            others = [int(v) for v in rng.choice([j for j in range(n) if j != t], size=k, replace=False)]
+            if kind == 'u':
+                op = Op('u', target=t, controls=tuple(others), u=haar_unitary(rng))
+            elif kind == 'x':
+                op = Op('x', target=t, controls=tuple(others))
+            else:
+                op = Op('phase', qubits=tuple(others + [t]), angle=float(rng.uniform(0, 6.28)))
+            log(f'n={n} t={t} {kind} ctrls={others}')
+            reg.apply(op)
+            O.apply_sv(ref, n, op)
+            assert max_abs(reg.get_amps(), ref) <= TOL128, (t, kind, others)
+    reg.close()
+
+
+@pytest.mark.parametrize('n', [1, 2, 3, 4, 5])
+def test_small_registers(q, env, n):
+    ops = random_gate_ops(n, 40, seed=n, max_controls=n - 1)
+    state = random_state(n, n)
+    log(f'small n={n}')
+    assert max_abs(run_gpu(q, env, n, ops, state=state), oracle_run(n, ops, state)) <= TOL128
+    assert max_abs(run_gpu(q, env, n, ops, state=state, fusion=13), oracle_run(n, ops, state)) <= TOL128
+
+
+@pytest.mark.parametrize('fusion', [9, 10, 11, 12, 13])
+@pytest.mark.parametrize('n,seed', [(14, 1), (17, 2)])
+def test_fused_random_gates(q, env, n, seed, fusion):
+    """Mixed dense / NOT / phase gates with up to 4 controls anywhere (inside
+    and outside the tile), fused at every tile width."""
+    ops = random_gate_ops(n, 300, seed=seed, max_controls=4)
+    state = random_state(n, seed)
+    log(f'fused n={n} seed={seed} k={fusion}')
+    assert max_abs(run_gpu(q, env, n, ops, state=state, fusion=fusion), oracle_run(n, ops, state)) <= TOL128
+
+
+def test_fused_layered_with_mcphase_and_param(q, env):
+    n = 18
+    for ops in (layered_circuit(n, 6, 5, mcphase=True), param_circuit(n, 4, 6)):
+        ref = O.run_sv(n, ops)
+        for fusion in (None, 13, 10):
+            log(f'layered/param n={n} fusion={fusion}')
+            assert max_abs(run_gpu(q, env, n, ops, fusion=fusion), ref) <= TOL128
+
+
+def test_ragged_and_empty_circuits(q, env):
+    n = 12
+    state = random_state(n, 7)
+    # empty circuit leaves the state untouched
+    got = run_gpu(q, env, n, [], state=state, fusion=13)
+    assert max_abs(got, state) == 0.0
+    # a single phase (no dense target) and a single gate on the top qubit
+    for ops in ([Op('phase', qubits=(3,), angle=0.3)], [Op('u', target=n - 1, u=H)]):
+        assert max_abs(run_gpu(q, env, n, ops, state=state, fusion=12), oracle_run(n, ops, state)) <= TOL128
+
+
+def test_probabilities_and_measurement_bit_exact(q, env):
+    n = 12
+    ops = layered_circuit(n, 5, 8, mcphase=True)
+    ref = O.run_sv(n, ops)
+    got, reg = run_gpu(q, env, n, ops, keep=True)
+    for qb in range(n):
+        for o in (0, 1):
+            assert abs(reg.calc_prob_of_outcome(qb, o) - O.sv_prob_outcome(ref, n, qb, o)) <= TOL128
+    draws = measurement_draws(11, 0, n)
+    for qb in range(n):
+        o_gpu, p_gpu = reg.measure(qb, draws[qb])
+        o_ref, p_ref = O.sv_measure(ref, n, qb, draws[qb])
+        assert o_gpu == o_ref, qb
+        assert abs(p_gpu - p_ref) <= TOL128
+    assert max_abs(reg.get_amps(), ref) <= TOL128
+    assert abs(reg.calc_total_prob() - 1.0) <= TOL128
+    reg.close()
+
+
+def test_measure_deterministic_edges(q, env):
+    reg = q.Register(env, 4)
+    reg.init_basis(0b0101)
+    assert reg.measure(0, 0.999999999) == (1, 1.0)
+    assert reg.measure(1, 0.999999999)[0] == 0
+    reg.close()
+
+
+@pytest.mark.parametrize('fusion', [None, 14])
+def test_complex64_fidelity(q, env, fusion):
+    n = 16
+    ops = layered_circuit(n, 20, 3, mcphase=True)
+    ref = O.run_sv(n, ops)
+    got, reg = run_gpu(q, env, n, ops, prec=q.C64, fusion=fusion, keep=True)
+    assert fidelity_deficit(ref, got) <= TOL64_FID
+    # reductions accumulate in double
+    assert abs(reg.calc_total_prob() - float(np.sum(np.abs(got) ** 2))) <= 1e-12
+    draws = measurement_draws(5, 1, 4)
+    for qb in range(4):
+        p0_ref = O.sv_prob_outcome(ref, n, qb, 0)
+        o, _ = reg.measure(qb, draws[qb])
+        if abs(draws[qb] - p0_ref) > 1e-4:  # outside the complex64 near-tie band
+            assert o == O.sv_measure(ref, n, qb, draws[qb])[0]
+    reg.close()
+
+
+def test_error_codes_leave_state_unchanged(q, env):
+    n = 5
+    state = random_state(n, 1)
+    reg = q.Register(env, n)
+    reg.set_amps(state)
+    bad_u = np.array([[1, 1], [0, 1]], dtype=np.complex128)
+    cases = [
+        (lambda: reg.unitary(n, H), 'QS_E_ARG'),
+        (lambda: reg.unitary(-1, H), 'QS_E_ARG'),
+        (lambda: reg.multi_controlled_unitary([1, 1], 0, H), 'QS_E_ARG'),
+        (lambda: reg.multi_controlled_unitary([0], 0, H), 'QS_E_ARG'),
+        (lambda: reg.multi_controlled_not([7], 0), 'QS_E_ARG'),
+        (lambda: reg.unitary(0, bad_u), 'QS_E_NOT_UNITARY'),
+        (lambda: reg.mix_dephasing(0, 0.1), 'QS_E_KIND'),
+        (lambda: reg.multi_controlled_phase([], 0.1), 'QS_E_ARG'),
+        (lambda: reg.calc_prob_of_outcome(0, 2), 'QS_E_ARG'),
+        (lambda: reg.measure(0, 1.0), 'QS_E_ARG'),
+        (lambda: reg.init_basis(1 << n), 'QS_E_ARG'),
+        (lambda: reg.get_amps(30, 3), 'QS_E_ARG'),
+    ]
+    for fn, name in cases:
+        with pytest.raises(q.QStateError) as ei:
+            fn()
+        assert ei.value.name == name
+    c = q.Circuit([Op('u', target=n + 2, u=H)])
+    with pytest.raises(q.QStateError):
+        c.run(reg, 0)
+    c.close()
+    assert max_abs(reg.get_amps(), state) == 0.0
+    stale = reg.h
+    reg.close()
+    assert q.lib().qs_reg_destroy(stale) == -5      # double destroy
+    assert q.lib().qs_reg_destroy(None) == -5
+    assert q.lib().qs_init_zero(stale) == -5
+
+
+def test_owned_and_wrapped_registers_agree(q, env):
+    n = 10
+    ops = layered_circuit(n, 4, 2)
+    a = run_gpu(q, env, n, ops)
+    reg = q.Register(env, n, owned=True)
+    reg.init_zero()
+    for op in ops:
+        reg.apply(op)
+    assert max_abs(reg.get_amps(), a) == 0.0
+    reg.close()
+
+
+def test_profiler_counts_launches(q, env):
+    n = 12
+    env.profile(True)
+    env.profile_reset()
+    ops = layered_circuit(n, 2, 1)
+    run_gpu(q, env, n, ops, fusion=12)
+    launches, ms = env.profile_read(q.qstate.K_FUSED)
+    env.profile(False)
+    assert launches >= 1 and ms > 0.0

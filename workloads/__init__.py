@@ -7,5 +7,6 @@ that arithmetic on their own.
 """
 from .circuits import (  # noqa: F401
     Op, haar_unitary, layered_circuit, noisy_circuit, param_circuit,
-    measurement_draws, gate_counts, product_layer, X, H, ry, rz,
+    measurement_draws, gate_counts, product_layer, inverse, random_state,
+    random_gate_ops, X, H, ry, rz,
 )

@@ -149,3 +149,46 @@ def gate_counts(ops: list[Op]) -> dict:
             key = 'cu'
         out[key] = out.get(key, 0) + 1
     return out
+
+
+def inverse(ops: list[Op]) -> list[Op]:
+    """The adjoint gate list: reversed order, U -> U^dagger, phase -> -phase."""
+    out: list[Op] = []
+    for o in reversed(ops):
+        if o.kind == 'u':
+            out.append(Op('u', target=o.target, controls=o.controls,
+                          u=np.ascontiguousarray(o.u.conj().T)))
+        elif o.kind == 'x':
+            out.append(Op('x', target=o.target, controls=o.controls))
+        elif o.kind == 'phase':
+            out.append(Op('phase', qubits=o.qubits, angle=-o.angle,
+                          controls=o.controls, target=o.target))
+        else:
+            raise ValueError(f'{o.kind} has no inverse')
+    return out
+
+
+def random_state(nbits: int, seed: int) -> np.ndarray:
+    """A normalised complex Gaussian vector of 2^nbits amplitudes."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    psi = rng.standard_normal(1 << nbits) + 1j * rng.standard_normal(1 << nbits)
+    return np.ascontiguousarray(psi / np.linalg.norm(psi))
+
+
+def random_gate_ops(n: int, count: int, seed: int, max_controls: int = 3) -> list[Op]:
+    """Mixed single-target gates: dense (Haar), NOT and multi-qubit phases on
+    random targets with 0..max_controls random controls."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ops: list[Op] = []
+    for _ in range(count):
+        k = int(rng.integers(0, min(max_controls, n - 1) + 1))
+        qs = [int(v) for v in rng.choice(n, size=k + 1, replace=False)]
+        kind = ('u', 'u', 'x', 'phase')[int(rng.integers(0, 4))]
+        if kind == 'u':
+            ops.append(Op('u', target=qs[k], controls=tuple(qs[:k]), u=haar_unitary(rng)))
+        elif kind == 'x':
+            ops.append(Op('x', target=qs[k], controls=tuple(qs[:k])))
+        else:
+            ops.append(Op('phase', qubits=tuple(qs), angle=float(rng.uniform(0, 2 * math.pi)),
+                          controls=tuple(qs[:k]), target=qs[k]))
+    return ops
