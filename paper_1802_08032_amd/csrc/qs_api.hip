@@ -734,11 +734,10 @@ qs_status qs_circuit_add_channel(qs_circuit c, int channel, int target, double p
     return QS_OK;
 }
 
-qs_status qs_circuit_run(qs_reg r, qs_circuit c, int fusion_qubits, int* n_passes)
+static qs_status circuit_check(qs_reg r, qs_circuit c)
 {
     QS_CHECK_REG(r);
     if (!valid_circ(c)) return qs::set_error(QS_E_HANDLE, "invalid circuit handle");
-    if (fusion_qubits < 0) return qs::set_error(QS_E_ARG, "negative fusion width");
     // Validate every op against this register before launching anything.
     for (const OpRec& op : c->ops) {
         if (op.kind == 3) {
@@ -753,14 +752,41 @@ qs_status qs_circuit_run(qs_reg r, qs_circuit c, int fusion_qubits, int* n_passe
         for (int q : op.ctrls)
             if (q >= r->n) return qs::set_error(QS_E_ARG, "circuit qubit outside the register");
     }
-    if (fusion_qubits > 0 && r->kind == QS_STATEVEC)
-        return qs::run_fused_sv(r, c->ops, fusion_qubits, n_passes);
+    return QS_OK;
+}
+
+static qs_status circuit_unfused(qs_reg r, qs_circuit c, int* n_passes)
+{
     for (const OpRec& op : c->ops) {
         qs_status s = qs::apply_op(r, op);
         if (s) return s;
     }
     if (n_passes) *n_passes = (int)c->ops.size();
     return QS_OK;
+}
+
+qs_status qs_circuit_run(qs_reg r, qs_circuit c, int fusion_qubits, int* n_passes)
+{
+    qs_status s = circuit_check(r, c);
+    if (s) return s;
+    if (fusion_qubits < 0) return qs::set_error(QS_E_ARG, "negative fusion width");
+    if (fusion_qubits > 0 && r->kind == QS_STATEVEC)
+        return qs::run_fused_sv(r, c->ops, qs::default_fused_config(r->prec, fusion_qubits, r->n), n_passes);
+    return circuit_unfused(r, c, n_passes);
+}
+
+qs_status qs_circuit_run_tiled(qs_reg r, qs_circuit c, int tile_qubits, int thread_bits, int max_phases,
+                               int* n_passes)
+{
+    qs_status s = circuit_check(r, c);
+    if (s) return s;
+    if (r->kind != QS_STATEVEC) return qs::set_error(QS_E_KIND, "tiled runs need a state vector");
+    const int RB = tile_qubits - thread_bits;
+    if (!qs::fused_shape_supported(r->prec, thread_bits, RB))
+        return qs::set_error(QS_E_ARG, "unsupported tile shape");
+    if (tile_qubits > r->n) return qs::set_error(QS_E_ARG, "tile wider than the register");
+    if (max_phases < 0) return qs::set_error(QS_E_ARG, "negative phase cap");
+    return qs::run_fused_sv(r, c->ops, qs::FusedConfig{thread_bits, RB, max_phases}, n_passes);
 }
 
 }  // extern "C"

@@ -53,7 +53,7 @@ struct FPass {
 };
 
 struct FOp {
-    int kind;        // 0 dense, 1 not, 2 phase
+    int kind;        // specialised op code (see apply_op)
     int rb;          // target register bit (dense / not)
     uint32_t rmask;  // register bits that must be 1
     uint32_t tmask;  // thread-index bits that must be 1
@@ -61,73 +61,142 @@ struct FOp {
     double m[8];     // dense matrix, or phase factor in m[0], m[1]
 };
 
-template <typename T, int RB, int RBIT>
-__device__ __forceinline__ void dense_rb(typename C2<T>::type (&v)[1 << RB], const FOp& op)
+// In-register op application.  Conditions that are the same for the whole
+// workgroup (controls outside the tile, register-bit controls) become scalar
+// selects; only thread-bit controls need per-lane selects.  Every variant is
+// straight-line code over compile-time register indices.
+
+template <typename T>
+__device__ __forceinline__ void load_mat(T (&m)[8], const FOp& op)
 {
-    using V = typename C2<T>::type;
-    T m[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) m[k] = (T)op.m[k];
-    const uint32_t rmask = op.rmask;
-#pragma unroll
-    for (int r0 = 0; r0 < (1 << RB); ++r0) {
-        if (r0 & (1 << RBIT)) continue;
-        if (((uint32_t)r0 & rmask) != rmask) continue;
-        apply2<T, V>(m, v[r0], v[r0 | (1 << RBIT)]);
-    }
 }
 
-template <typename T, int RB, int RBIT>
-__device__ __forceinline__ void not_rb(typename C2<T>::type (&v)[1 << RB], const FOp& op)
+// Identity element k of a row-major interleaved 2x2 matrix.
+template <typename T>
+__device__ __forceinline__ T ident(int k) { return (k == 0 || k == 6) ? T(1) : T(0); }
+
+// Dense 2x2 on register bit RBIT.  MASKED: only pairs whose register index
+// has every bit of rmask set (identity matrix elsewhere, chosen per pair).
+template <typename T, int RB, int RBIT, bool MASKED>
+__device__ __forceinline__ void dense_rb(typename C2<T>::type (&v)[1 << RB], const T (&m)[8], uint32_t rmask)
 {
     using V = typename C2<T>::type;
-    const uint32_t rmask = op.rmask;
 #pragma unroll
     for (int r0 = 0; r0 < (1 << RB); ++r0) {
         if (r0 & (1 << RBIT)) continue;
-        if (((uint32_t)r0 & rmask) != rmask) continue;
-        const V t = v[r0];
-        v[r0] = v[r0 | (1 << RBIT)];
-        v[r0 | (1 << RBIT)] = t;
+        if constexpr (MASKED) {
+            const bool pc = ((uint32_t)r0 & rmask) == rmask;
+            T mm[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) mm[k] = pc ? m[k] : ident<T>(k);
+            apply2<T, V>(mm, v[r0], v[r0 | (1 << RBIT)]);
+        } else {
+            apply2<T, V>(m, v[r0], v[r0 | (1 << RBIT)]);
+        }
     }
 }
 
+// NOT on register bit RBIT: swap each pair where `sel` (per lane) and, when
+// MASKED, the pair's register controls hold.  LANE = false: sel is true.
+template <typename T, int RB, int RBIT, bool MASKED, bool LANE>
+__device__ __forceinline__ void not_rb(typename C2<T>::type (&v)[1 << RB], uint32_t rmask, bool sel)
+{
+    using V = typename C2<T>::type;
+#pragma unroll
+    for (int r0 = 0; r0 < (1 << RB); ++r0) {
+        if (r0 & (1 << RBIT)) continue;
+        const int r1 = r0 | (1 << RBIT);
+        bool c = true;
+        if constexpr (MASKED) c = ((uint32_t)r0 & rmask) == rmask;
+        if constexpr (LANE) c = c && sel;
+        if constexpr (!MASKED && !LANE) {
+            const V t = v[r0];
+            v[r0] = v[r1];
+            v[r1] = t;
+        } else {
+            const V a = v[r0], b = v[r1];
+            v[r0].x = c ? b.x : a.x;
+            v[r0].y = c ? b.y : a.y;
+            v[r1].x = c ? a.x : b.x;
+            v[r1].y = c ? a.y : b.y;
+        }
+    }
+}
+
+// Diagonal phase: multiply the registers whose index has every bit of rmask
+// set by (fr, fi) (already 1 on lanes that fail their thread-bit controls).
 template <typename T, int RB>
-__device__ __forceinline__ void phase_op(typename C2<T>::type (&v)[1 << RB], const FOp& op)
+__device__ __forceinline__ void phase_op(typename C2<T>::type (&v)[1 << RB], T fr, T fi, uint32_t rmask)
 {
     using V = typename C2<T>::type;
-    const T fr = (T)op.m[0], fi = (T)op.m[1];
-    const uint32_t rmask = op.rmask;
 #pragma unroll
     for (int r = 0; r < (1 << RB); ++r) {
-        if (((uint32_t)r & rmask) != rmask) continue;
-        v[r] = cmul<T, V>(fr, fi, v[r]);
+        const bool pc = ((uint32_t)r & rmask) == rmask;
+        const T ar = pc ? fr : T(1), ai = pc ? fi : T(0);
+        v[r] = cmul<T, V>(ar, ai, v[r]);
     }
 }
 
-template <typename T, int RB>
-__device__ __forceinline__ void apply_op(typename C2<T>::type (&v)[1 << RB], const FOp& op)
+// Op codes: the host specialises every op so that the device dispatches with
+// one switch and each case is straight-line code.
+//   code = 4 * rb + variant        dense gate (variant: bit 0 register controls,
+//                                  bit 1 thread-bit controls)
+//   code = 32 + 4 * rb + variant   NOT
+//   code = 64 + lane               phase (lane: thread-bit controls present)
+enum : int { kDense = 0, kNot = 32, kPhase = 64 };
+
+template <typename T, int RB, int RBIT, int VAR>
+__device__ __forceinline__ void dense_case(typename C2<T>::type (&v)[1 << RB], const FOp& op, uint32_t tid)
 {
-    if (op.kind == 2) {
-        phase_op<T, RB>(v, op);
-        return;
+    T m[8];
+    load_mat<T>(m, op);
+    if constexpr (VAR & 2) {
+        const bool sel = (tid & op.tmask) == op.tmask;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) m[k] = sel ? m[k] : ident<T>(k);
     }
-    if (op.kind == 0) {
-        switch (op.rb) {
-        case 0: dense_rb<T, RB, 0>(v, op); break;
-        case 1: if constexpr (RB > 1) dense_rb<T, RB, 1>(v, op); break;
-        case 2: if constexpr (RB > 2) dense_rb<T, RB, 2>(v, op); break;
-        case 3: if constexpr (RB > 3) dense_rb<T, RB, 3>(v, op); break;
-        case 4: if constexpr (RB > 4) dense_rb<T, RB, 4>(v, op); break;
-        }
-        return;
+    dense_rb<T, RB, RBIT, (VAR & 1) != 0>(v, m, op.rmask);
+}
+
+template <typename T, int RB, int RBIT, int VAR>
+__device__ __forceinline__ void not_case(typename C2<T>::type (&v)[1 << RB], const FOp& op, uint32_t tid)
+{
+    const bool sel = (tid & op.tmask) == op.tmask;
+    not_rb<T, RB, RBIT, (VAR & 1) != 0, (VAR & 2) != 0>(v, op.rmask, sel);
+}
+
+template <typename T, int RB, bool LANE>
+__device__ __forceinline__ void phase_case(typename C2<T>::type (&v)[1 << RB], const FOp& op, uint32_t tid)
+{
+    T fr = (T)op.m[0], fi = (T)op.m[1];
+    if constexpr (LANE) {
+        const bool sel = (tid & op.tmask) == op.tmask;
+        fr = sel ? fr : T(1);
+        fi = sel ? fi : T(0);
     }
-    switch (op.rb) {
-    case 0: not_rb<T, RB, 0>(v, op); break;
-    case 1: if constexpr (RB > 1) not_rb<T, RB, 1>(v, op); break;
-    case 2: if constexpr (RB > 2) not_rb<T, RB, 2>(v, op); break;
-    case 3: if constexpr (RB > 3) not_rb<T, RB, 3>(v, op); break;
-    case 4: if constexpr (RB > 4) not_rb<T, RB, 4>(v, op); break;
+    phase_op<T, RB>(v, fr, fi, op.rmask);
+}
+
+template <typename T, int RB>
+__device__ __forceinline__ void apply_op(typename C2<T>::type (&v)[1 << RB], const FOp& op, uint32_t tid)
+{
+    switch (op.kind) {
+#define QS_DENSE(RBIT)                                                                   \
+    case kDense + 4 * RBIT + 0: if constexpr (RB > RBIT) dense_case<T, RB, RBIT, 0>(v, op, tid); break; \
+    case kDense + 4 * RBIT + 1: if constexpr (RB > RBIT) dense_case<T, RB, RBIT, 1>(v, op, tid); break; \
+    case kDense + 4 * RBIT + 2: if constexpr (RB > RBIT) dense_case<T, RB, RBIT, 2>(v, op, tid); break; \
+    case kDense + 4 * RBIT + 3: if constexpr (RB > RBIT) dense_case<T, RB, RBIT, 3>(v, op, tid); break; \
+    case kNot + 4 * RBIT + 0: if constexpr (RB > RBIT) not_case<T, RB, RBIT, 0>(v, op, tid); break;     \
+    case kNot + 4 * RBIT + 1: if constexpr (RB > RBIT) not_case<T, RB, RBIT, 1>(v, op, tid); break;     \
+    case kNot + 4 * RBIT + 2: if constexpr (RB > RBIT) not_case<T, RB, RBIT, 2>(v, op, tid); break;     \
+    case kNot + 4 * RBIT + 3: if constexpr (RB > RBIT) not_case<T, RB, RBIT, 3>(v, op, tid); break;
+    QS_DENSE(0) QS_DENSE(1) QS_DENSE(2) QS_DENSE(3) QS_DENSE(4)
+#undef QS_DENSE
+    case kPhase + 0: phase_case<T, RB, false>(v, op, tid); break;
+    case kPhase + 1: phase_case<T, RB, true>(v, op, tid); break;
+    default: break;
     }
 }
 
@@ -188,8 +257,8 @@ __global__ __launch_bounds__(1 << TB) void k_fused(typename C2<T>::type* __restr
             if (ph > 0) relayout<T, TB, RB>(v, lds, F, tid);
             for (int o = F.op_begin; o < F.op_end; ++o) {
                 const FOp& op = ops[o];
-                const bool tok = ((tid & op.tmask) == op.tmask) && ((base & op.gmask) == op.gmask);
-                if (tok) apply_op<T, RB>(v, op);
+                if ((base & op.gmask) != op.gmask) continue;  // same for the whole tile
+                apply_op<T, RB>(v, op, tid);
             }
         }
         if (P->final_transpose) relayout<T, TB, RB>(v, lds, P->fin, tid);
@@ -461,8 +530,8 @@ FOp encode_op(const OpRec& op, const PassPlan& P, const Layout& L)
             }
     };
     for (int q : op.ctrls) classify(q);
-    f.kind = op.kind;
     if (op.kind == 2) {
+        f.kind = kPhase + (f.tmask ? 1 : 0);
         f.m[0] = cos(op.angle);
         f.m[1] = sin(op.angle);
         return f;
@@ -470,60 +539,78 @@ FOp encode_op(const OpRec& op, const PassPlan& P, const Layout& L)
     const int jt = local[op.target];
     for (size_t b = 0; b < L.reg.size(); ++b)
         if (L.reg[b] == jt) f.rb = (int)b;
+    const int var = (f.rmask ? 1 : 0) | (f.tmask ? 2 : 0);
+    f.kind = (op.kind == 0 ? kDense : kNot) + 4 * f.rb + var;
     if (op.kind == 0)
         for (int k = 0; k < 8; ++k) f.m[k] = op.u[k];
     return f;
 }
 
-struct Config {
+// Tile shapes compiled in: (thread bits, register bits).  LDS holds the
+// whole tile, so 2^K * element size <= 160 KiB.
+struct Shape {
     int TB, RB;
 };
-
-Config pick_config(int prec, int k, int n)
-{
-    // K = TB + RB <= min(k, n); LDS = 2^K * element bytes <= 128 KiB
-    int K = std::min(k, n);
-    const int kmax = prec == QS_C128 ? 13 : 14;
-    K = std::min(K, kmax);
-    if (K < 9) return Config{0, 0};
-    if (K == 14) return Config{9, 5};
-    if (K == 13) return Config{8, 5};
-    if (K == 12) return Config{8, 4};
-    if (K == 11) return Config{8, 3};
-    if (K == 10) return Config{7, 3};
-    return Config{6, 3};
-}
+constexpr Shape kShapes128[] = {{6, 3}, {7, 3}, {8, 3}, {8, 4}, {9, 3}, {8, 5}, {9, 4}, {10, 3}};
+constexpr Shape kShapes64[] = {{6, 3}, {7, 3}, {8, 3}, {8, 4}, {9, 3}, {8, 5}, {9, 4}, {10, 3},
+                               {9, 5}, {10, 4}};
 
 template <typename T, int TB, int RB>
 hipError_t launch_cfg(hipStream_t s, void* amp, const FPass* P, const FOp* ops, uint64_t ntiles)
 {
     using V = typename C2<T>::type;
     uint64_t grid = ntiles;
-    const uint64_t cap = 256ull * 8;
+    const uint64_t cap = 256ull * 16;
     if (grid > cap) grid = cap;
     hipLaunchKernelGGL((k_fused<T, TB, RB>), dim3((unsigned)grid), dim3(1 << TB), 0, s, (V*)amp, P, ops, ntiles);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_fused_pass(hipStream_t s, const Config& c, void* amp, const FPass* P, const FOp* ops,
+hipError_t launch_fused_pass(hipStream_t s, const FusedConfig& c, void* amp, const FPass* P, const FOp* ops,
                              uint64_t ntiles)
 {
-    if constexpr (sizeof(T) == 4)
-        if (c.TB == 9 && c.RB == 5) return launch_cfg<T, 9, 5>(s, amp, P, ops, ntiles);
-    if (c.TB == 8 && c.RB == 5) return launch_cfg<T, 8, 5>(s, amp, P, ops, ntiles);
-    if (c.TB == 8 && c.RB == 4) return launch_cfg<T, 8, 4>(s, amp, P, ops, ntiles);
-    if (c.TB == 8 && c.RB == 3) return launch_cfg<T, 8, 3>(s, amp, P, ops, ntiles);
-    if (c.TB == 7 && c.RB == 3) return launch_cfg<T, 7, 3>(s, amp, P, ops, ntiles);
-    return launch_cfg<T, 6, 3>(s, amp, P, ops, ntiles);
+#define QS_SHAPE(tb, rb) \
+    if (c.TB == tb && c.RB == rb) return launch_cfg<T, tb, rb>(s, amp, P, ops, ntiles);
+    QS_SHAPE(6, 3) QS_SHAPE(7, 3) QS_SHAPE(8, 3) QS_SHAPE(8, 4) QS_SHAPE(9, 3)
+    QS_SHAPE(8, 5) QS_SHAPE(9, 4) QS_SHAPE(10, 3)
+    if constexpr (sizeof(T) == 4) {
+        QS_SHAPE(9, 5) QS_SHAPE(10, 4)
+    }
+#undef QS_SHAPE
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-qs_status run_fused_sv(qs_reg r, const std::vector<OpRec>& ops, int k, int* passes_out)
+bool fused_shape_supported(int prec, int TB, int RB)
 {
-    const Config cfg = pick_config(r->prec, k, r->n);
-    if (cfg.TB == 0) {  // too small to tile: one kernel per op
+    if (prec == QS_C128) {
+        for (const Shape& sh : kShapes128)
+            if (sh.TB == TB && sh.RB == RB) return true;
+    } else {
+        for (const Shape& sh : kShapes64)
+            if (sh.TB == TB && sh.RB == RB) return true;
+    }
+    return false;
+}
+
+FusedConfig default_fused_config(int prec, int k, int n)
+{
+    int K = std::min(k, n);
+    K = std::min(K, prec == QS_C128 ? 13 : 14);
+    FusedConfig c{0, 0, kPhMax};
+    if (K < 9) return c;
+    static const int tb_of[15] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 6, 7, 8, 8, 8, 9};
+    c.TB = tb_of[K];
+    c.RB = K - c.TB;
+    return c;
+}
+
+qs_status run_fused_sv(qs_reg r, const std::vector<OpRec>& ops, FusedConfig cfg, int* passes_out)
+{
+    if (cfg.max_phases <= 0 || cfg.max_phases > kPhMax) cfg.max_phases = kPhMax;
+    if (cfg.TB == 0 || cfg.TB + cfg.RB > r->n) {  // too small to tile: one kernel per op
         for (const OpRec& op : ops) {
             qs_status s = apply_op(r, op);
             if (s) return s;
@@ -532,7 +619,7 @@ qs_status run_fused_sv(qs_reg r, const std::vector<OpRec>& ops, int k, int* pass
         return QS_OK;
     }
     const int TB = cfg.TB, RB = cfg.RB, K = TB + RB;
-    std::vector<PassPlan> plan = plan_passes(ops, r->n, TB, RB, kPhMax, 1 << 12);
+    std::vector<PassPlan> plan = plan_passes(ops, r->n, TB, RB, cfg.max_phases, 1 << 12);
 
     // serialise passes + ops
     std::vector<FPass> hp(plan.size());

@@ -84,8 +84,15 @@ qs_status profiled(qs_reg r, int klass, F&& f)
     return QS_OK;
 }
 
-// Fused execution of a state-vector circuit (qs_fused.hip).
-qs_status run_fused_sv(qs_reg r, const std::vector<OpRec>& ops, int k, int* passes);
+// Fused execution of a state-vector circuit (qs_fused.hip): tiles of
+// 2^(TB+RB) amplitudes, 2^TB threads, at most max_phases register layouts
+// per pass.
+struct FusedConfig {
+    int TB, RB, max_phases;
+};
+bool fused_shape_supported(int prec, int TB, int RB);
+FusedConfig default_fused_config(int prec, int k, int n);
+qs_status run_fused_sv(qs_reg r, const std::vector<OpRec>& ops, FusedConfig cfg, int* passes);
 // Per-operation execution of one recorded op (qs_api.hip).
 qs_status apply_op(qs_reg r, const OpRec& op);
 

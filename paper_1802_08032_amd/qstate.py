@@ -79,6 +79,7 @@ SIGNATURES = {
     'qs_circuit_add_channel': (_i, [_vp, _i, _i, _d]),
     'qs_circuit_size': (_i, [_vp, _PI]),
     'qs_circuit_run': (_i, [_vp, _vp, _i, _PI]),
+    'qs_circuit_run_tiled': (_i, [_vp, _vp, _i, _i, _i, _PI]),
 }
 
 
@@ -303,6 +304,12 @@ class Circuit:
     def run(self, reg: Register, fusion_qubits: int = 0) -> int:
         passes = C.c_int()
         _check(lib().qs_circuit_run(reg.h, self.h, fusion_qubits, C.byref(passes)))
+        return passes.value
+
+    def run_tiled(self, reg: Register, tile_qubits: int, thread_bits: int, max_phases: int = 0) -> int:
+        passes = C.c_int()
+        _check(lib().qs_circuit_run_tiled(reg.h, self.h, tile_qubits, thread_bits, max_phases,
+                                          C.byref(passes)))
         return passes.value
 
     def close(self):
