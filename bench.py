@@ -3,10 +3,11 @@
 Workload: one 32-qubit complex128 state vector (64 GiB) and a depth-10
 layered random circuit (per layer: a Haar-random unitary on every qubit, a
 CNOT brick, one phase gate with 3 controls + 1 target), 485 gates.  One step
-= init |0..0> + the whole circuit (fused into HBM round trips of 2^13-
-amplitude tiles) + total probability + probability of an outcome + one
-measurement.  Inputs are seeded and synthetic; the register is resident in
-HBM before the timed region starts.
+= init |0..0> + the whole circuit (fused into HBM round trips of 2^K-
+amplitude tiles by run-time compiled pass kernels, tile shape chosen by the
+autotuner during warm-up) + total probability + probability of an outcome +
+one measurement.  Inputs are seeded and synthetic; the register is resident
+in HBM before the timed region starts.
 
 Prints one JSON line (metric, value = gates/s, roofline of the dominant
 kernel measured with HIP events around each of its launches, CPU oracle
@@ -79,30 +80,48 @@ def main():
     ap.add_argument('--warmup', type=int, default=1)
     ap.add_argument('--qubits', type=int, default=32)
     ap.add_argument('--depth', type=int, default=10)
-    ap.add_argument('--fusion', type=int, default=13)
+    ap.add_argument('--tile', default='auto', help="'auto' (autotuner) or K,TB,contig")
     ap.add_argument('--no-extras', action='store_true', help='skip unfused / per-target / CPU legs')
+    ap.add_argument('--copy-calibration', action='store_true',
+                    help='only run a device copy of 16 GiB (HBM counter calibration)')
     args = ap.parse_args()
     if args.gpus != 1:
         sys.exit('bench.py measures one GPU only: the method runs on one MI355X with the whole '
                  'state resident; --gpus above 1 is not supported.')
 
     import torch
+    if args.copy_calibration:
+        a = torch.zeros(1 << 30, dtype=torch.complex128, device='cuda')
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({'copy_bytes_read': a.numel() * 16, 'copy_bytes_written': b.numel() * 16, 'launches': 3}))
+        return
     import paper_1802_08032_amd as q
+    from paper_1802_08032_amd import autotune
     from workloads import layered_circuit, measurement_draws
 
-    n, depth, K = args.qubits, args.depth, args.fusion
+    n, depth = args.qubits, args.depth
     elem = 16
     ops = layered_circuit(n, depth, seed=1, mcphase=True)
     gates = len(ops)
-    log(f'{n} qubits c128, depth {depth}, {gates} gates, fusion k={K}')
+    log(f'{n} qubits c128, depth {depth}, {gates} gates')
     env = q.Env(0)
     reg = q.Register(env, n, q.STATEVEC, q.C128)
     circ = q.Circuit(ops)
     draws = measurement_draws(1, 0, args.warmup + args.steps)
+    if args.tile == 'auto':
+        tuned = autotune.tune(reg, circ, ops, budget_s=60.0, log=log)
+        K, TB, L = tuned['tile_qubits'], tuned['thread_bits'], tuned['contig_qubits']
+    else:
+        K, TB, L = (int(v) for v in args.tile.split(','))
+        tuned = None
+    log(f'tile: {K} qubits, {1 << TB} threads, {L} contiguous qubits')
 
     def step(i):
         reg.init_zero()
-        passes = circ.run(reg, K)
+        passes = circ.run_compiled(reg, K, TB, 0, L)
         reg.calc_total_prob()
         reg.calc_prob_of_outcome(n - 1, 0)
         reg.measure(0, float(draws[i]))
@@ -148,8 +167,9 @@ def main():
         'data': 'synthetic',
         'config': {
             'workload': f'{n}-qubit complex128 state vector, depth-{depth} layered random circuit '
-                        f'(Haar 1q layer + CNOT brick + 3-control phase per layer), fused k={K}',
-            'qubits': n, 'depth': depth, 'gates_per_step': gates, 'fusion_qubits': K,
+                        f'(Haar 1q layer + CNOT brick + 3-control phase per layer), fused tiles of {K} qubits',
+            'qubits': n, 'depth': depth, 'gates_per_step': gates, 'tile_qubits': K,
+            'workgroup_threads': 1 << TB, 'contig_qubits': L, 'autotuned': tuned is not None,
             'fused_passes_per_step': passes, 'parallelism': 'single GPU',
         },
         'circuits_per_s': args.steps / dt,
@@ -158,7 +178,8 @@ def main():
         'roofline': {
             'bound': 'hbm', 'achieved': achieved, 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
             'frac': achieved / HBM_PEAK_GBS, 'traffic': None,
-            'kernel': 'k_fused<double,8,5>', 'launches': launches, 'avg_ms': avg_ms,
+            'kernel': f'qs_pass (run-time compiled fused pass, {K}-qubit tile)', 'launches': launches,
+            'avg_ms': avg_ms,
         },
     }
 
@@ -174,6 +195,9 @@ def main():
         out['unfused_gates_per_s'] = gates / t_unf
         out['unfused_effective_gbps'] = algorithmic_bytes(ops, n, elem) / t_unf / 1e9
         out['fused_pass_speedup'] = t_unf / (fused_ms / max(1, launches) * passes * 1e-3)
+        if tuned is not None:
+            out['autotune_trials'] = [{k: t[k] for k in ('tile_qubits', 'thread_bits', 'contig_qubits', 'passes',
+                                                          'seconds')} for t in tuned.get('trials', [])]
         # per-target effective bandwidth of one dense gate (median of 5)
         log('per-target sweep')
         u = ops[0].u

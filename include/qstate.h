@@ -184,6 +184,28 @@ qs_status qs_circuit_run(qs_reg r, qs_circuit c, int fusion_qubits, int* n_passe
  * QS_E_ARG for other shapes or a tile wider than the register. */
 qs_status qs_circuit_run_tiled(qs_reg r, qs_circuit c, int tile_qubits, int thread_bits,
                                int max_phases, int* n_passes);
+/* As qs_circuit_run_tiled, but each pass runs a kernel generated for that
+ * pass's structure (targets, controls, register layouts) and compiled for
+ * gfx950 at run time; matrices and angles stay kernel data.  Each workgroup
+ * loops over tiles and prefetches the next tile while computing the
+ * current one.  contig_qubits (1..6, <= thread_bits; 0: 6) global qubits
+ * 0..contig_qubits-1 stay on consecutive lanes whenever a tile is read or
+ * written, i.e. HBM is accessed in contiguous runs of 2^contig_qubits
+ * amplitudes; fewer pinned qubits leave more tile qubits for gates.  Compiled code
+ * is cached in memory and on disk ($QS_JIT_CACHE, default
+ * $HOME/.cache/qstate); the first run of a new structure pays the compile
+ * time.  The compiled form is kept with the circuit until ops are added or
+ * the register shape or tile changes.  Accepts 6..10 thread bits and 1..5
+ * register bits with the tile in 160 KiB of LDS.  State vectors only. */
+qs_status qs_circuit_run_compiled(qs_reg r, qs_circuit c, int tile_qubits, int thread_bits,
+                                  int max_phases, int contig_qubits, int* n_passes);
+/* Host-only: the generated HIP source of pass `pass` for an n-qubit
+ * register of precision `prec` (copied into buf, NUL-terminated, truncated
+ * to cap - 1 bytes; *len gets the full length, *n_passes the pass count).
+ * Needs no GPU. */
+qs_status qs_circuit_source(qs_circuit c, int n, int prec, int tile_qubits, int thread_bits,
+                            int max_phases, int contig_qubits, int pass, char* buf, size_t cap,
+                            size_t* len, int* n_passes);
 
 #ifdef __cplusplus
 }

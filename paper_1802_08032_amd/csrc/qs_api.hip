@@ -654,6 +654,7 @@ qs_status qs_circuit_destroy(qs_circuit c)
 {
     if (!valid_circ(c) || !handle_remove(c)) return qs::set_error(QS_E_HANDLE, "invalid circuit handle");
     c->magic = 0;
+    qs::jit_plan_free(c->jit);
     delete c;
     return QS_OK;
 }
@@ -787,6 +788,65 @@ qs_status qs_circuit_run_tiled(qs_reg r, qs_circuit c, int tile_qubits, int thre
     if (tile_qubits > r->n) return qs::set_error(QS_E_ARG, "tile wider than the register");
     if (max_phases < 0) return qs::set_error(QS_E_ARG, "negative phase cap");
     return qs::run_fused_sv(r, c->ops, qs::FusedConfig{thread_bits, RB, max_phases}, n_passes);
+}
+
+// Shapes the run-time compiled passes accept: 6..10 thread bits, 1..5
+// register bits, the tile in at most 160 KiB of LDS.
+static qs_status check_compiled_shape(int prec, int n, int tile_qubits, int thread_bits, int max_phases,
+                                      int contig)
+{
+    if (contig < 0 || contig > 6 || contig > thread_bits) return qs::set_error(QS_E_ARG, "bad contiguous-qubit count");
+    const int RB = tile_qubits - thread_bits;
+    if (thread_bits < 6 || thread_bits > 10 || RB < 1 || RB > 5)
+        return qs::set_error(QS_E_ARG, "unsupported tile shape");
+    if ((elem_bytes(prec) << tile_qubits) > 160u * 1024u) return qs::set_error(QS_E_ARG, "tile exceeds LDS");
+    if (tile_qubits > n) return qs::set_error(QS_E_ARG, "tile wider than the register");
+    if (max_phases < 0) return qs::set_error(QS_E_ARG, "negative phase cap");
+    return QS_OK;
+}
+
+qs_status qs_circuit_run_compiled(qs_reg r, qs_circuit c, int tile_qubits, int thread_bits, int max_phases,
+                                  int contig_qubits, int* n_passes)
+{
+    qs_status s = circuit_check(r, c);
+    if (s) return s;
+    if (r->kind != QS_STATEVEC) return qs::set_error(QS_E_KIND, "compiled runs need a state vector");
+    if ((s = check_compiled_shape(r->prec, r->n, tile_qubits, thread_bits, max_phases, contig_qubits))) return s;
+    for (const OpRec& op : c->ops)
+        if (op.kind == 3) return qs::set_error(QS_E_KIND, "channels need a density matrix");
+    qs::FusedConfig cfg{thread_bits, tile_qubits - thread_bits, max_phases};
+    cfg.contig = contig_qubits ? contig_qubits : std::min(6, r->n);
+    return qs::run_compiled_sv(r, c, cfg, n_passes);
+}
+
+qs_status qs_circuit_source(qs_circuit c, int n, int prec, int tile_qubits, int thread_bits, int max_phases,
+                            int contig_qubits, int pass, char* buf, size_t cap, size_t* len, int* n_passes)
+{
+    if (!valid_circ(c)) return qs::set_error(QS_E_HANDLE, "invalid circuit handle");
+    if (prec != QS_C64 && prec != QS_C128) return qs::set_error(QS_E_ARG, "unknown precision");
+    if (n < 1 || n > 40) return qs::set_error(QS_E_ARG, "invalid qubit count");
+    qs_status s = check_compiled_shape(prec, n, tile_qubits, thread_bits, max_phases, contig_qubits);
+    if (s) return s;
+    for (const OpRec& op : c->ops) {
+        if (op.kind == 3) return qs::set_error(QS_E_KIND, "channels need a density matrix");
+        if (op.kind != 2 && op.target >= n) return qs::set_error(QS_E_ARG, "circuit qubit outside the register");
+        for (int q : op.ctrls)
+            if (q >= n) return qs::set_error(QS_E_ARG, "circuit qubit outside the register");
+    }
+    std::vector<std::string> srcs;
+    qs::FusedConfig cfg{thread_bits, tile_qubits - thread_bits, max_phases};
+    cfg.contig = contig_qubits ? contig_qubits : std::min(6, n);
+    qs::generate_sources(c->ops, n, prec, cfg, srcs);
+    if (n_passes) *n_passes = (int)srcs.size();
+    if (pass < 0 || pass >= (int)srcs.size()) return qs::set_error(QS_E_ARG, "no such pass");
+    const std::string& src = srcs[pass];
+    if (len) *len = src.size();
+    if (buf && cap > 0) {
+        const size_t k = std::min(cap - 1, src.size());
+        memcpy(buf, src.data(), k);
+        buf[k] = '\0';
+    }
+    return QS_OK;
 }
 
 }  // extern "C"

@@ -51,9 +51,15 @@ struct OpRec {
     double p;
 };
 
+namespace qs {
+struct JitPlan;
+void jit_plan_free(JitPlan* p);
+}  // namespace qs
+
 struct qs_circuit_s {
     uint32_t magic;
     std::vector<OpRec> ops;
+    qs::JitPlan* jit = nullptr;  // cached run-time compiled form (qs_jit.hip)
 };
 
 namespace qs {
@@ -89,10 +95,15 @@ qs_status profiled(qs_reg r, int klass, F&& f)
 // per pass.
 struct FusedConfig {
     int TB, RB, max_phases;
+    int contig = 6;  // low qubits kept on consecutive lanes for HBM access
 };
 bool fused_shape_supported(int prec, int TB, int RB);
 FusedConfig default_fused_config(int prec, int k, int n);
 qs_status run_fused_sv(qs_reg r, const std::vector<OpRec>& ops, FusedConfig cfg, int* passes);
+// Run-time compiled passes (qs_jit.hip).
+qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passes);
+qs_status generate_sources(const std::vector<OpRec>& ops, int n, int prec, FusedConfig cfg,
+                           std::vector<std::string>& out);
 // Per-operation execution of one recorded op (qs_api.hip).
 qs_status apply_op(qs_reg r, const OpRec& op);
 

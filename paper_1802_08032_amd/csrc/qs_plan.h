@@ -1,0 +1,42 @@
+// Planner for fused state-vector passes (see qs_plan.hip).
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "qs_host.h"
+
+namespace qs {
+
+constexpr int kPhMax = 24;  // register layouts per pass, at most
+
+// A register layout of a 2^(TB+RB)-amplitude tile: local qubit of each
+// thread bit and of each register bit.
+struct Layout {
+    std::vector<int> thr;
+    std::vector<int> reg;
+};
+
+struct PhasePlan {
+    Layout lay;
+    std::vector<int> ops;  // indices into the circuit, in application order
+};
+
+struct PassPlan {
+    std::vector<int> S;    // global qubits of the tile, ascending (local j <-> S[j])
+    std::vector<int> ops;  // indices into the circuit, in application order
+    std::vector<PhasePlan> phases;
+    Layout store;          // layout written back to HBM (coalesced)
+};
+
+uint64_t qubit_mask(const OpRec& op);
+bool coalesced(const Layout& L, int contig);
+// contig: global qubits 0..contig-1 sit on the first lanes whenever the tile
+// is read from or written to HBM (contiguous runs of 2^contig amplitudes).
+std::vector<PassPlan> plan_passes(const std::vector<OpRec>& all, int n, int TB, int RB, int max_phases,
+                                  int max_ops, int contig);
+// LDS images (K values) of the local bits for a re-layout from A to B.
+std::vector<uint32_t> swizzle(const Layout& A, const Layout& B, int K);
+
+}  // namespace qs

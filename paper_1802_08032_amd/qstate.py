@@ -80,6 +80,8 @@ SIGNATURES = {
     'qs_circuit_size': (_i, [_vp, _PI]),
     'qs_circuit_run': (_i, [_vp, _vp, _i, _PI]),
     'qs_circuit_run_tiled': (_i, [_vp, _vp, _i, _i, _i, _PI]),
+    'qs_circuit_run_compiled': (_i, [_vp, _vp, _i, _i, _i, _i, _PI]),
+    'qs_circuit_source': (_i, [_vp, _i, _i, _i, _i, _i, _i, _i, C.c_char_p, _sz, C.POINTER(_sz), _PI]),
 }
 
 
@@ -311,6 +313,24 @@ class Circuit:
         _check(lib().qs_circuit_run_tiled(reg.h, self.h, tile_qubits, thread_bits, max_phases,
                                           C.byref(passes)))
         return passes.value
+
+    def run_compiled(self, reg: Register, tile_qubits: int, thread_bits: int, max_phases: int = 0,
+                     contig_qubits: int = 0) -> int:
+        passes = C.c_int()
+        _check(lib().qs_circuit_run_compiled(reg.h, self.h, tile_qubits, thread_bits, max_phases,
+                                             contig_qubits, C.byref(passes)))
+        return passes.value
+
+    def source(self, n: int, prec: int, tile_qubits: int, thread_bits: int, pass_index: int = 0,
+               max_phases: int = 0, contig_qubits: int = 0):
+        """(generated HIP source of one pass, number of passes); host only."""
+        ln, npass = C.c_size_t(), C.c_int()
+        _check(lib().qs_circuit_source(self.h, n, prec, tile_qubits, thread_bits, max_phases, contig_qubits,
+                                       pass_index, None, 0, C.byref(ln), C.byref(npass)))
+        buf = C.create_string_buffer(ln.value + 1)
+        _check(lib().qs_circuit_source(self.h, n, prec, tile_qubits, thread_bits, max_phases, contig_qubits,
+                                       pass_index, buf, ln.value + 1, C.byref(ln), C.byref(npass)))
+        return buf.value.decode(), npass.value
 
     def close(self):
         if self.h:

@@ -1,0 +1,58 @@
+"""CPU checks of the run-time specialised pass kernels: the generated HIP
+source of each pass compiles for gfx950 with hipRTC (no GPU needed), and
+the generated code uses the literal layout the planner chose."""
+import ctypes as C
+import os
+
+import pytest
+
+from workloads import layered_circuit, random_gate_ops
+
+
+def hiprtc():
+    for name in ('libhiprtc.so', '/opt/rocm/lib/libhiprtc.so'):
+        try:
+            return C.CDLL(name)
+        except OSError:
+            continue
+    pytest.skip('hipRTC not available')
+
+
+def compile_src(src: str):
+    L = hiprtc()
+    prog = C.c_void_p()
+    assert L.hiprtcCreateProgram(C.byref(prog), src.encode(), b'qs_pass.hip', 0, None, None) == 0
+    opts = [b'--offload-arch=gfx950', b'-O3', b'-Xclang', b'-target-feature', b'-Xclang', b'-packed-fp32-ops']
+    arr = (C.c_char_p * len(opts))(*opts)
+    rc = L.hiprtcCompileProgram(prog, len(opts), arr)
+    size = C.c_size_t()
+    L.hiprtcGetProgramLogSize(prog, C.byref(size))
+    log = C.create_string_buffer(size.value + 1)
+    L.hiprtcGetProgramLog(prog, log)
+    code = C.c_size_t()
+    L.hiprtcGetCodeSize(prog, C.byref(code))
+    L.hiprtcDestroyProgram(C.byref(prog))
+    return rc, log.value.decode(errors='replace'), code.value
+
+
+@pytest.mark.parametrize('prec_name,tile,tb', [('C128', 12, 9), ('C64', 14, 10)])
+def test_generated_pass_compiles(prec_name, tile, tb):
+    import paper_1802_08032_amd as q
+    prec = getattr(q, prec_name)
+    ops = layered_circuit(20, 3, 1, mcphase=True) + random_gate_ops(20, 40, 3, max_controls=3)
+    c = q.Circuit(ops)
+    src, npass = c.source(20, prec, tile, tb, 0)
+    assert npass >= 1 and 'qs_pass' in src
+    rc, log, size = compile_src(src)
+    assert rc == 0, log
+    assert size > 1000
+    c.close()
+
+
+def test_source_rejects_bad_shapes():
+    import paper_1802_08032_amd as q
+    c = q.Circuit(layered_circuit(12, 1, 0))
+    for args in ((12, q.C128, 14, 9), (12, q.C128, 12, 5), (12, q.C128, 12, 11), (10, q.C128, 12, 8)):
+        with pytest.raises(q.QStateError):
+            c.source(*args)
+    c.close()

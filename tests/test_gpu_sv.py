@@ -221,3 +221,33 @@ def test_profiler_counts_launches(q, env):
     launches, ms = env.profile_read(q.qstate.K_FUSED)
     env.profile(False)
     assert launches >= 1 and ms > 0.0
+
+
+@pytest.mark.parametrize('prec_name,tile,tb,contig', [('C128', 13, 10, 6), ('C128', 12, 9, 6), ('C128', 11, 8, 6),
+                                                      ('C128', 9, 6, 6), ('C128', 13, 9, 4), ('C128', 12, 8, 3),
+                                                      ('C64', 14, 10, 6), ('C64', 13, 9, 4)])
+def test_compiled_passes_match_oracle(q, env, prec_name, tile, tb, contig):
+    """Run-time specialised pass kernels: random gates with controls inside
+    and outside the tile, plus a layered circuit with multi-controlled phases."""
+    prec = getattr(q, prec_name)
+    n = 16
+    ops = random_gate_ops(n, 200, seed=tile + tb, max_controls=4) + layered_circuit(n, 3, 4, mcphase=True)
+    state = random_state(n, 3)
+    ref = oracle_run(n, ops, state)
+    reg = q.Register(env, n, q.STATEVEC, prec)
+    reg.set_amps(state)
+    c = q.Circuit(ops)
+    log(f'compiled {prec_name} tile={tile} tb={tb} contig={contig}')
+    passes = c.run_compiled(reg, tile, tb, 0, contig)
+    got = reg.get_amps()
+    if prec == q.C128:
+        assert max_abs(got, ref) <= TOL128
+    else:
+        assert fidelity_deficit(ref, got) <= TOL64_FID
+    # the cached compiled form is reused on a second run
+    reg.set_amps(state)
+    assert c.run_compiled(reg, tile, tb, 0, contig) == passes
+    got2 = reg.get_amps()
+    assert max_abs(got2, got) == 0.0
+    c.close()
+    reg.close()
