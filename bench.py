@@ -44,6 +44,27 @@ def algorithmic_bytes(ops, n, elem):
     return total
 
 
+def recorded_traffic(n, K, TB, L):
+    """HBM bytes per fused pass from the committed rocprofv3 counter summary,
+    or None when that summary was taken for another shape or an older version
+    of the pass generator."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, 'profiles', f'qs_pass_{n}q_c128_hbm_traffic.md')
+    if not os.path.exists(path):
+        return None
+    src = b''.join(open(os.path.join(root, 'paper_1802_08032_amd', 'csrc', f), 'rb').read()
+                   for f in ('qs_jit.hip', 'qs_plan.hip'))
+    sha = hashlib.sha1(src).hexdigest()[:12]
+    for line in open(path):
+        line = line.strip()
+        if line.startswith('{') and '"traffic_bytes"' in line:
+            rec = json.loads(line)
+            if rec.get('tile') == [K, TB, L] and rec.get('generator_sha1') == sha and rec.get('qubits') == n:
+                return rec['traffic_bytes']
+    return None
+
+
 def cpu_baseline(ops_full, n_full, sample_qubits=28, budget_s=12.0):
     """Oracle (plain CPU code) applying the same circuit's gates to a
     sample_qubits register until ~budget_s elapses; scaled to n_full by the
@@ -177,7 +198,7 @@ def main():
         'effective_pct_peak': 100.0 * eff_gbs / HBM_PEAK_GBS,
         'roofline': {
             'bound': 'hbm', 'achieved': achieved, 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
-            'frac': achieved / HBM_PEAK_GBS, 'traffic': None,
+            'frac': achieved / HBM_PEAK_GBS, 'traffic': recorded_traffic(n, K, TB, L),
             'kernel': f'qs_pass (run-time compiled fused pass, {K}-qubit tile)', 'launches': launches,
             'avg_ms': avg_ms,
         },
