@@ -94,6 +94,64 @@ def cpu_baseline(ops_full, n_full, sample_qubits=28, budget_s=12.0):
     }
 
 
+def batched_leg(q, torch, log, reps=5):
+    """512 registers of 10..20 qubits (uniform, seed 3), depth-16 RY/RZ + CZ
+    ladder circuits (register i: seed 1000 + i): one persistent launch per
+    batch replayed from a HIP graph, in complex128 and complex64, against the
+    plain path that runs one circuit at a time with one kernel per gate."""
+    from workloads import param_circuit
+    rng = np.random.Generator(np.random.PCG64(3))
+    sizes = [int(v) for v in rng.integers(10, 21, 512)]
+    ops = [param_circuit(n, 16, 1000 + i) for i, n in enumerate(sizes)]
+    env = q.Env(0)
+    out = {'registers': len(sizes), 'depth': 16, 'gates': int(sum(len(o) for o in ops))}
+    amps = {}
+    for name, prec in (('c128', q.C128), ('c64', q.C64)):
+        regs = [q.Register(env, n, q.STATEVEC, prec) for n in sizes]
+        circs = [q.Circuit(o) for o in ops]
+        b = q.Batch(regs, circs, 10)
+        b.capture(init_zero=True)
+        b.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            b.replay()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        p0, tot = b.probs(0)
+        out[f'batched_{name}_circuits_per_s'] = len(sizes) / dt
+        out[f'batched_{name}_ms_per_batch'] = dt * 1e3
+        out[f'batched_{name}_max_total_prob_error'] = float(np.max(np.abs(tot - 1.0)))
+        out[f'batched_{name}_mean_z0'] = float(np.mean(2 * p0 - 1))
+        amps[name] = [r.get_amps() for r in regs]
+        log(f'batched {name}: {dt * 1e3:.2f} ms per 512 circuits')
+        b.close()
+        for c in circs:
+            c.close()
+        for r in regs:
+            r.close()
+    fids = [1.0 - abs(np.vdot(a, b)) ** 2 for a, b in zip(amps['c128'], amps['c64'])]
+    out['c64_vs_c128_max_fidelity_deficit'] = float(np.max(fids))
+    # plain path: one circuit at a time, one kernel per gate, complex128
+    regs = [q.Register(env, n, q.STATEVEC, q.C128) for n in sizes]
+    circs = [q.Circuit(o) for o in ops]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r, c in zip(regs, circs):
+        r.init_zero()
+        c.run(r, 0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out['plain_c128_circuits_per_s'] = len(sizes) / dt
+    log(f'plain c128: {dt:.2f} s per 512 circuits')
+    for c in circs:
+        c.close()
+    for r in regs:
+        r.close()
+    env.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -240,6 +298,11 @@ def main():
     circ.close()
     reg.close()
     env.close()
+    if not args.no_extras:
+        del reg
+        torch.cuda.empty_cache()
+        log('batched registers')
+        out['batched'] = batched_leg(q, torch, log)
     print(json.dumps(out), flush=True)
 
 

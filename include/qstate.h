@@ -43,6 +43,7 @@ extern "C" {
 typedef struct qs_env_s* qs_env;         /* device + profiling state            */
 typedef struct qs_reg_s* qs_reg;         /* one quantum register (Qureg)        */
 typedef struct qs_circuit_s* qs_circuit; /* recorded gate list + fusion plan    */
+typedef struct qs_batch_s* qs_batch;     /* registers run by one launch         */
 
 typedef enum { QS_STATEVEC = 0, QS_DENSITY = 1 } qs_kind;
 typedef enum { QS_C64 = 1, QS_C128 = 2 } qs_prec;
@@ -206,6 +207,34 @@ qs_status qs_circuit_run_compiled(qs_reg r, qs_circuit c, int tile_qubits, int t
 qs_status qs_circuit_source(qs_circuit c, int n, int prec, int tile_qubits, int thread_bits,
                             int max_phases, int contig_qubits, int pass, char* buf, size_t cap,
                             size_t* len, int* n_passes);
+
+/* ---- batches: many independent registers in one persistent launch ------- */
+
+/* Bind `count` state-vector registers to `count` circuits (circuits[i] runs
+ * on regs[i]).  All registers must share one environment and precision and
+ * hold at least 9 qubits.  Every circuit is planned into fused passes of
+ * tiles of min(tile_qubits, smallest register) qubits (9..13 for QS_C128,
+ * 9..14 for QS_C64); one launch then runs every register, each by one
+ * workgroup, largest registers first.  The batch keeps device copies of the
+ * plans; registers and circuits must outlive it, and later changes to the
+ * circuits are not seen.  Work runs on the batch's own stream, ordered after
+ * and before the registers' streams. */
+qs_status qs_batch_create(const qs_reg* regs, const qs_circuit* circuits, int count, int tile_qubits,
+                          qs_batch* out);
+qs_status qs_batch_destroy(qs_batch b);
+/* Run every circuit once; init_zero != 0 first sets each register to |0..0>
+ * inside the same launch.  Asynchronous. */
+qs_status qs_batch_run(qs_batch b, int init_zero);
+/* Record qs_batch_run(b, init_zero) into a HIP graph (replacing any earlier
+ * one); qs_batch_replay launches it.  Asynchronous. */
+qs_status qs_batch_capture(qs_batch b, int init_zero);
+qs_status qs_batch_replay(qs_batch b);
+/* Per register i: p0[i] = P(qubit = 0), total[i] = total probability, in
+ * double precision with compensated sums (either output may be NULL).
+ * `qubit` must be below every register's size.  Synchronous. */
+qs_status qs_batch_probs(qs_batch b, int qubit, double* p0, double* total);
+/* Number of fused passes over all registers (for reporting). */
+qs_status qs_batch_info(qs_batch b, int* n_regs, int* tile_qubits, int* n_passes);
 
 #ifdef __cplusplus
 }

@@ -5,6 +5,6 @@ The compute path is libqstate.so (HIP, C ABI in include/qstate.h); this
 package is its thin Python binding.
 """
 from .qstate import (  # noqa: F401
-    C64, C128, DAMPING, DENSITY, DEPHASING, DEPOLARISING, STATEVEC, Circuit, Env,
+    C64, C128, DAMPING, DENSITY, DEPHASING, DEPOLARISING, STATEVEC, Batch, Circuit, Env,
     QStateError, Register, lib, reg_bytes,
 )

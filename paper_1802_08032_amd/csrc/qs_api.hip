@@ -17,6 +17,7 @@ namespace {
 constexpr uint32_t kEnvMagic = 0x51454e56u;  // "QENV"
 constexpr uint32_t kRegMagic = 0x51524547u;  // "QREG"
 constexpr uint32_t kCircMagic = 0x51435243u; // "QCRC"
+constexpr uint32_t kBatchMagic = 0x51424154u; // "QBAT"
 
 thread_local std::string g_error = "no error";
 
@@ -60,6 +61,7 @@ hipError_t dev_alloc(void** p, size_t bytes)
 bool valid_env(qs_env e) { return e && handle_live(e) && e->magic == kEnvMagic; }
 bool valid_reg(qs_reg r) { return r && handle_live(r) && r->magic == kRegMagic; }
 bool valid_circ(qs_circuit c) { return c && handle_live(c) && c->magic == kCircMagic; }
+bool valid_batch(qs_batch b) { return b && handle_live(b) && b->magic == kBatchMagic; }
 
 #define QS_CHECK_REG(r) \
     if (!valid_reg(r)) return qs::set_error(QS_E_HANDLE, "invalid register handle")
@@ -846,6 +848,197 @@ qs_status qs_circuit_source(qs_circuit c, int n, int prec, int tile_qubits, int 
         memcpy(buf, src.data(), k);
         buf[k] = '\0';
     }
+    return QS_OK;
+}
+
+
+// --- batches -----------------------------------------------------------------
+
+static void batch_free(qs_batch b)
+{
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->dbuf) hipFree(b->dbuf);
+    if (b->dprobs) hipFree(b->dprobs);
+    if (b->hprobs) hipHostFree(b->hprobs);
+    if (b->ev_in) hipEventDestroy(b->ev_in);
+    if (b->ev_out) hipEventDestroy(b->ev_out);
+    if (b->stream) hipStreamDestroy(b->stream);
+    b->magic = 0;
+    delete b;
+}
+
+qs_status qs_batch_create(const qs_reg* regs, const qs_circuit* circuits, int count, int tile_qubits,
+                          qs_batch* out)
+{
+    if (!out || !regs || !circuits || count < 1) return qs::set_error(QS_E_ARG, "empty batch");
+    std::vector<qs_reg> rv;
+    std::vector<const std::vector<OpRec>*> cv;
+    for (int i = 0; i < count; ++i) {
+        qs_status s = circuit_check(regs[i], circuits[i]);
+        if (s) return s;
+        const qs_reg r = regs[i];
+        if (r->kind != QS_STATEVEC) return qs::set_error(QS_E_KIND, "batches hold state vectors");
+        if (r->env != regs[0]->env || r->prec != regs[0]->prec)
+            return qs::set_error(QS_E_ARG, "batched registers must share environment and precision");
+        for (const OpRec& op : circuits[i]->ops)
+            if (op.kind == 3) return qs::set_error(QS_E_KIND, "channels need a density matrix");
+        rv.push_back(r);
+        cv.push_back(&circuits[i]->ops);
+    }
+    if (tile_qubits < 9) return qs::set_error(QS_E_ARG, "tile must hold at least 9 qubits");
+    QS_HIP(hipSetDevice(regs[0]->env->device));
+    qs_batch b = new qs_batch_s();
+    b->magic = kBatchMagic;
+    b->env = regs[0]->env;
+    b->prec = regs[0]->prec;
+    b->count = count;
+    b->regs = rv;
+    b->stream = nullptr;
+    b->ev_in = b->ev_out = nullptr;
+    for (qs_reg r : rv)
+        if (std::find(b->reg_streams.begin(), b->reg_streams.end(), r->stream) == b->reg_streams.end())
+            b->reg_streams.push_back(r->stream);
+    hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+    if (e == hipSuccess) e = dev_alloc((void**)&b->dprobs, 2 * sizeof(double) * count);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b->hprobs, 2 * sizeof(double) * count, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        hipGetLastError();
+        batch_free(b);
+        return qs::hip_error(e, "batch resources");
+    }
+    qs_status s = qs::batch_build(b, rv, cv, tile_qubits);
+    if (s) {
+        batch_free(b);
+        return s;
+    }
+    handle_add(b);
+    *out = b;
+    return QS_OK;
+}
+
+qs_status qs_batch_destroy(qs_batch b)
+{
+    if (!valid_batch(b) || !handle_remove(b)) return qs::set_error(QS_E_HANDLE, "invalid batch handle");
+    hipSetDevice(b->env->device);
+    hipStreamSynchronize(b->stream);
+    batch_free(b);
+    return QS_OK;
+}
+
+// The batch stream waits for the registers' streams; afterwards they wait for it.
+static qs_status batch_enter(qs_batch b)
+{
+    for (hipStream_t s : b->reg_streams) {
+        QS_HIP(hipEventRecord(b->ev_in, s));
+        QS_HIP(hipStreamWaitEvent(b->stream, b->ev_in, 0));
+    }
+    return QS_OK;
+}
+
+static qs_status batch_leave(qs_batch b)
+{
+    QS_HIP(hipEventRecord(b->ev_out, b->stream));
+    for (hipStream_t s : b->reg_streams) QS_HIP(hipStreamWaitEvent(s, b->ev_out, 0));
+    return QS_OK;
+}
+
+static qs_status batch_profiled(qs_batch b, hipError_t (*fn)(qs_batch, int), int arg)
+{
+    qs_env env = b->env;
+    hipEvent_t a = nullptr, c = nullptr;
+    if (env->profile) {
+        QS_HIP(hipEventCreate(&a));
+        QS_HIP(hipEventCreate(&c));
+        QS_HIP(hipEventRecord(a, b->stream));
+    }
+    const hipError_t e = fn(b, arg);
+    if (env->profile) {
+        QS_HIP(hipEventRecord(c, b->stream));
+        std::lock_guard<std::mutex> g(env->mu);
+        env->recs.push_back({QS_K_FUSED, a, c});
+    }
+    if (e != hipSuccess) return qs::hip_error(e, "batch launch");
+    return QS_OK;
+}
+
+qs_status qs_batch_run(qs_batch b, int init_zero)
+{
+    if (!valid_batch(b)) return qs::set_error(QS_E_HANDLE, "invalid batch handle");
+    QS_HIP(hipSetDevice(b->env->device));
+    qs_status s = batch_enter(b);
+    if (s) return s;
+    s = batch_profiled(b, [](qs_batch bb, int init) { return qs::batch_launch(bb, init); }, init_zero ? 1 : 0);
+    if (s) return s;
+    return batch_leave(b);
+}
+
+qs_status qs_batch_capture(qs_batch b, int init_zero)
+{
+    if (!valid_batch(b)) return qs::set_error(QS_E_HANDLE, "invalid batch handle");
+    QS_HIP(hipSetDevice(b->env->device));
+    QS_HIP(hipStreamSynchronize(b->stream));
+    if (b->exec) {
+        hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    QS_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    const hipError_t le = qs::batch_launch(b, init_zero ? 1 : 0);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(b->stream, &g);
+    if (le != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return qs::hip_error(le, "batch launch under capture");
+    }
+    if (ce != hipSuccess) return qs::hip_error(ce, "hipStreamEndCapture");
+    b->graph = g;
+    QS_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return QS_OK;
+}
+
+qs_status qs_batch_replay(qs_batch b)
+{
+    if (!valid_batch(b)) return qs::set_error(QS_E_HANDLE, "invalid batch handle");
+    if (!b->exec) return qs::set_error(QS_E_ARG, "nothing captured");
+    QS_HIP(hipSetDevice(b->env->device));
+    qs_status s = batch_enter(b);
+    if (s) return s;
+    s = batch_profiled(b, [](qs_batch bb, int) { return hipGraphLaunch(bb->exec, bb->stream); }, 0);
+    if (s) return s;
+    return batch_leave(b);
+}
+
+qs_status qs_batch_probs(qs_batch b, int qubit, double* p0, double* total)
+{
+    if (!valid_batch(b)) return qs::set_error(QS_E_HANDLE, "invalid batch handle");
+    for (qs_reg r : b->regs)
+        if (qubit < 0 || qubit >= r->n) return qs::set_error(QS_E_ARG, "qubit outside a batched register");
+    QS_HIP(hipSetDevice(b->env->device));
+    qs_status s = batch_enter(b);
+    if (s) return s;
+    s = batch_profiled(b, [](qs_batch bb, int q) { return qs::batch_probs_launch(bb, q, bb->dprobs); }, qubit);
+    if (s) return s;
+    QS_HIP(hipMemcpyAsync(b->hprobs, b->dprobs, 2 * sizeof(double) * b->count, hipMemcpyDeviceToHost, b->stream));
+    QS_HIP(hipStreamSynchronize(b->stream));
+    for (int i = 0; i < b->count; ++i) {
+        if (p0) p0[i] = b->hprobs[2 * i];
+        if (total) total[i] = b->hprobs[2 * i + 1];
+    }
+    return batch_leave(b);
+}
+
+qs_status qs_batch_info(qs_batch b, int* n_regs, int* tile_qubits, int* n_passes)
+{
+    if (!valid_batch(b)) return qs::set_error(QS_E_HANDLE, "invalid batch handle");
+    if (n_regs) *n_regs = b->count;
+    if (tile_qubits) *tile_qubits = b->TB + b->RB;
+    if (n_passes) *n_passes = b->passes_total;
     return QS_OK;
 }
 

@@ -235,35 +235,134 @@ __device__ __forceinline__ void relayout(typename C2<T>::type (&v)[1 << RB],
     __syncthreads();
 }
 
+// One tile of a planned pass: load, apply every phase's ops with the
+// re-layouts between them, store.  `base` = tile index with zeros at the
+// tile's qubits.
+template <typename T, int TB, int RB>
+__device__ __forceinline__ void process_tile(typename C2<T>::type* __restrict__ amp, const FPass* __restrict__ P,
+                                             const FOp* __restrict__ ops, uint64_t tile,
+                                             typename C2<T>::type* lds, uint32_t tid)
+{
+    using V = typename C2<T>::type;
+    constexpr int E = 1 << RB;
+    const uint64_t ld_t = span_sum<TB, uint64_t>(tid, P->ld_thr);
+    const uint64_t st_t = span_sum<TB, uint64_t>(tid, P->st_thr);
+    const int nph = P->nphases;
+    const uint64_t base = expand(tile, P->outside);
+    V v[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) v[r] = amp[base + ld_t + span_sum<RB, uint64_t>((uint32_t)r, P->ld_reg)];
+    for (int ph = 0; ph < nph; ++ph) {
+        const FPhase& F = P->ph[ph];
+        if (ph > 0) relayout<T, TB, RB>(v, lds, F, tid);
+        for (int o = F.op_begin; o < F.op_end; ++o) {
+            const FOp& op = ops[o];
+            if ((base & op.gmask) != op.gmask) continue;  // same for the whole tile
+            apply_op<T, RB>(v, op, tid);
+        }
+    }
+    if (P->final_transpose) relayout<T, TB, RB>(v, lds, P->fin, tid);
+#pragma unroll
+    for (int r = 0; r < E; ++r) amp[base + st_t + span_sum<RB, uint64_t>((uint32_t)r, P->st_reg)] = v[r];
+}
+
 template <typename T, int TB, int RB>
 __global__ __launch_bounds__(1 << TB) void k_fused(typename C2<T>::type* __restrict__ amp,
                                                    const FPass* __restrict__ P,
                                                    const FOp* __restrict__ ops, uint64_t ntiles)
 {
     using V = typename C2<T>::type;
-    constexpr int E = 1 << RB;
     __shared__ V lds[1 << (TB + RB)];
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+        process_tile<T, TB, RB>(amp, P, ops, tile, lds, threadIdx.x);
+}
+
+// Batched registers: each workgroup runs whole registers (in the given
+// order, largest first), every planned pass over all of the register's
+// tiles; a workgroup barrier separates passes, so no other workgroup is
+// involved.  With `init` set, the register is first set to |0..0>.
+struct BatchReg {
+    void* amp;
+    int n;
+    int npasses;
+    uint32_t pass0;  // first pass in the pass array
+    uint32_t pad;
+};
+
+template <typename T, int TB, int RB>
+__global__ __launch_bounds__(1 << TB) void k_batch(const BatchReg* __restrict__ regs,
+                                                   const uint32_t* __restrict__ order, int nregs,
+                                                   const FPass* __restrict__ passes,
+                                                   const FOp* __restrict__ ops, int init)
+{
+    using V = typename C2<T>::type;
+    constexpr int K = TB + RB;
+    __shared__ V lds[1 << K];
     const uint32_t tid = threadIdx.x;
-    const uint64_t ld_t = span_sum<TB, uint64_t>(tid, P->ld_thr);
-    const uint64_t st_t = span_sum<TB, uint64_t>(tid, P->st_thr);
-    const int nph = P->nphases;
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint64_t base = expand(tile, P->outside);
-        V v[E];
-#pragma unroll
-        for (int r = 0; r < E; ++r) v[r] = amp[base + ld_t + span_sum<RB, uint64_t>((uint32_t)r, P->ld_reg)];
-        for (int ph = 0; ph < nph; ++ph) {
-            const FPhase& F = P->ph[ph];
-            if (ph > 0) relayout<T, TB, RB>(v, lds, F, tid);
-            for (int o = F.op_begin; o < F.op_end; ++o) {
-                const FOp& op = ops[o];
-                if ((base & op.gmask) != op.gmask) continue;  // same for the whole tile
-                apply_op<T, RB>(v, op, tid);
+    for (int i = blockIdx.x; i < nregs; i += gridDim.x) {
+        const BatchReg R = regs[order[i]];
+        V* amp = (V*)R.amp;
+        const uint64_t len = 1ull << R.n;
+        if (init) {
+            for (uint64_t e = tid; e < len; e += (1u << TB)) {
+                V z;
+                z.x = (e == 0) ? T(1) : T(0);
+                z.y = T(0);
+                amp[e] = z;
             }
+            __syncthreads();
         }
-        if (P->final_transpose) relayout<T, TB, RB>(v, lds, P->fin, tid);
+        const uint64_t ntiles = len >> K;
+        for (int p = 0; p < R.npasses; ++p) {
+            const FPass* P = passes + R.pass0 + p;
+            for (uint64_t tile = 0; tile < ntiles; ++tile) process_tile<T, TB, RB>(amp, P, ops, tile, lds, tid);
+            __syncthreads();  // the next pass reads amplitudes this pass wrote
+        }
+    }
+}
+
+// Per-register probabilities: out[2 i] = P(qubit q = 0), out[2 i + 1] =
+// total probability, both as compensated double sums.
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_probs(const BatchReg* __restrict__ regs, int nregs, int q,
+                                                     double* __restrict__ out)
+{
+    using V = typename C2<T>::type;
+    __shared__ double sh[4][4];
+    for (int i = blockIdx.x; i < nregs; i += gridDim.x) {
+        const BatchReg R = regs[i];
+        const V* amp = (const V*)R.amp;
+        const uint64_t len = 1ull << R.n;
+        NSum s0 = {0.0, 0.0}, st = {0.0, 0.0};
+        for (uint64_t e = threadIdx.x; e < len; e += 256) {
+            const V a = amp[e];
+            const double p = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+            nadd(s0, ((e >> q) & 1) ? 0.0 : p);
+            nadd(st, p);
+        }
 #pragma unroll
-        for (int r = 0; r < E; ++r) amp[base + st_t + span_sum<RB, uint64_t>((uint32_t)r, P->st_reg)] = v[r];
+        for (int off = 32; off >= 1; off >>= 1) {
+            s0 = nmerge(s0, NSum{__shfl_xor(s0.s, off, 64), __shfl_xor(s0.c, off, 64)});
+            st = nmerge(st, NSum{__shfl_xor(st.s, off, 64), __shfl_xor(st.c, off, 64)});
+        }
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            sh[0][w] = s0.s;
+            sh[1][w] = s0.c;
+            sh[2][w] = st.s;
+            sh[3][w] = st.c;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            NSum a = {sh[0][0], sh[1][0]}, b = {sh[2][0], sh[3][0]};
+            for (int k = 1; k < 4; ++k) {
+                a = nmerge(a, NSum{sh[0][k], sh[1][k]});
+                b = nmerge(b, NSum{sh[2][k], sh[3][k]});
+            }
+            out[2 * i] = a.s + a.c;
+            out[2 * i + 1] = b.s + b.c;
+        }
+        __syncthreads();
     }
 }
 
@@ -318,6 +417,43 @@ FOp encode_op(const OpRec& op, const PassPlan& P, const Layout& L)
     if (op.kind == 0)
         for (int k = 0; k < 8; ++k) f.m[k] = op.u[k];
     return f;
+}
+
+// Device form of a planned pass list, appended to hp / hops (op indices in
+// the phases are positions in hops).
+void serialize(const std::vector<PassPlan>& plan, const std::vector<OpRec>& ops, int TB, int RB,
+               std::vector<FPass>& hp, std::vector<FOp>& hops)
+{
+    const int K = TB + RB;
+    for (size_t p = 0; p < plan.size(); ++p) {
+        const PassPlan& P = plan[p];
+        FPass F;
+        memset(&F, 0, sizeof(F));
+        F.nphases = (int)P.phases.size();
+        F.outside = make_insert(P.S.data(), (int)P.S.size(), 0);
+        const Layout& L0 = P.phases.front().lay;
+        for (int b = 0; b < TB; ++b) {
+            F.ld_thr[b] = 1ull << P.S[L0.thr[b]];
+            F.st_thr[b] = 1ull << P.S[P.store.thr[b]];
+        }
+        for (int b = 0; b < RB; ++b) {
+            F.ld_reg[b] = 1ull << P.S[L0.reg[b]];
+            F.st_reg[b] = 1ull << P.S[P.store.reg[b]];
+        }
+        for (size_t ph = 0; ph < P.phases.size(); ++ph) {
+            FPhase& Fp = F.ph[ph];
+            const Layout& prev = ph ? P.phases[ph - 1].lay : P.phases[ph].lay;
+            fill_phase(Fp, prev, P.phases[ph].lay, K);
+            Fp.op_begin = (int)hops.size();
+            for (int idx : P.phases[ph].ops) hops.push_back(encode_op(ops[idx], P, P.phases[ph].lay));
+            Fp.op_end = (int)hops.size();
+        }
+        const Layout& last = P.phases.back().lay;
+        F.final_transpose = (last.reg == P.store.reg && last.thr == P.store.thr) ? 0 : 1;
+        fill_phase(F.fin, last, P.store, K);
+        F.fin.op_begin = F.fin.op_end = 0;
+        hp.push_back(F);
+    }
 }
 
 // Tile shapes compiled in: (thread bits, register bits).  LDS holds the
@@ -396,36 +532,9 @@ qs_status run_fused_sv(qs_reg r, const std::vector<OpRec>& ops, FusedConfig cfg,
     std::vector<PassPlan> plan = plan_passes(ops, r->n, TB, RB, cfg.max_phases, 1 << 12, 6);
 
     // serialise passes + ops
-    std::vector<FPass> hp(plan.size());
+    std::vector<FPass> hp;
     std::vector<FOp> hops;
-    for (size_t p = 0; p < plan.size(); ++p) {
-        const PassPlan& P = plan[p];
-        FPass& F = hp[p];
-        memset(&F, 0, sizeof(F));
-        F.nphases = (int)P.phases.size();
-        F.outside = make_insert(P.S.data(), (int)P.S.size(), 0);
-        const Layout& L0 = P.phases.front().lay;
-        for (int b = 0; b < TB; ++b) {
-            F.ld_thr[b] = 1ull << P.S[L0.thr[b]];
-            F.st_thr[b] = 1ull << P.S[P.store.thr[b]];
-        }
-        for (int b = 0; b < RB; ++b) {
-            F.ld_reg[b] = 1ull << P.S[L0.reg[b]];
-            F.st_reg[b] = 1ull << P.S[P.store.reg[b]];
-        }
-        for (size_t ph = 0; ph < P.phases.size(); ++ph) {
-            FPhase& Fp = F.ph[ph];
-            const Layout& prev = ph ? P.phases[ph - 1].lay : P.phases[ph].lay;
-            fill_phase(Fp, prev, P.phases[ph].lay, K);
-            Fp.op_begin = (int)hops.size();
-            for (int idx : P.phases[ph].ops) hops.push_back(encode_op(ops[idx], P, P.phases[ph].lay));
-            Fp.op_end = (int)hops.size();
-        }
-        const Layout& last = P.phases.back().lay;
-        F.final_transpose = (last.reg == P.store.reg && last.thr == P.store.thr) ? 0 : 1;
-        fill_phase(F.fin, last, P.store, K);
-        F.fin.op_begin = F.fin.op_end = 0;
-    }
+    serialize(plan, ops, TB, RB, hp, hops);
     if (hops.empty()) hops.push_back(FOp{});
 
     const size_t pbytes = hp.size() * sizeof(FPass), obytes = hops.size() * sizeof(FOp);
@@ -457,6 +566,124 @@ qs_status run_fused_sv(qs_reg r, const std::vector<OpRec>& ops, FusedConfig cfg,
     if (e != hipSuccess) return hip_error(e, "fused passes");
     if (passes_out) *passes_out = (int)hp.size();
     return QS_OK;
+}
+
+// ===========================================================================
+// Batched registers (one persistent launch)
+
+namespace {
+
+template <typename T, int TB, int RB>
+hipError_t batch_launch_t(qs_batch_s* b, int init)
+{
+    const char* base = (const char*)b->dbuf;
+    hipLaunchKernelGGL((k_batch<T, TB, RB>), dim3(b->grid), dim3(1 << TB), 0, b->stream,
+                       (const BatchReg*)(base + b->off_regs), (const uint32_t*)(base + b->off_order), b->count,
+                       (const FPass*)(base + b->off_passes), (const FOp*)(base + b->off_ops), init);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t batch_launch_p(qs_batch_s* b, int init)
+{
+#define QS_B(tb, rb) \
+    if (b->TB == tb && b->RB == rb) return batch_launch_t<T, tb, rb>(b, init);
+    QS_B(6, 3) QS_B(7, 3) QS_B(8, 3) QS_B(8, 4) QS_B(9, 3) QS_B(8, 5) QS_B(9, 4) QS_B(10, 3)
+    if constexpr (sizeof(T) == 4) {
+        QS_B(9, 5) QS_B(10, 4)
+    }
+#undef QS_B
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int TB, int RB>
+int batch_occupancy()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<T, TB, RB>, 1 << TB, 0) != hipSuccess) nb = 1;
+    return nb < 1 ? 1 : nb;
+}
+
+template <typename T>
+int batch_occupancy_p(int TB, int RB)
+{
+#define QS_O(tb, rb) \
+    if (TB == tb && RB == rb) return batch_occupancy<T, tb, rb>();
+    QS_O(6, 3) QS_O(7, 3) QS_O(8, 3) QS_O(8, 4) QS_O(9, 3) QS_O(8, 5) QS_O(9, 4) QS_O(10, 3)
+    if constexpr (sizeof(T) == 4) {
+        QS_O(9, 5) QS_O(10, 4)
+    }
+#undef QS_O
+    return 1;
+}
+
+}  // namespace
+
+qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
+                      const std::vector<const std::vector<OpRec>*>& circs, int K)
+{
+    int nmin = 64;
+    for (qs_reg r : regs) nmin = std::min(nmin, r->n);
+    const FusedConfig cfg = default_fused_config(b->prec, K, nmin);
+    if (cfg.TB == 0 || cfg.TB + cfg.RB > nmin)
+        return set_error(QS_E_ARG, "batched registers need at least 9 qubits and a tile no wider than the smallest");
+    b->TB = cfg.TB;
+    b->RB = cfg.RB;
+    std::vector<FPass> hp;
+    std::vector<FOp> hops;
+    std::vector<BatchReg> hr(regs.size());
+    const int contig = std::min(4, cfg.TB);
+    for (size_t i = 0; i < regs.size(); ++i) {
+        std::vector<PassPlan> plan = plan_passes(*circs[i], regs[i]->n, cfg.TB, cfg.RB, kPhMax, 1 << 12, contig);
+        hr[i].amp = regs[i]->amp;
+        hr[i].n = regs[i]->n;
+        hr[i].pass0 = (uint32_t)hp.size();
+        hr[i].npasses = (int)plan.size();
+        hr[i].pad = 0;
+        serialize(plan, *circs[i], cfg.TB, cfg.RB, hp, hops);
+    }
+    if (hp.empty()) hp.push_back(FPass{});
+    if (hops.empty()) hops.push_back(FOp{});
+    // largest registers first so the longest work starts earliest
+    std::vector<uint32_t> order(regs.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (uint32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t c) { return hr[a].n > hr[c].n; });
+    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    b->off_regs = 0;
+    b->off_order = align(hr.size() * sizeof(BatchReg));
+    b->off_passes = align(b->off_order + order.size() * sizeof(uint32_t));
+    b->off_ops = align(b->off_passes + hp.size() * sizeof(FPass));
+    const size_t total = align(b->off_ops + hops.size() * sizeof(FOp));
+    std::vector<char> host(total, 0);
+    memcpy(host.data() + b->off_regs, hr.data(), hr.size() * sizeof(BatchReg));
+    memcpy(host.data() + b->off_order, order.data(), order.size() * sizeof(uint32_t));
+    memcpy(host.data() + b->off_passes, hp.data(), hp.size() * sizeof(FPass));
+    memcpy(host.data() + b->off_ops, hops.data(), hops.size() * sizeof(FOp));
+    hipError_t e = hipMalloc(&b->dbuf, total);
+    if (e != hipSuccess) return hip_error(e, "batch plan buffer");
+    e = hipMemcpy(b->dbuf, host.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_error(e, "batch plan upload");
+    const int per_cu = b->prec == QS_C128 ? batch_occupancy_p<double>(cfg.TB, cfg.RB)
+                                          : batch_occupancy_p<float>(cfg.TB, cfg.RB);
+    b->grid = (int)std::min<long>((long)regs.size(), 256L * per_cu);
+    b->passes_total = (int)(hp.size());
+    return QS_OK;
+}
+
+hipError_t batch_launch(qs_batch_s* b, int init)
+{
+    return b->prec == QS_C128 ? batch_launch_p<double>(b, init) : batch_launch_p<float>(b, init);
+}
+
+hipError_t batch_probs_launch(qs_batch_s* b, int q, double* dev_out)
+{
+    const BatchReg* regs = (const BatchReg*)((const char*)b->dbuf + b->off_regs);
+    const int grid = std::min(b->count, 2048);
+    if (b->prec == QS_C128)
+        hipLaunchKernelGGL(k_batch_probs<double>, dim3(grid), dim3(256), 0, b->stream, regs, b->count, q, dev_out);
+    else
+        hipLaunchKernelGGL(k_batch_probs<float>, dim3(grid), dim3(256), 0, b->stream, regs, b->count, q, dev_out);
+    return hipGetLastError();
 }
 
 }  // namespace qs

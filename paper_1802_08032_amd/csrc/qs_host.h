@@ -62,6 +62,27 @@ struct qs_circuit_s {
     qs::JitPlan* jit = nullptr;  // cached run-time compiled form (qs_jit.hip)
 };
 
+// A batch of registers run together by one persistent launch (qs_fused.hip).
+struct qs_batch_s {
+    uint32_t magic;
+    qs_env env;
+    int prec;
+    int TB, RB;
+    int count;
+    int grid;
+    int passes_total;
+    hipStream_t stream;            // the batch's own stream (capturable)
+    std::vector<qs_reg> regs;
+    std::vector<hipStream_t> reg_streams;  // distinct streams of the registers
+    hipEvent_t ev_in, ev_out;
+    void* dbuf = nullptr;          // BatchReg[] + order[] + FPass[] + FOp[]
+    size_t off_regs, off_order, off_passes, off_ops;
+    double* dprobs = nullptr;      // 2 doubles per register
+    double* hprobs = nullptr;      // pinned copy
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 namespace qs {
 
 qs_status set_error(qs_status s, const std::string& msg);
@@ -100,6 +121,11 @@ struct FusedConfig {
 bool fused_shape_supported(int prec, int TB, int RB);
 FusedConfig default_fused_config(int prec, int k, int n);
 qs_status run_fused_sv(qs_reg r, const std::vector<OpRec>& ops, FusedConfig cfg, int* passes);
+// Batched registers (qs_fused.hip).
+qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
+                      const std::vector<const std::vector<OpRec>*>& circs, int K);
+hipError_t batch_launch(qs_batch_s* b, int init);
+hipError_t batch_probs_launch(qs_batch_s* b, int q, double* dev_out);
 // Run-time compiled passes (qs_jit.hip).
 qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passes);
 qs_status generate_sources(const std::vector<OpRec>& ops, int n, int prec, FusedConfig cfg,

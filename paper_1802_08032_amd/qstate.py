@@ -82,6 +82,13 @@ SIGNATURES = {
     'qs_circuit_run_tiled': (_i, [_vp, _vp, _i, _i, _i, _PI]),
     'qs_circuit_run_compiled': (_i, [_vp, _vp, _i, _i, _i, _i, _PI]),
     'qs_circuit_source': (_i, [_vp, _i, _i, _i, _i, _i, _i, _i, C.c_char_p, _sz, C.POINTER(_sz), _PI]),
+    'qs_batch_create': (_i, [_vp, _vp, _i, _i, C.POINTER(_vp)]),
+    'qs_batch_destroy': (_i, [_vp]),
+    'qs_batch_run': (_i, [_vp, _i]),
+    'qs_batch_capture': (_i, [_vp, _i]),
+    'qs_batch_replay': (_i, [_vp]),
+    'qs_batch_probs': (_i, [_vp, _i, _vp, _vp]),
+    'qs_batch_info': (_i, [_vp, _PI, _PI, _PI]),
 }
 
 
@@ -335,4 +342,47 @@ class Circuit:
     def close(self):
         if self.h:
             _check(lib().qs_circuit_destroy(self.h))
+            self.h = None
+
+
+class Batch:
+    """Many state-vector registers, each with its own circuit, run by one
+    persistent launch (optionally replayed from a captured HIP graph)."""
+
+    def __init__(self, regs, circuits, tile_qubits: int = 10):
+        if len(regs) != len(circuits) or not regs:
+            raise ValueError('one circuit per register')
+        rh = (C.c_void_p * len(regs))(*[r.h.value for r in regs])
+        ch = (C.c_void_p * len(circuits))(*[c.h.value for c in circuits])
+        h = C.c_void_p()
+        _check(lib().qs_batch_create(rh, ch, len(regs), tile_qubits, C.byref(h)))
+        self.h = h
+        self.regs = list(regs)
+        self.circuits = list(circuits)
+
+    def run(self, init_zero: bool = True):
+        _check(lib().qs_batch_run(self.h, int(init_zero)))
+
+    def capture(self, init_zero: bool = True):
+        _check(lib().qs_batch_capture(self.h, int(init_zero)))
+
+    def replay(self):
+        _check(lib().qs_batch_replay(self.h))
+
+    def probs(self, qubit: int = 0):
+        """(P(qubit = 0), total probability) per register, as numpy arrays."""
+        n = len(self.regs)
+        p0 = np.empty(n)
+        tot = np.empty(n)
+        _check(lib().qs_batch_probs(self.h, qubit, p0.ctypes.data_as(C.c_void_p), tot.ctypes.data_as(C.c_void_p)))
+        return p0, tot
+
+    def info(self):
+        a, b, c = C.c_int(), C.c_int(), C.c_int()
+        _check(lib().qs_batch_info(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return {'registers': a.value, 'tile_qubits': b.value, 'passes': c.value}
+
+    def close(self):
+        if self.h:
+            _check(lib().qs_batch_destroy(self.h))
             self.h = None

@@ -1,0 +1,142 @@
+"""Batched registers: many independent state vectors of uneven size, each
+with its own circuit, run by one persistent launch and replayed from a HIP
+graph; every register against the oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+from tests.gpu_util import fidelity_deficit, log, max_abs
+from workloads import param_circuit, random_gate_ops
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope='module')
+def q():
+    import paper_1802_08032_amd as q
+    return q
+
+
+@pytest.fixture(scope='module')
+def env(q):
+    e = q.Env(0)
+    yield e
+    e.close()
+
+
+def make_batch(q, env, sizes, prec, depth, seed0, tile):
+    regs = [q.Register(env, n, q.STATEVEC, prec) for n in sizes]
+    ops = [param_circuit(n, depth, seed0 + i) + random_gate_ops(n, 20, seed0 + 500 + i, max_controls=2)
+           for i, n in enumerate(sizes)]
+    circs = [q.Circuit(o) for o in ops]
+    b = q.Batch(regs, circs, tile)
+    return regs, ops, circs, b
+
+
+def close_all(b, regs, circs):
+    b.close()
+    for c in circs:
+        c.close()
+    for r in regs:
+        r.close()
+
+
+@pytest.mark.parametrize('tile', [9, 10, 12])
+def test_batch_c128_matches_oracle(q, env, tile):
+    rng = np.random.default_rng(tile)
+    sizes = [int(v) for v in rng.integers(max(tile, 9), 15, 20)]
+    regs, ops, circs, b = make_batch(q, env, sizes, q.C128, 3, 100, tile)
+    log(f'batch c128 tile={tile} sizes={sizes}')
+    b.run(init_zero=True)
+    p0, tot = b.probs(0)
+    for i, n in enumerate(sizes):
+        ref = O.run_sv(n, ops[i])
+        assert max_abs(regs[i].get_amps(), ref) <= 1e-12, (i, n)
+        assert abs(p0[i] - O.sv_prob_outcome(ref, n, 0, 0)) <= 1e-12
+        assert abs(tot[i] - 1.0) <= 1e-12
+    close_all(b, regs, circs)
+
+
+def test_batch_c64_fidelity(q, env):
+    sizes = [9, 10, 11, 12, 13, 14, 15, 16, 10, 12]
+    regs, ops, circs, b = make_batch(q, env, sizes, q.C64, 4, 7, 10)
+    b.run(init_zero=True)
+    for i, n in enumerate(sizes):
+        assert fidelity_deficit(O.run_sv(n, ops[i]), regs[i].get_amps()) <= 1e-5, (i, n)
+    close_all(b, regs, circs)
+
+
+def test_graph_replay_matches_eager(q, env):
+    """Replays of the captured launch, with eager work in between, give the
+    eager result every time."""
+    sizes = [9, 11, 13, 10, 12, 14]
+    regs, ops, circs, b = make_batch(q, env, sizes, q.C128, 3, 40, 9)
+    b.run(init_zero=True)
+    eager = [r.get_amps() for r in regs]
+    b.capture(init_zero=True)
+    for rep in range(3):
+        for r in regs:  # eager work on the registers between replays
+            r.unitary(0, np.eye(2))
+            r.calc_total_prob()
+        b.replay()
+        for i, r in enumerate(regs):
+            assert max_abs(r.get_amps(), eager[i]) == 0.0, (rep, i)
+    close_all(b, regs, circs)
+
+
+def test_batch_rejects_bad_input(q, env):
+    r8 = q.Register(env, 8)
+    r12 = q.Register(env, 12, q.STATEVEC, q.C64)
+    r10 = q.Register(env, 10)
+    c = q.Circuit(param_circuit(8, 1, 0))
+    c10 = q.Circuit(param_circuit(10, 1, 0))
+    with pytest.raises(q.QStateError):      # below 9 qubits
+        q.Batch([r8], [c], 9)
+    with pytest.raises(q.QStateError):      # mixed precision
+        q.Batch([r10, r12], [c10, c10], 9)
+    with pytest.raises(q.QStateError):      # circuit wider than the register
+        q.Batch([r10], [q.Circuit(param_circuit(12, 1, 0))], 9)
+    for x in (c, c10):
+        x.close()
+    for r in (r8, r12, r10):
+        r.close()
+
+
+@pytest.mark.parametrize('prec_name', ['C128', 'C64'])
+def test_c3_workload_512_registers(q, env, prec_name):
+    """512 registers of 10..20 qubits (uniform, seed 3), depth-16 RY/RZ + CZ
+    ladder circuits (register i: seed 1000 + i).  Registers up to 13 qubits
+    are compared with the oracle amplitude by amplitude, every register's
+    P(q0 = 0) with the oracle's for the small ones and its total probability
+    with 1 for all."""
+    prec = getattr(q, prec_name)
+    rng = np.random.Generator(np.random.PCG64(3))
+    sizes = [int(v) for v in rng.integers(10, 21, 512)]
+    regs = [q.Register(env, n, q.STATEVEC, prec) for n in sizes]
+    ops = [param_circuit(n, 16, 1000 + i) for i, n in enumerate(sizes)]
+    circs = [q.Circuit(o) for o in ops]
+    log(f'c3 {prec_name}: 512 registers')
+    b = q.Batch(regs, circs, 10)
+    b.capture(init_zero=True)
+    b.replay()
+    p0, tot = b.probs(0)
+    tol_tot = 1e-12 if prec == q.C128 else 1e-5
+    assert np.max(np.abs(tot - 1.0)) <= tol_tot
+    checked = 0
+    for i, n in enumerate(sizes):
+        if n > 13:
+            continue
+        ref = O.run_sv(n, ops[i])
+        got = regs[i].get_amps()
+        if prec == q.C128:
+            assert max_abs(got, ref) <= 1e-12, (i, n)
+            assert abs(p0[i] - O.sv_prob_outcome(ref, n, 0, 0)) <= 1e-12
+        else:
+            assert fidelity_deficit(ref, got) <= 1e-5, (i, n)
+        checked += 1
+    assert checked > 100
+    b.close()
+    for c in circs:
+        c.close()
+    for r in regs:
+        r.close()
