@@ -172,10 +172,12 @@ qs_status qs_circuit_add_channel(qs_circuit c, int channel, int target, double p
 qs_status qs_circuit_size(qs_circuit c, int* n_ops);
 /* Apply the circuit to `r`.  fusion_qubits = 0 launches one kernel per
  * operation (the one-pass-per-gate method of Sec. II.B.1).  fusion_qubits
- * = k > 0 groups consecutive gates whose qubits fit in a set of at most k
+ * = k > 0 groups consecutive gates whose targets fit in a set of at most k
  * qubits and applies each group in one read and one write of the state
- * (gate fusion, Sec. II.B).  *n_passes (may be NULL) receives the number
- * of full-state kernel passes launched. */
+ * (gate fusion, Sec. II.B); density matrices use the run-time compiled
+ * passes on their 2N-qubit vector (see qs_circuit_run_compiled), with k
+ * counting vector qubits.  *n_passes (may be NULL) receives the number of
+ * full-state kernel passes launched. */
 qs_status qs_circuit_run(qs_reg r, qs_circuit c, int fusion_qubits, int* n_passes);
 /* Fused run of a state-vector circuit with an explicit tile shape (used by
  * the autotuner): tiles of 2^tile_qubits amplitudes held by 2^thread_bits
@@ -197,14 +199,18 @@ qs_status qs_circuit_run_tiled(qs_reg r, qs_circuit c, int tile_qubits, int thre
  * $HOME/.cache/qstate); the first run of a new structure pays the compile
  * time.  The compiled form is kept with the circuit until ops are added or
  * the register shape or tile changes.  Accepts 6..10 thread bits and 1..5
- * register bits with the tile in 160 KiB of LDS.  State vectors only. */
+ * register bits with the tile in 160 KiB of LDS.  A density matrix runs as
+ * its 2N-qubit vector (Eq. 2): a gate becomes the gate on q and its
+ * conjugate on q + N, a channel a 4x4 superoperator on (q, q + N), and an
+ * uncontrolled gate is merged with the channels that follow it on the same
+ * qubit; tile_qubits then counts vector qubits (at most 2N). */
 qs_status qs_circuit_run_compiled(qs_reg r, qs_circuit c, int tile_qubits, int thread_bits,
                                   int max_phases, int contig_qubits, int* n_passes);
 /* Host-only: the generated HIP source of pass `pass` for an n-qubit
- * register of precision `prec` (copied into buf, NUL-terminated, truncated
- * to cap - 1 bytes; *len gets the full length, *n_passes the pass count).
- * Needs no GPU. */
-qs_status qs_circuit_source(qs_circuit c, int n, int prec, int tile_qubits, int thread_bits,
+ * register of kind `kind` and precision `prec` (copied into buf,
+ * NUL-terminated, truncated to cap - 1 bytes; *len gets the full length,
+ * *n_passes the pass count).  Needs no GPU. */
+qs_status qs_circuit_source(qs_circuit c, int n, int kind, int prec, int tile_qubits, int thread_bits,
                             int max_phases, int contig_qubits, int pass, char* buf, size_t cap,
                             size_t* len, int* n_passes);
 

@@ -775,6 +775,14 @@ qs_status qs_circuit_run(qs_reg r, qs_circuit c, int fusion_qubits, int* n_passe
     if (fusion_qubits < 0) return qs::set_error(QS_E_ARG, "negative fusion width");
     if (fusion_qubits > 0 && r->kind == QS_STATEVEC)
         return qs::run_fused_sv(r, c->ops, qs::default_fused_config(r->prec, fusion_qubits, r->n), n_passes);
+    if (fusion_qubits > 0 && r->kind == QS_DENSITY) {
+        // density matrices fuse through the compiled passes on their 2N-qubit vector
+        qs::FusedConfig cfg = qs::default_fused_config(r->prec, fusion_qubits, r->nbits);
+        if (cfg.TB != 0) {
+            cfg.contig = std::min(4, cfg.TB);
+            return qs::run_compiled_sv(r, c, cfg, n_passes);
+        }
+    }
     return circuit_unfused(r, c, n_passes);
 }
 
@@ -812,33 +820,32 @@ qs_status qs_circuit_run_compiled(qs_reg r, qs_circuit c, int tile_qubits, int t
 {
     qs_status s = circuit_check(r, c);
     if (s) return s;
-    if (r->kind != QS_STATEVEC) return qs::set_error(QS_E_KIND, "compiled runs need a state vector");
-    if ((s = check_compiled_shape(r->prec, r->n, tile_qubits, thread_bits, max_phases, contig_qubits))) return s;
-    for (const OpRec& op : c->ops)
-        if (op.kind == 3) return qs::set_error(QS_E_KIND, "channels need a density matrix");
+    if ((s = check_compiled_shape(r->prec, r->nbits, tile_qubits, thread_bits, max_phases, contig_qubits))) return s;
     qs::FusedConfig cfg{thread_bits, tile_qubits - thread_bits, max_phases};
-    cfg.contig = contig_qubits ? contig_qubits : std::min(6, r->n);
+    cfg.contig = contig_qubits ? contig_qubits : std::min(6, r->nbits);
     return qs::run_compiled_sv(r, c, cfg, n_passes);
 }
 
-qs_status qs_circuit_source(qs_circuit c, int n, int prec, int tile_qubits, int thread_bits, int max_phases,
-                            int contig_qubits, int pass, char* buf, size_t cap, size_t* len, int* n_passes)
+qs_status qs_circuit_source(qs_circuit c, int n, int kind, int prec, int tile_qubits, int thread_bits,
+                            int max_phases, int contig_qubits, int pass, char* buf, size_t cap, size_t* len,
+                            int* n_passes)
 {
     if (!valid_circ(c)) return qs::set_error(QS_E_HANDLE, "invalid circuit handle");
     if (prec != QS_C64 && prec != QS_C128) return qs::set_error(QS_E_ARG, "unknown precision");
-    if (n < 1 || n > 40) return qs::set_error(QS_E_ARG, "invalid qubit count");
-    qs_status s = check_compiled_shape(prec, n, tile_qubits, thread_bits, max_phases, contig_qubits);
+    if (qs_reg_bytes(n, kind, prec) == 0) return qs::set_error(QS_E_ARG, "invalid qubit count or kind");
+    const int nbits = kind == QS_DENSITY ? 2 * n : n;
+    qs_status s = check_compiled_shape(prec, nbits, tile_qubits, thread_bits, max_phases, contig_qubits);
     if (s) return s;
     for (const OpRec& op : c->ops) {
-        if (op.kind == 3) return qs::set_error(QS_E_KIND, "channels need a density matrix");
+        if (op.kind == 3 && kind != QS_DENSITY) return qs::set_error(QS_E_KIND, "channels need a density matrix");
         if (op.kind != 2 && op.target >= n) return qs::set_error(QS_E_ARG, "circuit qubit outside the register");
         for (int q : op.ctrls)
             if (q >= n) return qs::set_error(QS_E_ARG, "circuit qubit outside the register");
     }
     std::vector<std::string> srcs;
     qs::FusedConfig cfg{thread_bits, tile_qubits - thread_bits, max_phases};
-    cfg.contig = contig_qubits ? contig_qubits : std::min(6, n);
-    qs::generate_sources(c->ops, n, prec, cfg, srcs);
+    cfg.contig = contig_qubits ? contig_qubits : std::min(6, nbits);
+    qs::generate_sources(c->ops, n, kind, prec, cfg, srcs);
     if (n_passes) *n_passes = (int)srcs.size();
     if (pass < 0 || pass >= (int)srcs.size()) return qs::set_error(QS_E_ARG, "no such pass");
     const std::string& src = srcs[pass];

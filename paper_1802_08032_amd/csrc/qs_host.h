@@ -42,13 +42,15 @@ struct qs_reg_s {
 
 // One recorded circuit operation.
 struct OpRec {
-    int kind;            // 0 dense, 1 not, 2 phase, 3 channel
+    int kind;            // 0 dense, 1 not, 2 phase, 3 channel, 4 dense 4x4 on (target, target2)
     int target;
     int channel;
-    std::vector<int> ctrls;  // controls (dense/not) or all qubits (phase)
+    std::vector<int> ctrls;  // controls (dense/not/4x4) or all qubits (phase)
     double u[8];
     double angle;
     double p;
+    int target2 = -1;        // kind 4: second target (the high bit of the 4-index)
+    std::vector<double> m4;  // kind 4: row-major 4x4 complex, index = bit(target) + 2 bit(target2)
 };
 
 namespace qs {
@@ -126,9 +128,14 @@ qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
                       const std::vector<const std::vector<OpRec>*>& circs, int K);
 hipError_t batch_launch(qs_batch_s* b, int init);
 hipError_t batch_probs_launch(qs_batch_s* b, int q, double* dev_out);
+// Eq. 2 on the 2N-qubit vector of a density matrix: gates become a gate on
+// q and its conjugate on q+N, channels become 4x4 superoperators on
+// (q, q+N); an uncontrolled gate and the channels that follow it on the same
+// qubit are merged into one 4x4 (qs_plan.hip).
+std::vector<OpRec> dm_vector_ops(const std::vector<OpRec>& ops, int N);
 // Run-time compiled passes (qs_jit.hip).
 qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passes);
-qs_status generate_sources(const std::vector<OpRec>& ops, int n, int prec, FusedConfig cfg,
+qs_status generate_sources(const std::vector<OpRec>& ops, int n, int kind, int prec, FusedConfig cfg,
                            std::vector<std::string>& out);
 // Per-operation execution of one recorded op (qs_api.hip).
 qs_status apply_op(qs_reg r, const OpRec& op);

@@ -22,13 +22,6 @@ struct Mat2 {
     T m[8];
 };
 
-// 4x4 complex matrix acting on the 4-group (rho00, rho10, rho01, rho11) of a
-// density matrix (row bit t, column bit t+N), row-major, interleaved.
-template <typename T>
-struct Mat4 {
-    T m[32];
-};
-
 struct Launch {
     hipStream_t stream;
     int device;
@@ -67,27 +60,5 @@ template <typename T> hipError_t launch_collapse_sv(const Launch& L, void* amp, 
                                                     int outcome, double scale);
 template <typename T> hipError_t launch_collapse_dm(const Launch& L, void* rho, int N, int q,
                                                     int outcome, double scale);
-
-// --- fused tile pass ---------------------------------------------------------
-// One op inside a fused pass, on local (tile) qubit indices.
-struct TileOp {
-    int kind;         // 0 dense, 1 not, 2 phase (diagonal on all-ones of mask)
-    int target;       // local target
-    uint32_t cmask;   // local control mask (dense/not) or phase mask
-    uint32_t pad;
-    double u[8];      // dense matrix (or phase re/im in u[0], u[1])
-};
-
-constexpr int kMaxTileQubits = 14;
-constexpr int kMaxTileOps = 256;
-
-struct TilePlan {
-    int k;                       // tile qubits
-    int qubits[kMaxTileQubits];  // global qubit of local bit j, ascending
-    int nops;
-};
-
-template <typename T> hipError_t launch_fused(const Launch& L, void* amp, int nbits, const TilePlan& plan,
-                                              const TileOp* dev_ops);
 
 }  // namespace qs

@@ -76,6 +76,28 @@ __device__ __forceinline__ void qs_ap(const R (&m)[8], V& a, V& b)
 // LDS-only workgroup barrier: waits for this wave's LDS traffic, not for
 // its outstanding global loads (the prefetch of the next tile).
 #define QS_BAR() asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory")
+// 4x4 complex matrix on (a, b, c, d) = index bit(t1) + 2 bit(t2).
+__device__ __forceinline__ void qs_ap4(const R (&m)[32], V& a, V& b, V& c, V& d)
+{
+    const V x[4] = {a, b, c, d};
+    V y[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        R re = 0, im = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const R mr = m[2 * (4 * i + j)], mi = m[2 * (4 * i + j) + 1];
+            re += mr * x[j].x - mi * x[j].y;
+            im += mr * x[j].y + mi * x[j].x;
+        }
+        y[i].x = re;
+        y[i].y = im;
+    }
+    a = y[0];
+    b = y[1];
+    c = y[2];
+    d = y[3];
+}
 __device__ __forceinline__ void qs_cm(R fr, R fi, V& a)
 {
     V r;
@@ -227,6 +249,31 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
                     s << "            const bool c = " << cond << ";\n            fr = c ? fr : (R)1; fi = c ? fi : (R)0;\n";
                 for (int r = 0; r < E; ++r)
                     if (((uint32_t)r & rmask) == rmask) s << "            qs_cm(fr, fi, " << vn(r) << ");\n";
+                s << "        }\n";
+                continue;
+            }
+            if (op.kind == 4) {  // 4x4 on two register bits
+                int b1 = -1, b2 = -1;
+                for (int k = 0; k < RB; ++k) {
+                    if (L.reg[k] == local[op.target]) b1 = k;
+                    if (L.reg[k] == local[op.target2]) b2 = k;
+                }
+                for (int k = 0; k < 32; ++k) g.mats.push_back(op.m4[k]);
+                s << "        {\n            R m[32];\n";
+                for (int k = 0; k < 32; ++k) s << "            m[" << k << "] = mt[" << off + k << "];\n";
+                if (!cond.empty()) {
+                    s << "            const bool c = " << cond << ";\n";
+                    for (int k = 0; k < 32; ++k) {
+                        const bool diag = (k % 2 == 0) && ((k / 2) % 5 == 0);
+                        s << "            m[" << k << "] = c ? m[" << k << "] : (R)" << (diag ? 1 : 0) << ";\n";
+                    }
+                }
+                for (int r0 = 0; r0 < E; ++r0) {
+                    if (((r0 >> b1) & 1) || ((r0 >> b2) & 1)) continue;
+                    if (((uint32_t)r0 & rmask) != rmask) continue;
+                    s << "            qs_ap4(m, " << vn(r0) << ", " << vn(r0 | (1 << b1)) << ", " << vn(r0 | (1 << b2))
+                      << ", " << vn(r0 | (1 << b1) | (1 << b2)) << ");\n";
+                }
                 s << "        }\n";
                 continue;
             }
@@ -450,12 +497,16 @@ void jit_plan_free(JitPlan* p)
 
 qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passes_out)
 {
-    const std::vector<OpRec>& ops = c->ops;
+    // a density matrix runs as its 2N-qubit vector (Eq. 2)
+    std::vector<OpRec> dm_ops;
+    if (r->kind == QS_DENSITY) dm_ops = dm_vector_ops(c->ops, r->n);
+    const std::vector<OpRec>& ops = r->kind == QS_DENSITY ? dm_ops : c->ops;
+    const int nbits = r->nbits;
     if (cfg.max_phases <= 0 || cfg.max_phases > kPhMax) cfg.max_phases = kPhMax;
     JitPlan* J = c->jit;
-    const bool fresh = !J || J->n != r->n || J->prec != r->prec || J->TB != cfg.TB || J->RB != cfg.RB ||
+    const bool fresh = !J || J->n != nbits || J->prec != r->prec || J->TB != cfg.TB || J->RB != cfg.RB ||
                        J->max_phases != cfg.max_phases || J->contig != cfg.contig || J->device != r->env->device ||
-                       J->nops != ops.size();
+                       J->nops != c->ops.size();
     if (fresh) {
         if (J) {
             hipStreamSynchronize(r->stream);  // kernels of the old plan may still read its matrices
@@ -463,7 +514,7 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
             c->jit = nullptr;
         }
         const bool dbl = r->prec == QS_C128;
-        std::vector<PassPlan> plan = plan_passes(ops, r->n, cfg.TB, cfg.RB, cfg.max_phases, 1 << 12, cfg.contig);
+        std::vector<PassPlan> plan = plan_passes(ops, nbits, cfg.TB, cfg.RB, cfg.max_phases, 1 << 12, cfg.contig);
         std::vector<std::string> srcs;
         std::vector<double> mats;
         std::unique_ptr<JitPlan> nj(new JitPlan());
@@ -496,17 +547,17 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
             nj->dmats = nullptr;
             return hip_error(e, "matrix upload");
         }
-        nj->n = r->n;
+        nj->n = nbits;
         nj->prec = r->prec;
         nj->TB = cfg.TB;
         nj->RB = cfg.RB;
         nj->max_phases = cfg.max_phases;
         nj->contig = cfg.contig;
         nj->device = r->env->device;
-        nj->nops = ops.size();
+        nj->nops = c->ops.size();
         J = c->jit = nj.release();
     }
-    unsigned long long ntiles = 1ull << (r->n - (cfg.TB + cfg.RB));
+    unsigned long long ntiles = 1ull << (nbits - (cfg.TB + cfg.RB));
     for (size_t p = 0; p < J->fns.size(); ++p) {
         void* amp = r->amp;
         const void* mp = (const char*)J->dmats + J->mat_off[p] * esz_of(r->prec);
@@ -523,10 +574,14 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
 }
 
 // Source of the specialised kernels for one circuit (inspection / tests).
-qs_status generate_sources(const std::vector<OpRec>& ops, int n, int prec, FusedConfig cfg,
+qs_status generate_sources(const std::vector<OpRec>& circuit_ops, int n, int kind, int prec, FusedConfig cfg,
                            std::vector<std::string>& out)
 {
     if (cfg.max_phases <= 0 || cfg.max_phases > kPhMax) cfg.max_phases = kPhMax;
+    std::vector<OpRec> dm_ops;
+    if (kind == QS_DENSITY) dm_ops = dm_vector_ops(circuit_ops, n);
+    const std::vector<OpRec>& ops = kind == QS_DENSITY ? dm_ops : circuit_ops;
+    if (kind == QS_DENSITY) n *= 2;
     std::vector<PassPlan> plan = plan_passes(ops, n, cfg.TB, cfg.RB, cfg.max_phases, 1 << 12, cfg.contig);
     out.clear();
     for (const PassPlan& P : plan) out.push_back(generate(P, ops, cfg.TB, cfg.RB, prec == QS_C128).src);

@@ -2,6 +2,8 @@
 // whose targets fit a tile of K qubits, and each pass into register layouts
 // (phases).  Used by the generic fused kernel and by the run-time compiled
 // pass kernels.
+#include <math.h>
+
 #include <algorithm>
 #include <vector>
 
@@ -9,11 +11,18 @@
 
 namespace qs {
 
+uint64_t target_mask(const OpRec& op)
+{
+    if (op.kind == 2) return 0;
+    uint64_t m = 1ull << op.target;
+    if (op.kind == 4) m |= 1ull << op.target2;
+    return m;
+}
+
 uint64_t qubit_mask(const OpRec& op)
 {
-    uint64_t m = 0;
+    uint64_t m = target_mask(op);
     for (int q : op.ctrls) m |= 1ull << q;
-    if (op.kind != 2) m |= 1ull << op.target;
     return m;
 }
 
@@ -67,12 +76,17 @@ void plan_phases(PassPlan& P, const std::vector<OpRec>& all, int TB, int RB, int
     const int K = TB + RB;
     std::vector<int> local(64, -1);
     for (int j = 0; j < K; ++j) local[P.S[j]] = j;
+    auto ltargets = [&](const OpRec& op) -> uint32_t {
+        if (op.kind == 2) return 0;
+        uint32_t m = 1u << local[op.target];
+        if (op.kind == 4) m |= 1u << local[op.target2];
+        return m;
+    };
     auto lmask = [&](const OpRec& op) {
         uint32_t m = 0;
         for (int q : op.ctrls)
             if (local[q] >= 0) m |= 1u << local[q];
-        if (op.kind != 2) m |= 1u << local[op.target];
-        return m;
+        return m | ltargets(op);
     };
     std::vector<int> rem = P.ops;
     std::vector<int> kept;
@@ -80,14 +94,18 @@ void plan_phases(PassPlan& P, const std::vector<OpRec>& all, int TB, int RB, int
     auto preferred = [&](const std::vector<int>& ops_left) {
         std::vector<int> pref;
         uint32_t blocked = 0;
+        auto push_targets = [&](const OpRec& op) {
+            if (op.kind == 2) return;
+            pref.push_back(local[op.target]);
+            if (op.kind == 4) pref.push_back(local[op.target2]);
+        };
         for (int idx : ops_left) {
             const OpRec& op = all[idx];
             const uint32_t m = lmask(op);
-            if (op.kind != 2 && !(m & blocked)) pref.push_back(local[op.target]);
+            if (!(m & blocked)) push_targets(op);
             blocked |= m;
         }
-        for (int idx : ops_left)
-            if (all[idx].kind != 2) pref.push_back(local[all[idx].target]);
+        for (int idx : ops_left) push_targets(all[idx]);
         return pref;
     };
     bool first = true;
@@ -104,7 +122,7 @@ void plan_phases(PassPlan& P, const std::vector<OpRec>& all, int TB, int RB, int
             const OpRec& op = all[idx];
             const uint32_t m = lmask(op);
             const bool ready = !(m & blocked);
-            const bool fits = op.kind == 2 || ((regm >> local[op.target]) & 1);
+            const bool fits = (ltargets(op) & ~regm) == 0;
             if (ready && fits) {
                 ph.ops.push_back(idx);
             } else {
@@ -146,16 +164,11 @@ std::vector<PassPlan> plan_passes(const std::vector<OpRec>& all, int n, int TB, 
                 blocked |= m;
                 continue;
             }
-            if (op.kind == 2) {
-                take.push_back((int)i);
-                continue;
-            }
-            const uint64_t tb = 1ull << op.target;
-            if (S & tb) {
-                take.push_back((int)i);
-            } else if (ssize < K) {
-                S |= tb;
-                ++ssize;
+            const uint64_t need = target_mask(op) & ~S;
+            const int extra = __builtin_popcountll(need);
+            if (ssize + extra <= K) {
+                S |= need;
+                ssize += extra;
                 take.push_back((int)i);
             } else {
                 blocked |= m;
@@ -221,5 +234,131 @@ std::vector<uint32_t> swizzle(const Layout& A, const Layout& B, int K)
     return img;
 }
 
+
+}  // namespace qs
+
+namespace qs {
+namespace {
+
+using Super4 = std::vector<double>;  // 4x4 complex, row-major, re/im interleaved
+
+Super4 mat4_mul(const Super4& A, const Super4& B)  // A * B
+{
+    Super4 C(32, 0.0);
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            double re = 0.0, im = 0.0;
+            for (int k = 0; k < 4; ++k) {
+                const double ar = A[2 * (4 * i + k)], ai = A[2 * (4 * i + k) + 1];
+                const double br = B[2 * (4 * k + j)], bi = B[2 * (4 * k + j) + 1];
+                re += ar * br - ai * bi;
+                im += ar * bi + ai * br;
+            }
+            C[2 * (4 * i + j)] = re;
+            C[2 * (4 * i + j) + 1] = im;
+        }
+    return C;
+}
+
+// conj(U) (x) U on (row bit r, column bit c), index r + 2c:
+// M[r + 2c][r' + 2c'] = U[r][r'] conj(U[c][c']).
+Super4 gate_superop(const double* u)
+{
+    Super4 M(32, 0.0);
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c)
+            for (int r2 = 0; r2 < 2; ++r2)
+                for (int c2 = 0; c2 < 2; ++c2) {
+                    const double ar = u[2 * (2 * r + r2)], ai = u[2 * (2 * r + r2) + 1];
+                    const double br = u[2 * (2 * c + c2)], bi = -u[2 * (2 * c + c2) + 1];
+                    const int i = r + 2 * c, j = r2 + 2 * c2;
+                    M[2 * (4 * i + j)] = ar * br - ai * bi;
+                    M[2 * (4 * i + j) + 1] = ar * bi + ai * br;
+                }
+    return M;
+}
+
+// Channel superoperators on (rho00, rho10, rho01, rho11), the closed forms
+// of the three Kraus maps.
+Super4 channel_superop(int channel, double p)
+{
+    Super4 M(32, 0.0);
+    auto set = [&](int i, int j, double v) { M[2 * (4 * i + j)] = v; };
+    if (channel == QS_DEPHASING) {
+        set(0, 0, 1.0);
+        set(1, 1, 1.0 - 2.0 * p);
+        set(2, 2, 1.0 - 2.0 * p);
+        set(3, 3, 1.0);
+    } else if (channel == QS_DEPOLARISING) {
+        set(0, 0, 1.0 - 2.0 * p / 3.0);
+        set(0, 3, 2.0 * p / 3.0);
+        set(3, 3, 1.0 - 2.0 * p / 3.0);
+        set(3, 0, 2.0 * p / 3.0);
+        set(1, 1, 1.0 - 4.0 * p / 3.0);
+        set(2, 2, 1.0 - 4.0 * p / 3.0);
+    } else {
+        const double s = sqrt(1.0 - p);
+        set(0, 0, 1.0);
+        set(0, 3, p);
+        set(1, 1, s);
+        set(2, 2, s);
+        set(3, 3, 1.0 - p);
+    }
+    return M;
+}
+
+}  // namespace
+
+std::vector<OpRec> dm_vector_ops(const std::vector<OpRec>& ops, int N)
+{
+    std::vector<OpRec> out;
+    auto shifted = [&](const std::vector<int>& qs_) {
+        std::vector<int> r;
+        for (int q : qs_) r.push_back(q + N);
+        return r;
+    };
+    auto push_pair = [&](int t, const Super4& M) {
+        if (!out.empty()) {
+            OpRec& prev = out.back();
+            if (prev.kind == 4 && prev.ctrls.empty() && prev.target == t && prev.target2 == t + N) {
+                prev.m4 = mat4_mul(M, prev.m4);  // M applied after prev
+                return;
+            }
+        }
+        OpRec op{};
+        op.kind = 4;
+        op.target = t;
+        op.target2 = t + N;
+        op.m4 = M;
+        out.push_back(op);
+    };
+    for (const OpRec& op : ops) {
+        if (op.kind == 0 && op.ctrls.empty()) {
+            push_pair(op.target, gate_superop(op.u));
+        } else if (op.kind == 0) {
+            OpRec a = op, b = op;
+            b.target = op.target + N;
+            b.ctrls = shifted(op.ctrls);
+            for (int k = 1; k < 8; k += 2) b.u[k] = -op.u[k];
+            out.push_back(a);
+            out.push_back(b);
+        } else if (op.kind == 1) {
+            OpRec a = op, b = op;
+            b.target = op.target + N;
+            b.ctrls = shifted(op.ctrls);
+            out.push_back(a);
+            out.push_back(b);
+        } else if (op.kind == 2) {
+            OpRec a = op, b = op;
+            b.ctrls = shifted(op.ctrls);
+            b.angle = -op.angle;
+            out.push_back(a);
+            out.push_back(b);
+        } else if (op.kind == 3) {
+            push_pair(op.target, channel_superop(op.channel, op.p));
+        }
+    }
+    return out;
+}
 
 }  // namespace qs

@@ -81,7 +81,7 @@ SIGNATURES = {
     'qs_circuit_run': (_i, [_vp, _vp, _i, _PI]),
     'qs_circuit_run_tiled': (_i, [_vp, _vp, _i, _i, _i, _PI]),
     'qs_circuit_run_compiled': (_i, [_vp, _vp, _i, _i, _i, _i, _PI]),
-    'qs_circuit_source': (_i, [_vp, _i, _i, _i, _i, _i, _i, _i, C.c_char_p, _sz, C.POINTER(_sz), _PI]),
+    'qs_circuit_source': (_i, [_vp, _i, _i, _i, _i, _i, _i, _i, _i, C.c_char_p, _sz, C.POINTER(_sz), _PI]),
     'qs_batch_create': (_i, [_vp, _vp, _i, _i, C.POINTER(_vp)]),
     'qs_batch_destroy': (_i, [_vp]),
     'qs_batch_run': (_i, [_vp, _i]),
@@ -329,14 +329,14 @@ class Circuit:
         return passes.value
 
     def source(self, n: int, prec: int, tile_qubits: int, thread_bits: int, pass_index: int = 0,
-               max_phases: int = 0, contig_qubits: int = 0):
+               max_phases: int = 0, contig_qubits: int = 0, kind: int = STATEVEC):
         """(generated HIP source of one pass, number of passes); host only."""
         ln, npass = C.c_size_t(), C.c_int()
-        _check(lib().qs_circuit_source(self.h, n, prec, tile_qubits, thread_bits, max_phases, contig_qubits,
-                                       pass_index, None, 0, C.byref(ln), C.byref(npass)))
+        _check(lib().qs_circuit_source(self.h, n, kind, prec, tile_qubits, thread_bits, max_phases,
+                                       contig_qubits, pass_index, None, 0, C.byref(ln), C.byref(npass)))
         buf = C.create_string_buffer(ln.value + 1)
-        _check(lib().qs_circuit_source(self.h, n, prec, tile_qubits, thread_bits, max_phases, contig_qubits,
-                                       pass_index, buf, ln.value + 1, C.byref(ln), C.byref(npass)))
+        _check(lib().qs_circuit_source(self.h, n, kind, prec, tile_qubits, thread_bits, max_phases,
+                                       contig_qubits, pass_index, buf, ln.value + 1, C.byref(ln), C.byref(npass)))
         return buf.value.decode(), npass.value
 
     def close(self):

@@ -56,3 +56,15 @@ def test_source_rejects_bad_shapes():
         with pytest.raises(q.QStateError):
             c.source(*args)
     c.close()
+
+
+def test_generated_density_matrix_pass_compiles():
+    """Density matrices: gates on (q, q+N) and 4x4 channel superoperators."""
+    import paper_1802_08032_amd as q
+    from workloads import noisy_circuit
+    c = q.Circuit(noisy_circuit(7, 2, 1) + random_gate_ops(7, 10, 2, max_controls=2))
+    src, npass = c.source(7, q.C128, 12, 8, 0, 0, 4, kind=q.DENSITY)
+    assert 'qs_ap4(' in src
+    rc, log, size = compile_src(src)
+    assert rc == 0, log
+    c.close()

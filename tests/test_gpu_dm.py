@@ -125,3 +125,72 @@ def test_full_size_dm_14_qubits(q, env):
         b = reg.get_amps(k + dim * j, 1)[0]
         assert abs(a - np.conj(b)) <= 1e-15
     reg.close()
+
+
+@pytest.mark.parametrize('N,tile,tb,contig', [(6, 12, 8, 4), (8, 12, 9, 4), (9, 13, 9, 2), (10, 12, 8, 6)])
+def test_fused_dm_noisy_circuit_matches_oracle(q, env, N, tile, tb, contig):
+    """Density matrices through the compiled fused passes on the 2N-qubit
+    vector (gates + merged 4x4 channel superoperators), with controlled gates
+    and phases mixed in."""
+    ops = noisy_circuit(N, 4, N, p_depol=0.02, p_deph=0.03, gamma=0.05)
+    ops += random_gate_ops(N, 30, seed=N, max_controls=2)
+    ops += noisy_circuit(N, 1, N + 1)
+    ref = O.run_dm(N, ops)
+    reg = q.Register(env, N, q.DENSITY)
+    reg.init_zero()
+    c = q.Circuit(ops)
+    log(f'fused dm N={N} tile={tile} tb={tb} contig={contig}')
+    passes = c.run_compiled(reg, tile, tb, 0, contig)
+    assert passes < len(ops)
+    assert max_abs(reg.get_amps(), ref) <= TOL128
+    assert abs(reg.calc_total_prob() - O.dm_total_prob(ref, N)) <= TOL128
+    c.close()
+    reg.close()
+
+
+def test_fused_dm_via_circuit_run_and_c64(q, env):
+    N = 9
+    ops = noisy_circuit(N, 3, 7)
+    ref = O.run_dm(N, ops)
+    got = run_gpu(q, env, N, ops, kind=q.DENSITY, fusion=12)
+    assert max_abs(got, ref) <= TOL128
+    got64 = run_gpu(q, env, N, ops, kind=q.DENSITY, prec=q.C64, fusion=12)
+    assert max_abs(got64, ref) <= 1e-5
+
+
+def test_full_size_dm_14_qubits_fused(q, env):
+    """The 14-qubit noisy workload through the fused path: the noise-free run
+    equals |psi><psi| from the oracle entry by entry; the noisy run keeps
+    trace 1, Hermiticity and consistent outcome probabilities."""
+    N = 14
+    dim = 1 << N
+    gates = layered_circuit(N, 10, 2)
+    psi = O.run_sv(N, gates)
+    reg = q.Register(env, N, q.DENSITY)
+    reg.init_zero()
+    c = q.Circuit(gates)
+    log('dm14 fused noise-free')
+    c.run_compiled(reg, 12, 8, 0, 4)
+    err = 0.0
+    for blk in range(0, dim, 1024):
+        got = reg.get_amps(blk * dim, 1024 * dim).reshape(1024, dim)
+        ref = np.outer(psi.conj()[blk:blk + 1024], psi)
+        err = max(err, float(np.max(np.abs(got - ref))))
+    assert err <= TOL128
+    c.close()
+    log('dm14 fused noisy')
+    reg.init_zero()
+    c = q.Circuit(noisy_circuit(N, 10, 2))
+    c.run_compiled(reg, 12, 8, 0, 4)
+    assert abs(reg.calc_total_prob() - 1.0) <= 1e-12
+    for qb in range(N):
+        p0, p1 = reg.calc_prob_of_outcome(qb, 0), reg.calc_prob_of_outcome(qb, 1)
+        assert abs(p0 + p1 - 1.0) <= 1e-12 and p0 >= 0 and p1 >= 0
+    rng = np.random.default_rng(1)
+    for _ in range(64):
+        j, k = (int(v) for v in rng.integers(0, dim, 2))
+        a = reg.get_amps(j + dim * k, 1)[0]
+        b = reg.get_amps(k + dim * j, 1)[0]
+        assert abs(a - np.conj(b)) <= 1e-14
+    c.close()
+    reg.close()
