@@ -220,8 +220,10 @@ qs_status qs_circuit_source(qs_circuit c, int n, int kind, int prec, int tile_qu
  * on regs[i]).  All registers must share one environment and precision and
  * hold at least 9 qubits.  Every circuit is planned into fused passes of
  * tiles of min(tile_qubits, smallest register) qubits (9..13 for QS_C128,
- * 9..14 for QS_C64); one launch then runs every register, each by one
- * workgroup, largest registers first.  The batch keeps device copies of the
+ * 9..14 for QS_C64).  A run is one launch per pass level: launch p
+ * applies pass p of every register that has one, its tiles spread over all
+ * workgroups (largest registers first); launch boundaries order a
+ * register's passes.  The batch keeps device copies of the
  * plans; registers and circuits must outlive it, and later changes to the
  * circuits are not seen.  Work runs on the batch's own stream, ordered after
  * and before the registers' streams. */

@@ -241,7 +241,7 @@ __device__ __forceinline__ void relayout(typename C2<T>::type (&v)[1 << RB],
 template <typename T, int TB, int RB>
 __device__ __forceinline__ void process_tile(typename C2<T>::type* __restrict__ amp, const FPass* __restrict__ P,
                                              const FOp* __restrict__ ops, uint64_t tile,
-                                             typename C2<T>::type* lds, uint32_t tid)
+                                             typename C2<T>::type* lds, uint32_t tid, bool zero_init = false)
 {
     using V = typename C2<T>::type;
     constexpr int E = 1 << RB;
@@ -250,8 +250,17 @@ __device__ __forceinline__ void process_tile(typename C2<T>::type* __restrict__ 
     const int nph = P->nphases;
     const uint64_t base = expand(tile, P->outside);
     V v[E];
+    if (zero_init) {  // the tile of |0..0>: nothing to read
 #pragma unroll
-    for (int r = 0; r < E; ++r) v[r] = amp[base + ld_t + span_sum<RB, uint64_t>((uint32_t)r, P->ld_reg)];
+        for (int r = 0; r < E; ++r) {
+            const uint64_t a = base + ld_t + span_sum<RB, uint64_t>((uint32_t)r, P->ld_reg);
+            v[r].x = (a == 0) ? T(1) : T(0);
+            v[r].y = T(0);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < E; ++r) v[r] = amp[base + ld_t + span_sum<RB, uint64_t>((uint32_t)r, P->ld_reg)];
+    }
     for (int ph = 0; ph < nph; ++ph) {
         const FPhase& F = P->ph[ph];
         if (ph > 0) relayout<T, TB, RB>(v, lds, F, tid);
@@ -277,47 +286,41 @@ __global__ __launch_bounds__(1 << TB) void k_fused(typename C2<T>::type* __restr
         process_tile<T, TB, RB>(amp, P, ops, tile, lds, threadIdx.x);
 }
 
-// Batched registers: each workgroup runs whole registers (in the given
-// order, largest first), every planned pass over all of the register's
-// tiles; a workgroup barrier separates passes, so no other workgroup is
-// involved.  With `init` set, the register is first set to |0..0>.
+// Batched registers.  Every register's circuit is planned into passes; the
+// work of pass level p is the list of items (register, its pass p, range of
+// tiles) over all registers that have a pass p.  One launch per level runs
+// its items, each workgroup taking items in a grid-stride loop; the launch
+// boundary is the only synchronisation between the passes of a register, so
+// no workgroup ever waits for another.  Tiles of the first pass can be
+// produced as |0..0> instead of being read (init).
 struct BatchReg {
     void* amp;
     int n;
     int npasses;
-    uint32_t pass0;  // first pass in the pass array
+    uint32_t pass0;  // first pass of the register in the pass array
     uint32_t pad;
+};
+
+struct BatchItem {
+    uint32_t reg, pass, tile0, tile1;
 };
 
 template <typename T, int TB, int RB>
 __global__ __launch_bounds__(1 << TB) void k_batch(const BatchReg* __restrict__ regs,
-                                                   const uint32_t* __restrict__ order, int nregs,
+                                                   const BatchItem* __restrict__ items, int nitems,
                                                    const FPass* __restrict__ passes,
                                                    const FOp* __restrict__ ops, int init)
 {
     using V = typename C2<T>::type;
-    constexpr int K = TB + RB;
-    __shared__ V lds[1 << K];
+    __shared__ V lds[1 << (TB + RB)];
     const uint32_t tid = threadIdx.x;
-    for (int i = blockIdx.x; i < nregs; i += gridDim.x) {
-        const BatchReg R = regs[order[i]];
-        V* amp = (V*)R.amp;
-        const uint64_t len = 1ull << R.n;
-        if (init) {
-            for (uint64_t e = tid; e < len; e += (1u << TB)) {
-                V z;
-                z.x = (e == 0) ? T(1) : T(0);
-                z.y = T(0);
-                amp[e] = z;
-            }
-            __syncthreads();
-        }
-        const uint64_t ntiles = len >> K;
-        for (int p = 0; p < R.npasses; ++p) {
-            const FPass* P = passes + R.pass0 + p;
-            for (uint64_t tile = 0; tile < ntiles; ++tile) process_tile<T, TB, RB>(amp, P, ops, tile, lds, tid);
-            __syncthreads();  // the next pass reads amplitudes this pass wrote
-        }
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const BatchItem it = items[i];
+        const BatchReg R = regs[it.reg];
+        const FPass* P = passes + R.pass0 + it.pass;
+        const bool zi = init && it.pass == 0;
+        for (uint32_t tile = it.tile0; tile < it.tile1; ++tile)
+            process_tile<T, TB, RB>((V*)R.amp, P, ops, tile, lds, tid, zi);
     }
 }
 
@@ -577,10 +580,18 @@ template <typename T, int TB, int RB>
 hipError_t batch_launch_t(qs_batch_s* b, int init)
 {
     const char* base = (const char*)b->dbuf;
-    hipLaunchKernelGGL((k_batch<T, TB, RB>), dim3(b->grid), dim3(1 << TB), 0, b->stream,
-                       (const BatchReg*)(base + b->off_regs), (const uint32_t*)(base + b->off_order), b->count,
-                       (const FPass*)(base + b->off_passes), (const FOp*)(base + b->off_ops), init);
-    return hipGetLastError();
+    const BatchItem* items = (const BatchItem*)(base + b->off_order);
+    for (size_t p = 0; p < b->level_off.size(); ++p) {
+        const int count = b->level_count[p];
+        if (count == 0) continue;
+        const int grid = std::min(count, b->grid);
+        hipLaunchKernelGGL((k_batch<T, TB, RB>), dim3(grid), dim3(1 << TB), 0, b->stream,
+                           (const BatchReg*)(base + b->off_regs), items + b->level_off[p], count,
+                           (const FPass*)(base + b->off_passes), (const FOp*)(base + b->off_ops), init);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <typename T>
@@ -620,11 +631,11 @@ int batch_occupancy_p(int TB, int RB)
 }  // namespace
 
 qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
-                      const std::vector<const std::vector<OpRec>*>& circs, int K)
+                      const std::vector<const std::vector<OpRec>*>& circs, int tile_qubits)
 {
     int nmin = 64;
     for (qs_reg r : regs) nmin = std::min(nmin, r->n);
-    const FusedConfig cfg = default_fused_config(b->prec, K, nmin);
+    const FusedConfig cfg = default_fused_config(b->prec, tile_qubits, nmin);
     if (cfg.TB == 0 || cfg.TB + cfg.RB > nmin)
         return set_error(QS_E_ARG, "batched registers need at least 9 qubits and a tile no wider than the smallest");
     b->TB = cfg.TB;
@@ -633,30 +644,60 @@ qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
     std::vector<FOp> hops;
     std::vector<BatchReg> hr(regs.size());
     const int contig = std::min(4, cfg.TB);
+    const int K = cfg.TB + cfg.RB;
+    int maxpasses = 0;
+    std::vector<uint64_t> per_item(regs.size());
     for (size_t i = 0; i < regs.size(); ++i) {
-        std::vector<PassPlan> plan = plan_passes(*circs[i], regs[i]->n, cfg.TB, cfg.RB, kPhMax, 1 << 12, contig);
+        std::vector<OpRec> none;
+        const std::vector<OpRec>* ops = circs[i];
+        if (ops->empty()) {  // an empty circuit still gets one (identity) pass, which initialises
+            OpRec id{};
+            id.kind = 2;
+            id.ctrls = {0};
+            id.angle = 0.0;
+            none.push_back(id);
+            ops = &none;
+        }
+        std::vector<PassPlan> plan = plan_passes(*ops, regs[i]->n, cfg.TB, cfg.RB, kPhMax, 1 << 12, contig);
+        const uint64_t ntiles = 1ull << (regs[i]->n - K);
+        per_item[i] = std::max<uint64_t>(1, std::min<uint64_t>(16, ntiles));  // tiles per item
         hr[i].amp = regs[i]->amp;
         hr[i].n = regs[i]->n;
         hr[i].pass0 = (uint32_t)hp.size();
         hr[i].npasses = (int)plan.size();
         hr[i].pad = 0;
-        serialize(plan, *circs[i], cfg.TB, cfg.RB, hp, hops);
+        maxpasses = std::max(maxpasses, (int)plan.size());
+        serialize(plan, *ops, cfg.TB, cfg.RB, hp, hops);
     }
     if (hp.empty()) hp.push_back(FPass{});
     if (hops.empty()) hops.push_back(FOp{});
-    // largest registers first so the longest work starts earliest
-    std::vector<uint32_t> order(regs.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = (uint32_t)i;
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t c) { return hr[a].n > hr[c].n; });
+    // items level by level; within a level the largest registers first
+    std::vector<uint32_t> byn(regs.size());
+    for (size_t i = 0; i < byn.size(); ++i) byn[i] = (uint32_t)i;
+    std::stable_sort(byn.begin(), byn.end(), [&](uint32_t a, uint32_t c) { return hr[a].n > hr[c].n; });
+    std::vector<BatchItem> items;
+    b->level_off.clear();
+    b->level_count.clear();
+    for (int p = 0; p < maxpasses; ++p) {
+        b->level_off.push_back((int)items.size());
+        for (uint32_t i : byn) {
+            if (p >= hr[i].npasses) continue;
+            const uint64_t ntiles = 1ull << (hr[i].n - K), per = per_item[i];
+            for (uint64_t t0 = 0; t0 < ntiles; t0 += per)
+                items.push_back(BatchItem{i, (uint32_t)p, (uint32_t)t0, (uint32_t)std::min(ntiles, t0 + per)});
+        }
+        b->level_count.push_back((int)items.size() - b->level_off.back());
+    }
+    b->nitems = (int)items.size();
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
     b->off_regs = 0;
     b->off_order = align(hr.size() * sizeof(BatchReg));
-    b->off_passes = align(b->off_order + order.size() * sizeof(uint32_t));
+    b->off_passes = align(b->off_order + items.size() * sizeof(BatchItem));
     b->off_ops = align(b->off_passes + hp.size() * sizeof(FPass));
     const size_t total = align(b->off_ops + hops.size() * sizeof(FOp));
     std::vector<char> host(total, 0);
     memcpy(host.data() + b->off_regs, hr.data(), hr.size() * sizeof(BatchReg));
-    memcpy(host.data() + b->off_order, order.data(), order.size() * sizeof(uint32_t));
+    memcpy(host.data() + b->off_order, items.data(), items.size() * sizeof(BatchItem));
     memcpy(host.data() + b->off_passes, hp.data(), hp.size() * sizeof(FPass));
     memcpy(host.data() + b->off_ops, hops.data(), hops.size() * sizeof(FOp));
     hipError_t e = hipMalloc(&b->dbuf, total);
@@ -665,8 +706,8 @@ qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
     if (e != hipSuccess) return hip_error(e, "batch plan upload");
     const int per_cu = b->prec == QS_C128 ? batch_occupancy_p<double>(cfg.TB, cfg.RB)
                                           : batch_occupancy_p<float>(cfg.TB, cfg.RB);
-    b->grid = (int)std::min<long>((long)regs.size(), 256L * per_cu);
-    b->passes_total = (int)(hp.size());
+    b->grid = (int)(256L * per_cu);
+    b->passes_total = (int)hp.size();
     return QS_OK;
 }
 

@@ -77,8 +77,10 @@ struct qs_batch_s {
     std::vector<qs_reg> regs;
     std::vector<hipStream_t> reg_streams;  // distinct streams of the registers
     hipEvent_t ev_in, ev_out;
-    void* dbuf = nullptr;          // BatchReg[] + order[] + FPass[] + FOp[]
+    void* dbuf = nullptr;          // BatchReg[] + BatchItem[] + FPass[] + FOp[]
     size_t off_regs, off_order, off_passes, off_ops;
+    int nitems = 0;
+    std::vector<int> level_off, level_count;  // items of each pass level
     double* dprobs = nullptr;      // 2 doubles per register
     double* hprobs = nullptr;      // pinned copy
     hipGraph_t graph = nullptr;
