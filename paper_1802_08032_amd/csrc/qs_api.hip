@@ -305,6 +305,10 @@ qs_status qs_env_destroy(qs_env env)
         hipEventDestroy(rec.a);
         hipEventDestroy(rec.b);
     }
+    for (auto& sp : env->scratch_pool) {
+        hipFree(sp.first);
+        hipHostFree(sp.second);
+    }
     env->magic = 0;
     delete env;
     return QS_OK;
@@ -400,15 +404,25 @@ static qs_status reg_common(qs_env env, int n, int kind, int prec, void* stream,
         }
     }
     void* scratch = nullptr;
-    const size_t sbytes = (4 * qs::kReduceBlocks + 2) * sizeof(double);
-    hipError_t e = dev_alloc(&scratch, sbytes);
     void* hres = nullptr;
-    if (e == hipSuccess) e = hipHostMalloc(&hres, 2 * sizeof(double), hipHostMallocDefault);
-    if (e != hipSuccess) {
-        hipGetLastError();
-        if (scratch) hipFree(scratch);
-        if (!dev_ptr) hipFree(amp);
-        return qs::set_error(QS_E_OOM, "cannot allocate register scratch");
+    {
+        std::lock_guard<std::mutex> g(env->mu);
+        if (!env->scratch_pool.empty()) {
+            scratch = env->scratch_pool.back().first;
+            hres = env->scratch_pool.back().second;
+            env->scratch_pool.pop_back();
+        }
+    }
+    if (!scratch) {
+        const size_t sbytes = (4 * qs::kReduceBlocks + 2) * sizeof(double);
+        hipError_t e = dev_alloc(&scratch, sbytes);
+        if (e == hipSuccess) e = hipHostMalloc(&hres, 2 * sizeof(double), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            hipGetLastError();
+            if (scratch) hipFree(scratch);
+            if (!dev_ptr) hipFree(amp);
+            return qs::set_error(QS_E_OOM, "cannot allocate register scratch");
+        }
     }
     qs_reg r = new qs_reg_s();
     r->magic = kRegMagic;
@@ -446,8 +460,10 @@ qs_status qs_reg_destroy(qs_reg r)
     hipSetDevice(r->env->device);
     hipStreamSynchronize(r->stream);
     if (r->owned) hipFree(r->amp);
-    hipFree(r->scratch);
-    hipHostFree(r->host_res);
+    {
+        std::lock_guard<std::mutex> g(r->env->mu);
+        r->env->scratch_pool.push_back({r->scratch, r->host_res});
+    }
     r->magic = 0;
     delete r;
     return QS_OK;

@@ -544,12 +544,15 @@ qs_status run_fused_sv(qs_reg r, const std::vector<OpRec>& ops, FusedConfig cfg,
     std::vector<char> host(pbytes + obytes);
     memcpy(host.data(), hp.data(), pbytes);
     memcpy(host.data() + pbytes, hops.data(), obytes);
+    // stream-ordered plan buffer: no device-wide synchronisation, so
+    // registers on other streams keep running
     void* dbuf = nullptr;
-    hipError_t e = hipMalloc(&dbuf, pbytes + obytes);
+    hipError_t e = hipMallocAsync(&dbuf, pbytes + obytes, r->stream);
     if (e != hipSuccess) return hip_error(e, "plan buffer");
-    e = hipMemcpy(dbuf, host.data(), pbytes + obytes, hipMemcpyHostToDevice);
+    // from pageable memory the copy has left `host` when the call returns
+    e = hipMemcpyAsync(dbuf, host.data(), pbytes + obytes, hipMemcpyHostToDevice, r->stream);
     if (e != hipSuccess) {
-        hipFree(dbuf);
+        hipFreeAsync(dbuf, r->stream);
         return hip_error(e, "plan upload");
     }
     const FPass* dP = (const FPass*)dbuf;
@@ -562,11 +565,10 @@ qs_status run_fused_sv(qs_reg r, const std::vector<OpRec>& ops, FusedConfig cfg,
                                       : launch_fused_pass<float>(r->stream, cfg, r->amp, dP + p, dO, ntiles);
         });
     }
-    // the plan buffer is released once the passes that read it have finished
-    e = hipStreamSynchronize(r->stream);
-    hipFree(dbuf);
+    // released once the passes that read it have run
+    e = hipFreeAsync(dbuf, r->stream);
     if (st) return st;
-    if (e != hipSuccess) return hip_error(e, "fused passes");
+    if (e != hipSuccess) return hip_error(e, "plan free");
     if (passes_out) *passes_out = (int)hp.size();
     return QS_OK;
 }

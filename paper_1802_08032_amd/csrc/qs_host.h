@@ -23,6 +23,10 @@ struct qs_env_s {
     uint64_t launches[QS_K_COUNT];
     double ms[QS_K_COUNT];
     std::mutex mu;
+    // reduction scratch of destroyed registers, reused by new ones so that
+    // register turnover never frees device memory (which would synchronise
+    // the whole device)
+    std::vector<std::pair<double*, double*>> scratch_pool;
 };
 
 struct qs_reg_s {

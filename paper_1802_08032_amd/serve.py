@@ -1,0 +1,174 @@
+"""Continuous-batching request loop for circuits on one GPU.
+
+Requests (state-vector or density-matrix circuits, each ending with the
+measurement of every qubit under its own draws) arrive over time.  The loop
+admits them in arrival order as soon as a slot and enough HBM are free:
+admission counts the register's bytes (16 * 2^n, or 16 * 4^n for a density
+matrix, halved in complex64) against a budget.  Every admitted request runs
+on its own HIP stream in a worker thread, so requests that arrive while
+others are on the GPU start right away and their kernels overlap on the
+device.  Per request the loop records arrival, admission and completion
+times; `summary` gives p50 / p99 latency, circuits/s and the time-averaged
+HBM occupancy.
+
+The scheduling logic is independent of the executor, which only needs
+`nbytes(request)` and `run(request, slot)`.
+"""
+from __future__ import annotations
+
+import collections
+import concurrent.futures as cf
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import qstate as Q
+
+
+@dataclass
+class Request:
+    rid: int
+    kind: int            # qstate.STATEVEC or qstate.DENSITY
+    n: int               # qubits
+    ops: list            # workloads.Op list
+    arrival: float       # seconds after the start of serving
+    draws: np.ndarray    # one uniform draw per qubit for the final measurements
+    family: str = ''
+
+
+@dataclass
+class Result:
+    rid: int
+    outcomes: list
+    probs: list
+    arrival: float
+    admitted: float
+    finished: float
+    nbytes: int
+    amps: np.ndarray | None = None
+    error: str | None = None
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class GpuExecutor:
+    """Runs one request: register on the slot's stream, |0..0>, the circuit
+    (fused for state vectors of at least `min_fused` qubits, one kernel per
+    op otherwise), then measures qubits 0..n-1 in order."""
+
+    def __init__(self, env: Q.Env, prec: int = Q.C128, slots: int = 8, fusion: int = 12,
+                 min_fused: int = 12, keep_amps: bool = False):
+        import torch
+        self.torch = torch
+        self.env, self.prec, self.fusion, self.min_fused = env, prec, fusion, min_fused
+        self.keep_amps = keep_amps
+        self.streams = [torch.cuda.Stream(device=env.device) for _ in range(slots)]
+
+    def nbytes(self, req: Request) -> int:
+        return Q.reg_bytes(req.n, req.kind, self.prec)
+
+    def run(self, req: Request, slot: int):
+        torch = self.torch
+        stream = self.streams[slot]
+        with torch.cuda.stream(stream):
+            reg = Q.Register(self.env, req.n, req.kind, self.prec, stream=stream)
+            try:
+                reg.init_zero()
+                circ = Q.Circuit(req.ops)
+                fused = req.kind == Q.STATEVEC and req.n >= self.min_fused
+                circ.run(reg, self.fusion if fused else 0)
+                circ.close()
+                outs, probs = [], []
+                for q in range(req.n):
+                    o, p = reg.measure(q, float(req.draws[q]))
+                    outs.append(o)
+                    probs.append(p)
+                amps = reg.get_amps() if self.keep_amps else None
+            finally:
+                reg.close()
+        return outs, probs, amps
+
+
+@dataclass
+class Server:
+    executor: object
+    budget_bytes: int = 256 << 30
+    slots: int = 8
+    events: list = field(default_factory=list)  # (time, bytes in use)
+
+    def serve(self, requests, clock=time.perf_counter) -> list:
+        reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        pending = collections.deque()
+        inflight = {}
+        results = []
+        used = 0
+        free = list(range(self.slots))[::-1]
+        nxt = 0
+        t0 = clock()
+        self.events = [(0.0, 0)]
+        with cf.ThreadPoolExecutor(max_workers=self.slots) as pool:
+            while nxt < len(reqs) or pending or inflight:
+                now = clock() - t0
+                while nxt < len(reqs) and reqs[nxt].arrival <= now:
+                    pending.append(reqs[nxt])
+                    nxt += 1
+                # admit in arrival order while a slot and the bytes are free
+                while pending and free:
+                    r = pending[0]
+                    b = self.executor.nbytes(r)
+                    if b == 0 or b > self.budget_bytes:
+                        pending.popleft()
+                        results.append(Result(r.rid, [], [], r.arrival, now, now, b,
+                                              error='request exceeds the HBM budget'))
+                        continue
+                    if used + b > self.budget_bytes:
+                        break
+                    pending.popleft()
+                    used += b
+                    slot = free.pop()
+                    fut = pool.submit(self.executor.run, r, slot)
+                    inflight[fut] = (r, now, b, slot)
+                    self.events.append((now, used))
+                if inflight:
+                    timeout = None
+                    if nxt < len(reqs):
+                        timeout = max(0.0, reqs[nxt].arrival - (clock() - t0))
+                    done, _ = cf.wait(list(inflight), timeout=timeout, return_when=cf.FIRST_COMPLETED)
+                else:
+                    done = set()
+                    if nxt < len(reqs):
+                        time.sleep(max(0.0, reqs[nxt].arrival - (clock() - t0)))
+                for fut in done:
+                    r, t_adm, b, slot = inflight.pop(fut)
+                    t_end = clock() - t0
+                    used -= b
+                    free.append(slot)
+                    self.events.append((t_end, used))
+                    try:
+                        outs, probs, amps = fut.result()
+                        results.append(Result(r.rid, outs, probs, r.arrival, t_adm, t_end, b, amps))
+                    except Exception as e:  # reported per request; the loop keeps serving
+                        results.append(Result(r.rid, [], [], r.arrival, t_adm, t_end, b, error=str(e)))
+        return sorted(results, key=lambda x: x.rid)
+
+    def summary(self, results) -> dict:
+        ok = [r for r in results if r.error is None]
+        lat = np.array([r.latency for r in ok]) if ok else np.array([0.0])
+        makespan = max((r.finished for r in results), default=0.0)
+        ev = self.events + [(makespan, 0)]
+        area = sum((ev[i + 1][0] - ev[i][0]) * ev[i][1] for i in range(len(ev) - 1))
+        return {
+            'requests': len(results),
+            'completed': len(ok),
+            'failed': len(results) - len(ok),
+            'makespan_s': makespan,
+            'circuits_per_s': len(ok) / makespan if makespan > 0 else 0.0,
+            'latency_p50_s': float(np.percentile(lat, 50)),
+            'latency_p99_s': float(np.percentile(lat, 99)),
+            'latency_mean_s': float(lat.mean()),
+            'hbm_occupancy_mean': area / (self.budget_bytes * makespan) if makespan > 0 else 0.0,
+            'hbm_peak_bytes': max(e[1] for e in self.events),
+        }

@@ -192,3 +192,35 @@ def random_gate_ops(n: int, count: int, seed: int, max_controls: int = 3) -> lis
             ops.append(Op('phase', qubits=tuple(qs), angle=float(rng.uniform(0, 2 * math.pi)),
                           controls=tuple(qs[:k]), target=qs[k]))
     return ops
+
+
+def serving_requests(count: int, rate: float, seed: int = 7, sv_range=(12, 30), dm_range=(8, 13),
+                     depth_range=(5, 40), dm_fraction: float = 0.2) -> list[dict]:
+    """A stream of circuit requests with Poisson arrivals at `rate` per second
+    (rate <= 0: all arrive at t = 0).  A request is a density-matrix noisy
+    circuit with probability dm_fraction, else a state-vector circuit that is
+    layered or parameterised with probability 1/2 each.  Qubit counts are
+    log-uniform in the inclusive ranges, depths uniform; request rid draws
+    its circuit from seed (seed * 1000003 + rid) and its final measurement
+    draws from the Philox stream (seed, rid)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    t = 0.0
+    for rid in range(count):
+        if rate > 0:
+            t += float(rng.exponential(1.0 / rate))
+        dm = bool(rng.random() < dm_fraction)
+        lo, hi = dm_range if dm else sv_range
+        n = min(hi, int(math.floor(math.exp(rng.uniform(math.log(lo), math.log(hi + 1))))))
+        depth = int(rng.integers(depth_range[0], depth_range[1] + 1))
+        family = 'noisy' if dm else ('layered' if rng.random() < 0.5 else 'param')
+        cseed = seed * 1000003 + rid
+        if family == 'noisy':
+            ops = noisy_circuit(n, depth, cseed)
+        elif family == 'layered':
+            ops = layered_circuit(n, depth, cseed)
+        else:
+            ops = param_circuit(n, depth, cseed)
+        out.append({'rid': rid, 'density': dm, 'n': n, 'depth': depth, 'family': family, 'ops': ops,
+                    'arrival': t, 'draws': measurement_draws(seed, rid, n)})
+    return out
