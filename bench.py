@@ -152,6 +152,37 @@ def batched_leg(q, torch, log, reps=5):
     return out
 
 
+def serving_leg(q, torch, log, count=40):
+    """Mixed request stream (80 % state vectors of 12..30 qubits, 20 % noisy
+    density matrices of 8..13 qubits, log-uniform sizes, depth 5..40, every
+    qubit measured at the end), admitted by HBM bytes against 256 GiB with 8
+    concurrent slots: a closed-loop run (all requests at t = 0) gives the
+    capacity, then Poisson arrivals at 0.8 x that rate give the latencies."""
+    from paper_1802_08032_amd.serve import GpuExecutor, Request, Server
+    from workloads import serving_requests
+
+    def reqs(rate):
+        return [Request(s['rid'], q.DENSITY if s['density'] else q.STATEVEC, s['n'], s['ops'], s['arrival'],
+                        s['draws'], s['family']) for s in serving_requests(count, rate, 7)]
+
+    out = {'requests': count, 'budget_gib': 256, 'slots': 8}
+    for name, prec in (('c128', q.C128), ('c64', q.C64)):
+        env = q.Env(0)
+        ex = GpuExecutor(env, prec, slots=8)
+        srv = Server(ex, budget_bytes=256 << 30, slots=8)
+        closed = srv.summary(srv.serve(reqs(0.0)))
+        rate = 0.8 * closed['circuits_per_s']
+        res = srv.serve(reqs(rate))
+        opened = dict(srv.summary(res), arrival_rate=rate)
+        out[name] = {'closed_loop': closed, 'open_loop': opened}
+        log(f"serving {name}: {closed['circuits_per_s']:.2f} circuits/s closed loop; open loop at "
+            f"{rate:.2f}/s: p50 {opened['latency_p50_s']:.3f} s, p99 {opened['latency_p99_s']:.3f} s")
+        del ex, srv
+        env.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -303,6 +334,8 @@ def main():
         torch.cuda.empty_cache()
         log('batched registers')
         out['batched'] = batched_leg(q, torch, log)
+        log('serving')
+        out['serving'] = serving_leg(q, torch, log)
     print(json.dumps(out), flush=True)
 
 

@@ -158,7 +158,7 @@ class Server:
         ok = [r for r in results if r.error is None]
         lat = np.array([r.latency for r in ok]) if ok else np.array([0.0])
         makespan = max((r.finished for r in results), default=0.0)
-        ev = self.events + [(makespan, 0)]
+        ev = (self.events or [(0.0, 0)]) + [(makespan, 0)]
         area = sum((ev[i + 1][0] - ev[i][0]) * ev[i][1] for i in range(len(ev) - 1))
         return {
             'requests': len(results),
@@ -170,5 +170,5 @@ class Server:
             'latency_p99_s': float(np.percentile(lat, 99)),
             'latency_mean_s': float(lat.mean()),
             'hbm_occupancy_mean': area / (self.budget_bytes * makespan) if makespan > 0 else 0.0,
-            'hbm_peak_bytes': max(e[1] for e in self.events),
+            'hbm_peak_bytes': max((e[1] for e in self.events), default=0),
         }

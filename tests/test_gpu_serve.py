@@ -31,7 +31,8 @@ def test_each_result_same_alone_and_in_the_mix(q, prec_name):
     ex = GpuExecutor(env, prec, slots=6, fusion=12, min_fused=12, keep_amps=True)
     reqs = requests(18, rate=400.0, seed=11)
     log(f'serve mix {prec_name}')
-    mix = Server(ex, slots=6).serve(reqs)
+    srv = Server(ex, slots=6)
+    mix = srv.serve(reqs)
     assert all(r.error is None for r in mix), [r.error for r in mix if r.error]
     for req, r_mix in zip(reqs, mix):
         alone = Server(ex, slots=1).serve([req])[0]
@@ -51,6 +52,6 @@ def test_each_result_same_alone_and_in_the_mix(q, prec_name):
             assert abs(r_mix.probs[k] - p) <= tol or r_mix.outcomes[k] != o
         if prec == q.C128:
             assert max_abs(r_mix.amps, st) <= 1e-11
-    s = Server(ex, slots=6).summary(mix)
+    s = srv.summary(mix)
     assert s['completed'] == len(reqs)
     env.close()
