@@ -32,6 +32,7 @@ namespace {
 struct GenOut {
     std::string src;
     std::vector<double> mats;  // 8 values per op that reads a matrix or phase
+    bool bad = false;          // a relayout's swizzle broke the address split
 };
 
 std::string hex64(uint64_t v)
@@ -98,6 +99,22 @@ __device__ __forceinline__ void qs_ap4(const R (&m)[32], V& a, V& b, V& c, V& d)
     c = y[2];
     d = y[3];
 }
+typedef R VE __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ V qs_ldnt(const V* p)
+{
+    const VE e = __builtin_nontemporal_load((const VE*)p);
+    V v;
+    v.x = e.x;
+    v.y = e.y;
+    return v;
+}
+__device__ __forceinline__ void qs_stnt(V v, V* p)
+{
+    VE e;
+    e.x = v.x;
+    e.y = v.y;
+    __builtin_nontemporal_store(e, (VE*)p);
+}
 __device__ __forceinline__ void qs_cm(R fr, R fi, V& a)
 {
     V r;
@@ -156,9 +173,9 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     }
 
     // Tile loop with a one-tile prefetch: tile t + gridDim.x is loaded while
-    // tile t is computed.  The matrix pointer is made to depend on the tile
-    // (the added term is always 0) so that the scalar matrix loads stay in
-    // the loop instead of being hoisted out of it.
+    // tile t is computed.  The matrix pointer is made to depend
+    // on the tile (the added term is always 0) so that the scalar matrix loads
+    // stay in the loop instead of being hoisted out of it.
     s << "    unsigned long long tile = blockIdx.x;\n";
     s << "    if (tile >= ntiles) return;\n";
     s << "    auto ins = [](unsigned long long t) -> unsigned long long {\n";
@@ -175,22 +192,67 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
             if ((r >> b) & 1) o = use_xor ? (o ^ img[b]) : (o + img[b]);
         return o;
     };
-    for (int r = 0; r < E; ++r)
-        s << "    V v" << r << " = amp[base + ldt + " << hex64(reg_off(ldreg, r, false)) << "];\n";
+    // Amplitudes stream through once per pass, so loads and stores are
+    // marked non-temporal.
+    auto ld = [&](const std::string& bvar, int r) {
+        return "qs_ldnt(&amp[" + bvar + " + ldt + " + hex64(reg_off(ldreg, r, false)) + "])";
+    };
+    for (int r = 0; r < E; ++r) s << "    V v" << r << " = " << ld("base", r) << ";\n";
+    // Drain the first tile's loads before the loop.  The compiler's wait
+    // analysis merges the loop entry with the back edge; with these loads
+    // still pending at the entry it makes every iteration wait for the loads
+    // of the next tile before computing the current one.
+    s << "    __builtin_amdgcn_s_waitcnt(0x0F70);\n";
     s << "    for (;;) {\n";
-    s << "        const R* mt = mats + (tile >> 62);\n";
+    // z is always 0; LDS addresses derived from it are computed in the loop
+    // next to their use instead of being hoisted and held in registers.
+    s << "        const unsigned z = (unsigned)(tile >> 62);\n";
+    s << "        const R* mt = mats + z;\n";
     s << "        const unsigned long long ntile = tile + gridDim.x;\n";
     s << "        const bool more = ntile < ntiles;\n";
-    s << "        const unsigned long long nbase = ins(ntile);\n";
     for (int r = 0; r < E; ++r) s << "        V n" << r << ";\n";
     s << "        if (more) {\n";
-    for (int r = 0; r < E; ++r)
-        s << "            n" << r << " = amp[nbase + ldt + " << hex64(reg_off(ldreg, r, false)) << "];\n";
+    s << "            const unsigned long long nb = ins(ntile);\n";
+    for (int r = 0; r < E; ++r) s << "            n" << r << " = " << ld("nb", r) << ";\n";
     s << "        }\n";
 
     std::vector<int> name(E);
     for (int r = 0; r < E; ++r) name[r] = r;
     auto vn = [&](int r) { return "v" + std::to_string(name[r]); };
+
+    // Conditional NOTs (condition on thread or tile bits only) are not applied
+    // to the registers right away.  pend[b] names a per-lane bool: where it is
+    // true, the registers of every pair on register bit b hold the two
+    // amplitudes the other way round.  The flip is folded into the next LDS or
+    // HBM write address, into the matrix of a later gate on bit b (rows and
+    // columns exchanged), or applied with selects when an op needs bit b as a
+    // control or as a target of a 4x4 or phase.
+    std::vector<std::string> pend(RB);
+    int nflip = 0;
+    auto materialize = [&](uint32_t bits) {
+        for (int b = 0; b < RB; ++b) {
+            if (!((bits >> b) & 1) || pend[b].empty()) continue;
+            s << "        {\n            const bool c = " << pend[b] << ";\n";
+            for (int r0 = 0; r0 < E; ++r0) {
+                if ((r0 >> b) & 1) continue;
+                const std::string A = vn(r0), B = vn(r0 | (1 << b));
+                // component-wise selects keep both values in registers
+                s << "            { const V ta = " << A << ", tb = " << B << "; " << A << ".x = c ? tb.x : ta.x; " << A
+                  << ".y = c ? tb.y : ta.y; " << B << ".x = c ? ta.x : tb.x; " << B << ".y = c ? ta.y : tb.y; }\n";
+            }
+            s << "        }\n";
+            pend[b].clear();
+        }
+    };
+    auto flip_expr = [&](const std::vector<uint64_t>& img, bool wide) {
+        std::string e;
+        for (int b = 0; b < RB; ++b) {
+            if (pend[b].empty()) continue;
+            const std::string v = wide ? hex64(img[b]) : hex32((uint32_t)img[b]);
+            e += (e.empty() ? "" : " ^ ") + std::string("(") + pend[b] + " ? " + v + " : " + (wide ? "0ull" : "0u") + ")";
+        }
+        return e;
+    };
 
     size_t tcount = 0;
     auto emit_relayout = [&](size_t t) {
@@ -198,13 +260,33 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
         std::vector<uint64_t> wreg, rreg;
         for (int b = 0; b < RB; ++b) wreg.push_back(T.img[T.from->reg[b]]);
         for (int b = 0; b < RB; ++b) rreg.push_back(T.img[T.to->reg[b]]);
-        for (int r = 0; r < E; ++r)
-            s << "        lds[tw" << t << " ^ " << hex32((uint32_t)reg_off(wreg, r, true)) << "] = " << vn(r) << ";\n";
+        // The swizzle mixes only into address bits 0..2 and the thread and
+        // register parts have disjoint bits above them, so tw ^ x equals
+        // (tw ^ (x & 7)) + (x & ~7): at most eight distinct address registers
+        // per side, the rest goes into the instructions' immediate offsets.
+        for (int j = 0; j < K; ++j)
+            if ((T.img[j] ^ (1u << j)) & ~7u) g.bad = true;
+        auto addr = [&](const char* side, uint32_t x) {
+            std::ostringstream a;
+            a << "((" << side << t << "z ^ " << (x & 7u) << "u) + " << hex32(x & ~7u) << ")";
+            return a.str();
+        };
+        s << "        const unsigned tw" << t << "z = tw" << t << " ^ z, tr" << t << "z = tr" << t << " ^ z;\n";
+        const std::string fx = flip_expr(wreg, false);
+        if (fx.empty()) {
+            for (int r = 0; r < E; ++r)
+                s << "        lds[" << addr("tw", (uint32_t)reg_off(wreg, r, true)) << "] = " << vn(r) << ";\n";
+        } else {
+            // a flipped lane writes register r where register r ^ flips goes
+            s << "        const unsigned twf" << t << " = tw" << t << "z ^ " << fx << ";\n";
+            for (int r = 0; r < E; ++r)
+                s << "        lds[twf" << t << " ^ " << hex32((uint32_t)reg_off(wreg, r, true)) << "] = " << vn(r) << ";\n";
+            for (int b = 0; b < RB; ++b) pend[b].clear();
+        }
         s << "        QS_BAR();\n";
         // read into fresh names so that no value is overwritten before it is stored
         for (int r = 0; r < E; ++r)
-            s << "        const V w" << t << "_" << r << " = lds[tr" << t << " ^ "
-              << hex32((uint32_t)reg_off(rreg, r, true)) << "];\n";
+            s << "        const V w" << t << "_" << r << " = lds[" << addr("tr", (uint32_t)reg_off(rreg, r, true)) << "];\n";
         s << "        QS_BAR();\n";
         for (int r = 0; r < E; ++r) s << "        v" << r << " = w" << t << "_" << r << ";\n";
         for (int r = 0; r < E; ++r) name[r] = r;
@@ -241,10 +323,11 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
                 const std::string t = "((tid & " + hex32(tmask) + ") == " + hex32(tmask) + ")";
                 cond = cond.empty() ? t : cond + " && " + t;
             }
+            materialize(rmask);  // register controls are read as they stand
             const size_t off = g.mats.size();
             if (op.kind == 2) {  // phase on the registers whose masked bits are 1
                 g.mats.insert(g.mats.end(), {cos(op.angle), sin(op.angle), 0, 0, 0, 0, 0, 0});
-                s << "        {\n            R fr = mats[" << off << "], fi = mats[" << off + 1 << "];\n";
+                s << "        {\n            R fr = mt[" << off << "], fi = mt[" << off + 1 << "];\n";
                 if (!cond.empty())
                     s << "            const bool c = " << cond << ";\n            fr = c ? fr : (R)1; fi = c ? fi : (R)0;\n";
                 for (int r = 0; r < E; ++r)
@@ -258,6 +341,7 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
                     if (L.reg[k] == local[op.target]) b1 = k;
                     if (L.reg[k] == local[op.target2]) b2 = k;
                 }
+                materialize((1u << b1) | (1u << b2));
                 for (int k = 0; k < 32; ++k) g.mats.push_back(op.m4[k]);
                 s << "        {\n            R m[32];\n";
                 for (int k = 0; k < 32; ++k) s << "            m[" << k << "] = mt[" << off + k << "];\n";
@@ -282,18 +366,23 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
                 if (L.reg[k] == local[op.target]) b = k;
             if (op.kind == 1) {  // NOT
                 if (cond.empty()) {
+                    // a permutation of register names (a pending flip on b commutes with it)
                     for (int r0 = 0; r0 < E; ++r0) {
                         if ((r0 >> b) & 1) continue;
                         if (((uint32_t)r0 & rmask) != rmask) continue;
                         std::swap(name[r0], name[r0 | (1 << b)]);
                     }
+                } else if (rmask == 0) {
+                    const std::string f = "f" + std::to_string(nflip++);
+                    s << "        const bool " << f << " = " << (pend[b].empty() ? "" : "(" + pend[b] + ") != ") << "("
+                      << cond << ");\n";
+                    pend[b] = f;
                 } else {
                     s << "        {\n            const bool c = " << cond << ";\n";
                     for (int r0 = 0; r0 < E; ++r0) {
                         if ((r0 >> b) & 1) continue;
                         if (((uint32_t)r0 & rmask) != rmask) continue;
                         const std::string A = vn(r0), B = vn(r0 | (1 << b));
-                        // component-wise selects keep both values in registers
                         s << "            { const V ta = " << A << ", tb = " << B << "; " << A << ".x = c ? tb.x : ta.x; "
                           << A << ".y = c ? tb.y : ta.y; " << B << ".x = c ? ta.x : tb.x; " << B
                           << ".y = c ? ta.y : tb.y; }\n";
@@ -310,6 +399,12 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
                 for (int k = 0; k < 8; ++k)
                     s << "            m[" << k << "] = c ? m[" << k << "] : (R)" << ((k == 0 || k == 6) ? 1 : 0) << ";\n";
             }
+            if (!pend[b].empty()) {
+                // flipped lanes apply X U X: rows and columns exchanged
+                s << "            { const bool f = " << pend[b] << "; const R t0 = m[0], t1 = m[1], t2 = m[2], t3 = m[3];\n"
+                  << "              m[0] = f ? m[6] : t0; m[1] = f ? m[7] : t1; m[6] = f ? t0 : m[6]; m[7] = f ? t1 : m[7];\n"
+                  << "              m[2] = f ? m[4] : t2; m[3] = f ? m[5] : t3; m[4] = f ? t2 : m[4]; m[5] = f ? t3 : m[5]; }\n";
+            }
             for (int r0 = 0; r0 < E; ++r0) {
                 if ((r0 >> b) & 1) continue;
                 if (((uint32_t)r0 & rmask) != rmask) continue;
@@ -320,11 +415,20 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     }
     if (final_t) emit_relayout(tcount++);
     s << "        const unsigned long long bs = base + stt;\n";
-    for (int r = 0; r < E; ++r)
-        s << "        amp[bs + " << hex64(reg_off(streg, r, false)) << "] = " << vn(r) << ";\n";
+    const std::string fx = flip_expr(streg, true);
+    if (fx.empty()) {
+        for (int r = 0; r < E; ++r)
+            s << "        qs_stnt(" << vn(r) << ", &amp[bs + " << hex64(reg_off(streg, r, false)) << "]);\n";
+    } else {
+        // register offsets are sums of distinct powers of two, so a flipped
+        // lane's offset for register r is the XOR of r's and the flips' offsets
+        s << "        const unsigned long long sf = " << fx << ";\n";
+        for (int r = 0; r < E; ++r)
+            s << "        qs_stnt(" << vn(r) << ", &amp[bs + (" << hex64(reg_off(streg, r, false)) << " ^ sf)]);\n";
+    }
     s << "        if (!more) break;\n";
     for (int r = 0; r < E; ++r) s << "        v" << r << " = n" << r << ";\n";
-    s << "        tile = ntile;\n        base = nbase;\n    }\n}\n";
+    s << "        tile = ntile;\n        base = ins(tile);\n    }\n}\n";
     g.src = s.str();
     return g;
 }
@@ -515,11 +619,14 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
         }
         const bool dbl = r->prec == QS_C128;
         std::vector<PassPlan> plan = plan_passes(ops, nbits, cfg.TB, cfg.RB, cfg.max_phases, 1 << 12, cfg.contig);
+        std::vector<OpRec> ext(ops);
+        for (PassPlan& P : plan) merge_phase_ops(P, ext);
         std::vector<std::string> srcs;
         std::vector<double> mats;
         std::unique_ptr<JitPlan> nj(new JitPlan());
         for (const PassPlan& P : plan) {
-            GenOut go = generate(P, ops, cfg.TB, cfg.RB, dbl);
+            GenOut go = generate(P, ext, cfg.TB, cfg.RB, dbl);
+            if (go.bad) return set_error(QS_E_ARG, "internal: relayout swizzle outside address bits 0..2");
             nj->mat_off.push_back(mats.size());
             mats.insert(mats.end(), go.mats.begin(), go.mats.end());
             srcs.push_back(std::move(go.src));
@@ -583,8 +690,14 @@ qs_status generate_sources(const std::vector<OpRec>& circuit_ops, int n, int kin
     const std::vector<OpRec>& ops = kind == QS_DENSITY ? dm_ops : circuit_ops;
     if (kind == QS_DENSITY) n *= 2;
     std::vector<PassPlan> plan = plan_passes(ops, n, cfg.TB, cfg.RB, cfg.max_phases, 1 << 12, cfg.contig);
+    std::vector<OpRec> ext(ops);
+    for (PassPlan& P : plan) merge_phase_ops(P, ext);
     out.clear();
-    for (const PassPlan& P : plan) out.push_back(generate(P, ops, cfg.TB, cfg.RB, prec == QS_C128).src);
+    for (const PassPlan& P : plan) {
+        GenOut go = generate(P, ext, cfg.TB, cfg.RB, prec == QS_C128);
+        if (go.bad) return set_error(QS_E_ARG, "internal: relayout swizzle outside address bits 0..2");
+        out.push_back(go.src);
+    }
     return QS_OK;
 }
 

@@ -36,6 +36,13 @@ bool coalesced(const Layout& L, int contig);
 // is read from or written to HBM (contiguous runs of 2^contig amplitudes).
 std::vector<PassPlan> plan_passes(const std::vector<OpRec>& all, int n, int TB, int RB, int max_phases,
                                   int max_ops, int contig);
+// Within every phase of P, replace runs of ops that act on at most two
+// register qubits and carry no thread or tile condition by their product
+// (a 2x2 dense op or a 4x4 kind-4 op), wherever that takes fewer
+// multiply-adds than applying them one by one.  Merged ops are appended to
+// `ops`; the phases' index lists are rewritten.  Ops on disjoint qubits
+// commute, so ops may move past each other when their qubits are disjoint.
+void merge_phase_ops(PassPlan& P, std::vector<OpRec>& ops);
 // LDS images (K values) of the local bits for a re-layout from A to B.
 std::vector<uint32_t> swizzle(const Layout& A, const Layout& B, int K);
 

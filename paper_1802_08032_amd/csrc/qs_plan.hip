@@ -5,6 +5,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <complex>
 #include <vector>
 
 #include "qs_plan.h"
@@ -192,6 +193,224 @@ std::vector<PassPlan> plan_passes(const std::vector<OpRec>& all, int n, int TB, 
         passes.push_back(std::move(P));
     }
     return passes;
+}
+
+namespace {
+
+using Cx = std::complex<double>;
+
+// An operator on one or two qubits: index bit k of the 4x4 (or 2x2) matrix
+// is qubit q[k].
+struct LocalOp {
+    int nb = 0;
+    int q[2] = {-1, -1};
+    Cx m[4][4];
+};
+
+bool has(const LocalOp& A, int qb) { return A.q[0] == qb || (A.nb == 2 && A.q[1] == qb); }
+
+// The op as a LocalOp when all its qubits are register qubits (no thread or
+// tile condition) and there are at most two of them.
+bool soft_op(const OpRec& op, uint64_t regs, LocalOp& L)
+{
+    std::vector<int> sup;
+    if (op.kind == 0 || op.kind == 1) {
+        sup.push_back(op.target);
+        sup.insert(sup.end(), op.ctrls.begin(), op.ctrls.end());
+    } else if (op.kind == 2) {
+        sup = op.ctrls;
+    } else if (op.kind == 4) {
+        if (!op.ctrls.empty()) return false;
+        sup = {op.target, op.target2};
+    } else {
+        return false;
+    }
+    if (sup.empty() || sup.size() > 2) return false;
+    for (int qb : sup)
+        if (!((regs >> qb) & 1)) return false;
+    L = LocalOp();
+    L.nb = (int)sup.size();
+    L.q[0] = sup[0];
+    if (L.nb == 2) L.q[1] = sup[1];
+    const int dim = 1 << L.nb;
+    for (int i = 0; i < dim; ++i)
+        for (int j = 0; j < dim; ++j) L.m[i][j] = 0.0;
+    if (op.kind == 0 || op.kind == 1) {
+        // bit 0: target; bit 1 (if any): the control
+        Cx u[2][2];
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
+                u[i][j] = op.kind == 1 ? Cx(i != j ? 1.0 : 0.0, 0.0) : Cx(op.u[2 * (2 * i + j)], op.u[2 * (2 * i + j) + 1]);
+        for (int j = 0; j < dim; ++j) {
+            if (L.nb == 2 && !((j >> 1) & 1)) {
+                L.m[j][j] = 1.0;
+                continue;
+            }
+            for (int i = 0; i < dim; ++i)
+                if ((i >> 1) == (j >> 1)) L.m[i][j] = u[i & 1][j & 1];
+        }
+    } else if (op.kind == 2) {
+        for (int j = 0; j < dim; ++j) L.m[j][j] = j == dim - 1 ? std::polar(1.0, op.angle) : Cx(1.0, 0.0);
+    } else {
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) L.m[i][j] = Cx(op.m4[2 * (4 * i + j)], op.m4[2 * (4 * i + j) + 1]);
+    }
+    return true;
+}
+
+// A on qubits (q0[, q1]) whose qubits are a subset of them.
+LocalOp embed(const LocalOp& A, int nb, int q0, int q1)
+{
+    LocalOp B;
+    B.nb = nb;
+    B.q[0] = q0;
+    B.q[1] = q1;
+    const int dim = 1 << nb;
+    int pos[2] = {0, 0};  // bit of B's index holding A's bit k
+    for (int k = 0; k < A.nb; ++k) pos[k] = A.q[k] == q0 ? 0 : 1;
+    uint32_t amask = 0;
+    for (int k = 0; k < A.nb; ++k) amask |= 1u << pos[k];
+    auto sub = [&](int i) {
+        int s = 0;
+        for (int k = 0; k < A.nb; ++k) s |= ((i >> pos[k]) & 1) << k;
+        return s;
+    };
+    for (int i = 0; i < dim; ++i)
+        for (int j = 0; j < dim; ++j)
+            B.m[i][j] = ((uint32_t)(i ^ j) & ~amask) ? Cx(0.0, 0.0) : A.m[sub(i)][sub(j)];
+    return B;
+}
+
+LocalOp mul(const LocalOp& A, const LocalOp& B)  // A * B on the same qubits
+{
+    LocalOp C = A;
+    const int dim = 1 << A.nb;
+    for (int i = 0; i < dim; ++i)
+        for (int j = 0; j < dim; ++j) {
+            Cx s = 0.0;
+            for (int k = 0; k < dim; ++k) s += A.m[i][k] * B.m[k][j];
+            C.m[i][j] = s;
+        }
+    return C;
+}
+
+// Real multiply-adds per amplitude when an op is applied in registers.
+double op_cost(const OpRec& op, int nregctrl)
+{
+    switch (op.kind) {
+    case 0: return 8.0 / (1 << nregctrl);
+    case 1: return 0.0;  // a permutation of register names
+    case 2: return 4.0 / (1 << op.ctrls.size());
+    case 4: return 16.0 / (1 << nregctrl);
+    default: return 1e9;
+    }
+}
+
+struct Block {
+    LocalOp acc;            // product of everything merged so far
+    std::vector<int> plan;  // ops to emit, in order (originals or merged)
+    double cost = 0.0;
+};
+
+}  // namespace
+
+void merge_phase_ops(PassPlan& P, std::vector<OpRec>& ops)
+{
+    for (PhasePlan& ph : P.phases) {
+        uint64_t regs = 0;
+        for (int j : ph.lay.reg) regs |= 1ull << P.S[j];
+        std::vector<Block> blocks;
+        std::vector<int> out;
+        auto flush_touching = [&](uint64_t qubits) {
+            for (size_t b = 0; b < blocks.size();) {
+                const LocalOp& A = blocks[b].acc;
+                bool hit = false;
+                for (int k = 0; k < A.nb; ++k) hit |= (qubits >> A.q[k]) & 1;
+                if (hit) {
+                    out.insert(out.end(), blocks[b].plan.begin(), blocks[b].plan.end());
+                    blocks.erase(blocks.begin() + b);
+                } else {
+                    ++b;
+                }
+            }
+        };
+        for (int idx : ph.ops) {
+            LocalOp L;
+            if (!soft_op(ops[idx], regs, L)) {
+                flush_touching(qubit_mask(ops[idx]));
+                out.push_back(idx);
+                continue;
+            }
+            const double c_op = op_cost(ops[idx], ops[idx].kind == 2 ? 0 : (int)ops[idx].ctrls.size());
+            // blocks sharing a qubit with the op, and the union of qubits
+            std::vector<size_t> hit;
+            uint64_t uni = 0;
+            for (int k = 0; k < L.nb; ++k) uni |= 1ull << L.q[k];
+            for (size_t b = 0; b < blocks.size(); ++b) {
+                const LocalOp& A = blocks[b].acc;
+                bool h = false;
+                for (int k = 0; k < L.nb; ++k) h |= has(A, L.q[k]);
+                if (h) {
+                    hit.push_back(b);
+                    for (int k = 0; k < A.nb; ++k) uni |= 1ull << A.q[k];
+                }
+            }
+            if (__builtin_popcountll(uni) > 2) {
+                uint64_t qm = 0;
+                for (int k = 0; k < L.nb; ++k) qm |= 1ull << L.q[k];
+                flush_touching(qm);
+                Block nbk;
+                nbk.acc = L;
+                nbk.plan = {idx};
+                nbk.cost = c_op;
+                blocks.push_back(nbk);
+                continue;
+            }
+            const int nb = __builtin_popcountll(uni);
+            const int q0 = __builtin_ctzll(uni);
+            const int q1 = nb == 2 ? 63 - __builtin_clzll(uni) : -1;
+            LocalOp acc = embed(L, nb, q0, q1);
+            Block nbk;
+            nbk.cost = c_op;
+            for (size_t b : hit) {
+                acc = mul(acc, embed(blocks[b].acc, nb, q0, q1));
+                nbk.plan.insert(nbk.plan.end(), blocks[b].plan.begin(), blocks[b].plan.end());
+                nbk.cost += blocks[b].cost;
+            }
+            nbk.plan.push_back(idx);
+            nbk.acc = acc;
+            const double full = nb == 1 ? 8.0 : 16.0;
+            if (full < nbk.cost) {
+                OpRec m{};
+                m.target = q0;
+                if (nb == 1) {
+                    m.kind = 0;
+                    for (int i = 0; i < 2; ++i)
+                        for (int j = 0; j < 2; ++j) {
+                            m.u[2 * (2 * i + j)] = acc.m[i][j].real();
+                            m.u[2 * (2 * i + j) + 1] = acc.m[i][j].imag();
+                        }
+                } else {
+                    m.kind = 4;
+                    m.target2 = q1;
+                    m.m4.resize(32);
+                    for (int i = 0; i < 4; ++i)
+                        for (int j = 0; j < 4; ++j) {
+                            m.m4[2 * (4 * i + j)] = acc.m[i][j].real();
+                            m.m4[2 * (4 * i + j) + 1] = acc.m[i][j].imag();
+                        }
+                }
+                ops.push_back(m);
+                nbk.plan = {(int)ops.size() - 1};
+                nbk.cost = full;
+            }
+            std::sort(hit.begin(), hit.end());
+            for (size_t k = hit.size(); k-- > 0;) blocks.erase(blocks.begin() + hit[k]);
+            blocks.push_back(nbk);
+        }
+        for (const Block& b : blocks) out.insert(out.end(), b.plan.begin(), b.plan.end());
+        ph.ops = out;
+    }
 }
 
 // GF(2)-linear LDS address map for a re-layout from A to B.  Local bit j

@@ -223,6 +223,52 @@ def test_profiler_counts_launches(q, env):
     assert launches >= 1 and ms > 0.0
 
 
+def flip_circuit(n: int, seed: int):
+    """NOTs controlled by low (thread) qubits on every other qubit, each
+    followed by a gate on its target, a gate controlled by its target, a
+    4-qubit phase over flipped qubits, and flips left open at the end."""
+    rng = np.random.default_rng(seed)
+    ops = [Op('u', target=t, u=haar_unitary(rng)) for t in range(n)]
+    for t in range(4, n):
+        c = int(rng.integers(0, 4))
+        ops.append(Op('x', target=t, controls=(c,)))
+        ops.append(Op('x', target=t, controls=((c + 1) % 4,)))
+        ops.append(Op('u', target=t, u=haar_unitary(rng)))
+        ops.append(Op('x', target=t, controls=(c,)))
+        if t + 1 < n:
+            ops.append(Op('u', target=t + 1, controls=(t,), u=haar_unitary(rng)))
+    ops.append(Op('phase', qubits=(4, 5, 6, 7), angle=0.7, controls=(4, 5, 6), target=7))
+    for t in range(4, n):
+        ops.append(Op('x', target=t, controls=(t % 4, (t + 1) % 4)))
+        ops.append(Op('x', target=t, controls=(n - 1 - t % 3,)) if t < n - 3 else Op('x', target=t, controls=(0,)))
+    return ops
+
+
+@pytest.mark.parametrize('prec_name,tile,tb,contig', [('C128', 12, 8, 4), ('C128', 13, 9, 4), ('C128', 11, 8, 6),
+                                                      ('C64', 13, 9, 4)])
+def test_compiled_deferred_flips(q, env, prec_name, tile, tb, contig):
+    """Thread- and tile-controlled NOTs kept as per-lane flips: folded into
+    later gate matrices, applied before their target is used as a control,
+    and folded into the LDS and HBM write addresses."""
+    prec = getattr(q, prec_name)
+    n = 15
+    ops = flip_circuit(n, 11)
+    state = random_state(n, 5)
+    ref = oracle_run(n, ops, state)
+    reg = q.Register(env, n, q.STATEVEC, prec)
+    reg.set_amps(state)
+    c = q.Circuit(ops)
+    log(f'flips {prec_name} tile={tile} tb={tb} contig={contig}')
+    c.run_compiled(reg, tile, tb, 0, contig)
+    got = reg.get_amps()
+    if prec == q.C128:
+        assert max_abs(got, ref) <= TOL128
+    else:
+        assert fidelity_deficit(ref, got) <= TOL64_FID
+    c.close()
+    reg.close()
+
+
 @pytest.mark.parametrize('prec_name,tile,tb,contig', [('C128', 13, 10, 6), ('C128', 12, 9, 6), ('C128', 11, 8, 6),
                                                       ('C128', 9, 6, 6), ('C128', 13, 9, 4), ('C128', 12, 8, 3),
                                                       ('C64', 14, 10, 6), ('C64', 13, 9, 4)])
