@@ -4,9 +4,9 @@ Workload: one 32-qubit complex128 state vector (64 GiB) and a depth-10
 layered random circuit (per layer: a Haar-random unitary on every qubit, a
 CNOT brick, one phase gate with 3 controls + 1 target), 485 gates.  One step
 = init |0..0> + the whole circuit (fused into HBM round trips of 2^K-
-amplitude tiles by run-time compiled pass kernels, tile shape chosen by the
-autotuner during warm-up) + total probability + probability of an outcome +
-one measurement.  Inputs are seeded and synthetic; the register is resident
+amplitude tiles by run-time compiled pass kernels; 13-qubit tiles of 512
+threads by default, or the autotuner's choice with --tile auto) + total
+probability + probability of an outcome + one measurement.  Inputs are seeded and synthetic; the register is resident
 in HBM before the timed region starts.
 
 Prints one JSON line (metric, value = gates/s, roofline of the dominant
@@ -190,7 +190,7 @@ def main():
     ap.add_argument('--warmup', type=int, default=1)
     ap.add_argument('--qubits', type=int, default=32)
     ap.add_argument('--depth', type=int, default=10)
-    ap.add_argument('--tile', default='auto', help="'auto' (autotuner) or K,TB,contig")
+    ap.add_argument('--tile', default='13,9,4', help="K,TB,contig of the fused passes, or 'auto' (autotuner)")
     ap.add_argument('--no-extras', action='store_true', help='skip unfused / per-target / CPU legs')
     ap.add_argument('--copy-calibration', action='store_true',
                     help='only run a device copy of 16 GiB (HBM counter calibration)')
