@@ -4,8 +4,9 @@
 // probability reductions and measurement collapse.
 //
 // Layout: interleaved complex (double2 / float2), qubit q = bit q of the
-// index.  Every kernel is a grid-stride loop over 64-bit indices with a
-// grid capped at 16 blocks per CU.
+// index.  Every kernel loops over 64-bit indices with a grid capped at 16
+// blocks per CU; the streaming kernels take kPer amplitudes per thread per
+// step (see qs_device.h).
 #include <algorithm>
 
 #include "qs_device.h"
@@ -53,26 +54,27 @@ __global__ __launch_bounds__(kBlock) void k_gate_pair(typename C2<T>::type* __re
                                                       Mat2<T> u)
 {
     using V = typename C2<T>::type;
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    for (; i + stride < npairs; i += 2 * stride) {
-        const uint64_t a0 = expand(i, ins);
-        const uint64_t a1 = expand(i + stride, ins);
-        V x0 = amp[a0], y0 = amp[a0 + tb];
-        V x1 = amp[a1], y1 = amp[a1 + tb];
-        apply2<T, V>(u.m, x0, y0);
-        apply2<T, V>(u.m, x1, y1);
-        amp[a0] = x0;
-        amp[a0 + tb] = y0;
-        amp[a1] = x1;
-        amp[a1 + tb] = y1;
-    }
-    if (i < npairs) {
-        const uint64_t a = expand(i, ins);
-        V x = amp[a], y = amp[a + tb];
-        apply2<T, V>(u.m, x, y);
-        amp[a] = x;
-        amp[a + tb] = y;
+    constexpr int P = kPer<T> / 2;
+    const uint64_t ps = (uint64_t)kBlock * P;
+    for (uint64_t s = blockIdx.x; step_base(s, ps) < npairs; s += gridDim.x) {
+        const uint64_t c = step_base(s, ps);
+        uint64_t a[P];
+        V x[P], y[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const uint64_t i = step_item(c, j, ps);
+            a[j] = expand(i < npairs ? i : npairs - 1, ins);  // a clamped lane only reads
+            x[j] = ldnt(amp + a[j]);
+            y[j] = ldnt(amp + a[j] + tb);
+        }
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            apply2<T, V>(u.m, x[j], y[j]);
+            if (step_item(c, j, ps) < npairs) {
+                stnt(amp + a[j], x[j]);
+                stnt(amp + a[j] + tb, y[j]);
+            }
+        }
     }
 }
 
@@ -117,40 +119,39 @@ __global__ __launch_bounds__(kBlock) void k_gate_low(typename C2<T>::type* __res
 {
     using V = typename C2<T>::type;
     const int lane = threadIdx.x & 63;
-    const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
-    const uint64_t nw = ((uint64_t)gridDim.x * kBlock) >> 6;
     const bool up = (lane >> TT) & 1;
     const bool ok = ((uint32_t)lane & lowmask) == lowmask;
     // new = s * self + p * partner
     const T sr = up ? u.m[6] : u.m[0], si = up ? u.m[7] : u.m[1];
     const T pr = up ? u.m[4] : u.m[2], pi = up ? u.m[5] : u.m[3];
-    constexpr int U = 4;
-    uint64_t c = wave;
-    for (; c + (U - 1) * nw < nchunks; c += U * nw) {
+    // chunks play the role of items: a workgroup step of PS = 4 * kPer
+    // chunks is two half-runs PS apart, alternated as in step_item (with
+    // the 4 waves in place of the threads)
+    constexpr int U = kPer<T>;
+    const int w = threadIdx.x >> 6;
+    const uint64_t ps = (uint64_t)(kBlock / 64) * U;
+    auto chunk = [&](uint64_t base, int j) {
+        return base + (uint64_t)(j & 1) * ps + (uint64_t)(j >> 1) * (kBlock / 64) + w;
+    };
+    for (uint64_t s = blockIdx.x; step_base(s, ps) < nchunks; s += gridDim.x) {
+        const uint64_t c0 = step_base(s, ps);
         V v[U];
         uint64_t e[U];
 #pragma unroll
         for (int j = 0; j < U; ++j) {
-            e[j] = (expand(c + j * nw, hi) << 6) | (uint64_t)lane;
-            v[j] = amp[e[j]];
+            const uint64_t c = chunk(c0, j);
+            e[j] = (expand(c < nchunks ? c : nchunks - 1, hi) << 6) | (uint64_t)lane;
+            v[j] = ldnt(amp + e[j]);
         }
 #pragma unroll
         for (int j = 0; j < U; ++j) {
+            // the chunk test is uniform over the wave, so every lane joins the exchange
             V p;
             p.x = xchg<TT>(v[j].x, lane);
             p.y = xchg<TT>(v[j].y, lane);
             const V r = cmac2<T, V>(sr, si, v[j], pr, pi, p);
-            if (ok) amp[e[j]] = r;
+            if (ok && chunk(c0, j) < nchunks) stnt(amp + e[j], r);
         }
-    }
-    for (; c < nchunks; c += nw) {
-        const uint64_t e = (expand(c, hi) << 6) | (uint64_t)lane;
-        const V v = amp[e];
-        V p;
-        p.x = xchg<TT>(v.x, lane);
-        p.y = xchg<TT>(v.y, lane);
-        const V r = cmac2<T, V>(sr, si, v, pr, pi, p);
-        if (ok) amp[e] = r;
     }
 }
 
@@ -160,12 +161,25 @@ __global__ __launch_bounds__(kBlock) void k_not(typename C2<T>::type* __restrict
                                                 uint64_t npairs, uint64_t tb, BitInsert ins)
 {
     using V = typename C2<T>::type;
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < npairs; i += stride) {
-        const uint64_t a = expand(i, ins);
-        const V x = amp[a], y = amp[a + tb];
-        amp[a] = y;
-        amp[a + tb] = x;
+    constexpr int P = kPer<T> / 2;
+    const uint64_t ps = (uint64_t)kBlock * P;
+    for (uint64_t s = blockIdx.x; step_base(s, ps) < npairs; s += gridDim.x) {
+        const uint64_t c = step_base(s, ps);
+        uint64_t a[P];
+        V x[P], y[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const uint64_t i = step_item(c, j, ps);
+            a[j] = expand(i < npairs ? i : npairs - 1, ins);
+            x[j] = ldnt(amp + a[j]);
+            y[j] = ldnt(amp + a[j] + tb);
+        }
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+            if (step_item(c, j, ps) < npairs) {
+                stnt(amp + a[j], y[j]);
+                stnt(amp + a[j] + tb, x[j]);
+            }
     }
 }
 
@@ -177,11 +191,23 @@ __global__ __launch_bounds__(kBlock) void k_phase(typename C2<T>::type* __restri
                                                   T fr, T fi)
 {
     using V = typename C2<T>::type;
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) {
-        const uint64_t e = expand(i, ins);
-        if (skip != 0 && (e & skip) == skip) continue;
-        amp[e] = cmul<T, V>(fr, fi, amp[e]);
+    constexpr int U = kPer<T>;
+    const uint64_t ps = (uint64_t)kBlock * U;
+    for (uint64_t s = blockIdx.x; step_base(s, ps) < count; s += gridDim.x) {
+        const uint64_t c = step_base(s, ps);
+        uint64_t e[U];
+        bool on[U];
+        V v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t i = step_item(c, j, ps);
+            e[j] = expand(i < count ? i : count - 1, ins);
+            on[j] = i < count && !(skip != 0 && (e[j] & skip) == skip);
+            if (on[j]) v[j] = ldnt(amp + e[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (on[j]) stnt(amp + e[j], cmul<T, V>(fr, fi, v[j]));
     }
 }
 
@@ -200,25 +226,42 @@ __global__ __launch_bounds__(kBlock) void k_dm_gate(typename C2<T>::type* __rest
     T uc[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) uc[k] = (k & 1) ? -u.m[k] : u.m[k];
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x; g < ngroups; g += stride) {
-        const uint64_t b = expand(g, ins);
-        const bool R = (b & rmask) == rmask;
-        const bool Cc = (b & cmask) == cmask;
-        if (!R && !Cc) continue;
-        V m00 = rho[b], m10 = rho[b + tb], m01 = rho[b + cb], m11 = rho[b + tb + cb];
-        if (R) {  // U on the row index, for each column
-            apply2<T, V>(u.m, m00, m10);
-            apply2<T, V>(u.m, m01, m11);
+    constexpr int G = kPer<T> / 4;
+    const uint64_t ps = (uint64_t)kBlock * G;
+    for (uint64_t s = blockIdx.x; step_base(s, ps) < ngroups; s += gridDim.x) {
+        const uint64_t c = step_base(s, ps);
+        uint64_t b[G];
+        bool R[G], Cc[G];
+        V m00[G], m10[G], m01[G], m11[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const uint64_t g = step_item(c, j, ps);
+            b[j] = expand(g < ngroups ? g : ngroups - 1, ins);
+            R[j] = g < ngroups && (b[j] & rmask) == rmask;
+            Cc[j] = g < ngroups && (b[j] & cmask) == cmask;
+            if (R[j] || Cc[j]) {
+                m00[j] = ldnt(rho + b[j]);
+                m10[j] = ldnt(rho + b[j] + tb);
+                m01[j] = ldnt(rho + b[j] + cb);
+                m11[j] = ldnt(rho + b[j] + tb + cb);
+            }
         }
-        if (Cc) {  // conj(U) on the column index, for each row
-            apply2<T, V>(uc, m00, m01);
-            apply2<T, V>(uc, m10, m11);
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            if (!R[j] && !Cc[j]) continue;
+            if (R[j]) {  // U on the row index, for each column
+                apply2<T, V>(u.m, m00[j], m10[j]);
+                apply2<T, V>(u.m, m01[j], m11[j]);
+            }
+            if (Cc[j]) {  // conj(U) on the column index, for each row
+                apply2<T, V>(uc, m00[j], m01[j]);
+                apply2<T, V>(uc, m10[j], m11[j]);
+            }
+            stnt(rho + b[j], m00[j]);
+            stnt(rho + b[j] + tb, m10[j]);
+            stnt(rho + b[j] + cb, m01[j]);
+            stnt(rho + b[j] + tb + cb, m11[j]);
         }
-        rho[b] = m00;
-        rho[b + tb] = m10;
-        rho[b + cb] = m01;
-        rho[b + tb + cb] = m11;
     }
 }
 
@@ -235,33 +278,50 @@ __global__ __launch_bounds__(kBlock) void k_dm_channel(typename C2<T>::type* __r
                                                        BitInsert ins, double p0, double p1, double f)
 {
     using V = typename C2<T>::type;
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x; g < ngroups; g += stride) {
-        const uint64_t b = expand(g, ins);
-        V m10 = rho[b + tb], m01 = rho[b + cb];
-        m10.x = (T)(f * (double)m10.x);
-        m10.y = (T)(f * (double)m10.y);
-        m01.x = (T)(f * (double)m01.x);
-        m01.y = (T)(f * (double)m01.y);
-        rho[b + tb] = m10;
-        rho[b + cb] = m01;
-        if constexpr (CH != QS_DEPHASING) {
-            V m00 = rho[b], m11 = rho[b + tb + cb];
-            const double a0 = m00.x, a1 = m00.y, d0 = m11.x, d1 = m11.y;
-            V n00, n11;
-            if constexpr (CH == QS_DEPOLARISING) {  // p0 = 1 - 2p/3, p1 = 2p/3
-                n00.x = (T)(p0 * a0 + p1 * d0);
-                n00.y = (T)(p0 * a1 + p1 * d1);
-                n11.x = (T)(p0 * d0 + p1 * a0);
-                n11.y = (T)(p0 * d1 + p1 * a1);
-            } else {  // damping: p0 = gamma, p1 = 1 - gamma
-                n00.x = (T)(a0 + p0 * d0);
-                n00.y = (T)(a1 + p0 * d1);
-                n11.x = (T)(p1 * d0);
-                n11.y = (T)(p1 * d1);
+    constexpr int G = kPer<T> / 4;
+    const uint64_t ps = (uint64_t)kBlock * G;
+    for (uint64_t s = blockIdx.x; step_base(s, ps) < ngroups; s += gridDim.x) {
+        const uint64_t c = step_base(s, ps);
+        uint64_t b[G];
+        V m00[G], m10[G], m01[G], m11[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const uint64_t g = step_item(c, j, ps);
+            b[j] = expand(g < ngroups ? g : ngroups - 1, ins);
+            m10[j] = ldnt(rho + b[j] + tb);
+            m01[j] = ldnt(rho + b[j] + cb);
+            if constexpr (CH != QS_DEPHASING) {
+                m00[j] = ldnt(rho + b[j]);
+                m11[j] = ldnt(rho + b[j] + tb + cb);
             }
-            rho[b] = n00;
-            rho[b + tb + cb] = n11;
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            if (step_item(c, j, ps) >= ngroups) continue;
+            V n10, n01;
+            n10.x = (T)(f * (double)m10[j].x);
+            n10.y = (T)(f * (double)m10[j].y);
+            n01.x = (T)(f * (double)m01[j].x);
+            n01.y = (T)(f * (double)m01[j].y);
+            stnt(rho + b[j] + tb, n10);
+            stnt(rho + b[j] + cb, n01);
+            if constexpr (CH != QS_DEPHASING) {
+                const double a0 = m00[j].x, a1 = m00[j].y, d0 = m11[j].x, d1 = m11[j].y;
+                V n00, n11;
+                if constexpr (CH == QS_DEPOLARISING) {  // p0 = 1 - 2p/3, p1 = 2p/3
+                    n00.x = (T)(p0 * a0 + p1 * d0);
+                    n00.y = (T)(p0 * a1 + p1 * d1);
+                    n11.x = (T)(p0 * d0 + p1 * a0);
+                    n11.y = (T)(p0 * d1 + p1 * a1);
+                } else {  // damping: p0 = gamma, p1 = 1 - gamma
+                    n00.x = (T)(a0 + p0 * d0);
+                    n00.y = (T)(a1 + p0 * d1);
+                    n11.x = (T)(p1 * d0);
+                    n11.y = (T)(p1 * d1);
+                }
+                stnt(rho + b[j], n00);
+                stnt(rho + b[j] + tb + cb, n11);
+            }
         }
     }
 }
@@ -314,14 +374,25 @@ __global__ __launch_bounds__(kBlock) void k_prob_sv(const typename C2<T>::type* 
                                                     uint64_t len, int q, double* partials)
 {
     using V = typename C2<T>::type;
+    constexpr int U = kPer<T>;
     NSum s0 = {0.0, 0.0}, s1 = {0.0, 0.0};
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < len; i += stride) {
-        const V a = amp[i];
-        const double p = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
-        const bool one = (q >= 0) && ((i >> q) & 1);
-        nadd(s0, one ? 0.0 : p);
-        nadd(s1, one ? p : 0.0);
+    const uint64_t ps = (uint64_t)kBlock * U;
+    for (uint64_t s = blockIdx.x; step_base(s, ps) < len; s += gridDim.x) {
+        const uint64_t c = step_base(s, ps);
+        V v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t i = step_item(c, j, ps);
+            v[j] = ldnt(amp + (i < len ? i : len - 1));
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t i = step_item(c, j, ps);
+            const double p = i < len ? (double)v[j].x * (double)v[j].x + (double)v[j].y * (double)v[j].y : 0.0;
+            const bool one = (q >= 0) && ((i >> q) & 1);
+            nadd(s0, one ? 0.0 : p);
+            nadd(s1, one ? p : 0.0);
+        }
     }
     block_store2(s0, s1, partials);
 }
@@ -379,18 +450,27 @@ __global__ __launch_bounds__(kBlock) void k_collapse_sv(typename C2<T>::type* __
                                                         uint64_t len, int q, int outcome, double scale)
 {
     using V = typename C2<T>::type;
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < len; i += stride) {
-        const bool keep = (int)((i >> q) & 1) == outcome;
-        V v;
-        v.x = T(0);
-        v.y = T(0);
-        if (keep) {
-            const V a = amp[i];
-            v.x = (T)(scale * (double)a.x);
-            v.y = (T)(scale * (double)a.y);
+    constexpr int U = kPer<T>;
+    const uint64_t ps = (uint64_t)kBlock * U;
+    for (uint64_t s = blockIdx.x; step_base(s, ps) < len; s += gridDim.x) {
+        const uint64_t c = step_base(s, ps);
+        V v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t i = step_item(c, j, ps);
+            v[j].x = T(0);
+            v[j].y = T(0);
+            if (i < len && (int)((i >> q) & 1) == outcome) v[j] = ldnt(amp + i);
         }
-        amp[i] = v;
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t i = step_item(c, j, ps);
+            if (i >= len) continue;
+            V r;
+            r.x = (T)(scale * (double)v[j].x);
+            r.y = (T)(scale * (double)v[j].y);
+            stnt(amp + i, r);
+        }
     }
 }
 
@@ -402,18 +482,28 @@ __global__ __launch_bounds__(kBlock) void k_collapse_dm(typename C2<T>::type* __
                                                         double scale)
 {
     using V = typename C2<T>::type;
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < len; i += stride) {
-        const bool keep = (int)((i >> q) & 1) == outcome && (int)((i >> (q + N)) & 1) == outcome;
-        V v;
-        v.x = T(0);
-        v.y = T(0);
-        if (keep) {
-            const V a = rho[i];
-            v.x = (T)(scale * (double)a.x);
-            v.y = (T)(scale * (double)a.y);
+    constexpr int U = kPer<T>;
+    const uint64_t ps = (uint64_t)kBlock * U;
+    for (uint64_t s = blockIdx.x; step_base(s, ps) < len; s += gridDim.x) {
+        const uint64_t c = step_base(s, ps);
+        V v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t i = step_item(c, j, ps);
+            v[j].x = T(0);
+            v[j].y = T(0);
+            const bool keep = (int)((i >> q) & 1) == outcome && (int)((i >> (q + N)) & 1) == outcome;
+            if (i < len && keep) v[j] = ldnt(rho + i);
         }
-        rho[i] = v;
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t i = step_item(c, j, ps);
+            if (i >= len) continue;
+            V r;
+            r.x = (T)(scale * (double)v[j].x);
+            r.y = (T)(scale * (double)v[j].y);
+            stnt(rho + i, r);
+        }
     }
 }
 
@@ -452,8 +542,8 @@ hipError_t launch_gate(const Launch& L, void* amp, int nbits, int t, const int* 
         }
         const BitInsert hi = make_insert(hp, nh, ones);
         const uint64_t nchunks = 1ull << (nbits - 6 - nh);
-        // one wave per chunk, 4 chunks per wave per iteration
-        const int grid = grid_for(nchunks * 64, 4);
+        // one wave-row of 64 lanes per chunk, kPer chunks per wave per step
+        const int grid = grid_for(nchunks * 64, kPer<T>);
         switch (t) {
 #define QS_LOW(TT) case TT: hipLaunchKernelGGL((k_gate_low<T, TT>), dim3(grid), dim3(kBlock), 0, L.stream, \
                                          (V*)amp, nchunks, hi, lowmask, u); break;
@@ -472,7 +562,7 @@ hipError_t launch_gate(const Launch& L, void* amp, int nbits, int t, const int* 
     pos[nc] = t;
     const BitInsert ins = make_insert(pos, nc + 1, ones);
     const uint64_t npairs = 1ull << (nbits - 1 - nc);
-    hipLaunchKernelGGL(k_gate_pair<T>, dim3(grid_for(npairs, 2)), dim3(kBlock), 0, L.stream,
+    hipLaunchKernelGGL(k_gate_pair<T>, dim3(grid_for(npairs, kPer<T> / 2)), dim3(kBlock), 0, L.stream,
                        (V*)amp, npairs, 1ull << t, ins, u);
     if (klass) *klass = QS_K_GATE;
     return hipGetLastError();
@@ -491,7 +581,7 @@ hipError_t launch_not(const Launch& L, void* amp, int nbits, int t, const int* c
     pos[nc] = t;
     const BitInsert ins = make_insert(pos, nc + 1, ones);
     const uint64_t npairs = 1ull << (nbits - 1 - nc);
-    hipLaunchKernelGGL(k_not<T>, dim3(grid_for(npairs, 2)), dim3(kBlock), 0, L.stream,
+    hipLaunchKernelGGL(k_not<T>, dim3(grid_for(npairs, kPer<T> / 2)), dim3(kBlock), 0, L.stream,
                        (V*)amp, npairs, 1ull << t, ins);
     return hipGetLastError();
 }
@@ -507,7 +597,7 @@ hipError_t launch_phase(const Launch& L, void* amp, int nbits, uint64_t mask, ui
         if ((mask >> q) & 1) pos[np++] = q;
     const BitInsert ins = make_insert(pos, np, mask);
     const uint64_t count = 1ull << (nbits - np);
-    hipLaunchKernelGGL(k_phase<T>, dim3(grid_for(count, 2)), dim3(kBlock), 0, L.stream,
+    hipLaunchKernelGGL(k_phase<T>, dim3(grid_for(count, kPer<T>)), dim3(kBlock), 0, L.stream,
                        (V*)amp, count, ins, skip, (T)fre, (T)fim);
     return hipGetLastError();
 }
@@ -522,7 +612,7 @@ hipError_t launch_dm_gate(const Launch& L, void* rho, int N, int t, const int* c
     uint64_t rmask = 0;
     for (int k = 0; k < nc; ++k) rmask |= 1ull << ctrls[k];
     const uint64_t ngroups = 1ull << (2 * N - 2);
-    hipLaunchKernelGGL(k_dm_gate<T>, dim3(grid_for(ngroups, 2)), dim3(kBlock), 0, L.stream,
+    hipLaunchKernelGGL(k_dm_gate<T>, dim3(grid_for(ngroups, kPer<T> / 4)), dim3(kBlock), 0, L.stream,
                        (V*)rho, ngroups, 1ull << t, 1ull << (t + N), ins, rmask, rmask << N, u);
     return hipGetLastError();
 }
@@ -534,7 +624,7 @@ hipError_t launch_dm_channel(const Launch& L, void* rho, int N, int t, int chann
     const int pos[2] = {t, t + N};
     const BitInsert ins = make_insert(pos, 2, 0);
     const uint64_t ngroups = 1ull << (2 * N - 2);
-    const dim3 grid(grid_for(ngroups, 2)), block(kBlock);
+    const dim3 grid(grid_for(ngroups, kPer<T> / 4)), block(kBlock);
     const uint64_t tb = 1ull << t, cb = 1ull << (t + N);
     switch (channel) {
     case QS_DEPHASING:
@@ -560,7 +650,7 @@ hipError_t launch_prob_sv(const Launch& L, const void* amp, int nbits, int q, do
 {
     using V = typename C2<T>::type;
     const uint64_t len = 1ull << nbits;
-    int grid = grid_for(len, 8);
+    int grid = grid_for(len, kPer<T>);
     if (grid > kReduceBlocks) grid = kReduceBlocks;
     hipLaunchKernelGGL(k_prob_sv<T>, dim3(grid), dim3(kBlock), 0, L.stream, (const V*)amp, len, q,
                        partials);
@@ -587,7 +677,7 @@ hipError_t launch_collapse_sv(const Launch& L, void* amp, int nbits, int q, int 
 {
     using V = typename C2<T>::type;
     const uint64_t len = 1ull << nbits;
-    hipLaunchKernelGGL(k_collapse_sv<T>, dim3(grid_for(len, 4)), dim3(kBlock), 0, L.stream, (V*)amp,
+    hipLaunchKernelGGL(k_collapse_sv<T>, dim3(grid_for(len, kPer<T>)), dim3(kBlock), 0, L.stream, (V*)amp,
                        len, q, outcome, scale);
     return hipGetLastError();
 }
@@ -597,7 +687,7 @@ hipError_t launch_collapse_dm(const Launch& L, void* rho, int N, int q, int outc
 {
     using V = typename C2<T>::type;
     const uint64_t len = 1ull << (2 * N);
-    hipLaunchKernelGGL(k_collapse_dm<T>, dim3(grid_for(len, 4)), dim3(kBlock), 0, L.stream, (V*)rho,
+    hipLaunchKernelGGL(k_collapse_dm<T>, dim3(grid_for(len, kPer<T>)), dim3(kBlock), 0, L.stream, (V*)rho,
                        len, q, N, outcome, scale);
     return hipGetLastError();
 }
