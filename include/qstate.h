@@ -158,6 +158,17 @@ qs_status qs_calc_prob_of_outcome(qs_reg r, int qubit, int outcome, double* out)
  * vector) or 1/p (density matrix), with the scale formed in double
  * precision.  *prob receives P(outcome).  Synchronous. */
 qs_status qs_measure(qs_reg r, int qubit, double u01, int* outcome, double* prob);
+/* Measure every qubit, 0..n-1 in order, with draws u01[0..n-1] in [0, 1):
+ * the result is that of n successive qs_measure calls (each qubit's
+ * probability taken on the state its predecessors left; the outcomes are
+ * the same up to draws within rounding of p0), computed from compensated
+ * histograms of the unmeasured state (one full read, then reads of the
+ * surviving 2^-10, 2^-20, ... of it) and one write-only collapse to the
+ * measured basis entry.  outcomes[k] and probs[k] (either may be NULL)
+ * receive qubit k's outcome and P(outcome).  u01 is read during the call
+ * only.  QS_E_ARG for a NULL u01, a draw outside [0, 1) or an outcome of
+ * zero probability; the register is unchanged then.  Synchronous. */
+qs_status qs_measure_all(qs_reg r, const double* u01, int* outcomes, double* probs);
 
 /* ---- circuits: recorded gate lists with optional gate fusion ------------ */
 

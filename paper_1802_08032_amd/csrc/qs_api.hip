@@ -219,6 +219,18 @@ qs_status check_channel(qs_reg r, int channel, int t, double p)
 
 // Probabilities: out[0] = sum over bit q == 0, out[1] = bit q == 1 (q < 0:
 // total in out[0]).  Synchronous.
+// Neumaier compensated sum on the host.
+struct HSum {
+    double s, c;
+};
+
+void hadd(HSum& a, double v)
+{
+    const double t = a.s + v;
+    a.c += (fabs(a.s) >= fabs(v)) ? ((a.s - t) + v) : ((v - t) + a.s);
+    a.s = t;
+}
+
 qs_status probs(qs_reg r, int q, double out[2])
 {
     const qs::Launch L = launch_of(r);
@@ -488,8 +500,8 @@ qs_status qs_init_basis(qs_reg r, uint64_t index)
     const uint64_t pos = r->kind == QS_DENSITY ? index + (index << r->n) : index;
     const qs::Launch L = launch_of(r);
     return qs::profiled(r, QS_K_INIT, [&](int*) {
-        return r->prec == QS_C128 ? qs::launch_init_basis<double>(L, r->amp, len, pos)
-                                  : qs::launch_init_basis<float>(L, r->amp, len, pos);
+        return r->prec == QS_C128 ? qs::launch_init_basis<double>(L, r->amp, len, pos, 1.0, 0.0)
+                                  : qs::launch_init_basis<float>(L, r->amp, len, pos, 1.0, 0.0);
     });
 }
 
@@ -653,6 +665,127 @@ qs_status qs_measure(qs_reg r, int qubit, double u01, int* outcome, double* prob
     if (s) return s;
     if (outcome) *outcome = o;
     if (prob) *prob = p;
+    return QS_OK;
+}
+
+// Measure qubits 0..n-1 in turn.  Step k's numbers are those qs_measure
+// would compute on the state left by steps 0..k-1: with W(S) the sum of
+// |alpha|^2 (state vector) or of diagonal entries (density matrix) of the
+// ORIGINAL state over the set S of indices that agree with the outcomes so
+// far, and g = product of 1/p over those steps, p0 = W(S, bit k = 0) * g
+// clamped to [0, 1], outcome = (u < p0) ? 0 : 1, p = W(S, bit k = outcome) * g.
+// The W sums come from compensated histograms over 10 qubits at a time (the
+// first over the whole state, each later one over the surviving subspace),
+// and the state is collapsed once at the end: the measured basis entry
+// times sqrt(g) (state vector) or g (density matrix), every other entry 0.
+qs_status qs_measure_all(qs_reg r, const double* u01, int* outcomes, double* probs)
+{
+    QS_CHECK_REG(r);
+    if (!u01) return qs::set_error(QS_E_ARG, "NULL draws");
+    const int n = r->n;
+    for (int k = 0; k < n; ++k)
+        if (!(u01[k] >= 0.0 && u01[k] < 1.0)) return qs::set_error(QS_E_ARG, "draw must lie in [0, 1)");
+    const qs::Launch L = launch_of(r);
+    const bool dbl = r->prec == QS_C128;
+    std::vector<int> out_o(n);
+    std::vector<double> out_p(n);
+    double g = 1.0;
+    uint64_t pattern = 0;
+    // one step of the walk over bins: w[b] = (sum, compensation) of W over
+    // the bins of the current group; bits below k of b must match `sub`
+    auto walk = [&](const std::vector<double>& w, int nbins_log, int first_qubit) -> qs_status {
+        for (int k = 0; k < nbins_log; ++k) {
+            const uint64_t sub = (pattern >> first_qubit) & ((1ull << k) - 1);
+            HSum w0 = {0.0, 0.0}, w1 = {0.0, 0.0};
+            for (uint64_t b = 0; b < (1ull << nbins_log); ++b) {
+                if ((b & ((1ull << k) - 1)) != sub) continue;
+                HSum& acc = ((b >> k) & 1) ? w1 : w0;
+                hadd(acc, w[2 * b]);
+                hadd(acc, w[2 * b + 1]);
+            }
+            double p0 = (w0.s + w0.c) * g;
+            if (p0 < 0.0) p0 = 0.0;
+            if (p0 > 1.0) p0 = 1.0;
+            const int q = first_qubit + k;
+            const int o = (u01[q] < p0) ? 0 : 1;
+            const double p = ((o ? w1.s + w1.c : w0.s + w0.c)) * g;
+            if (!(p > 0.0)) return qs::set_error(QS_E_ARG, "selected outcome has zero probability");
+            out_o[q] = o;
+            out_p[q] = p;
+            g /= p;
+            pattern |= (uint64_t)o << q;
+        }
+        return QS_OK;
+    };
+    qs_status s = QS_OK;
+    if (r->kind == QS_DENSITY) {
+        const uint64_t dim = 1ull << n;
+        double* dd = nullptr;
+        QS_HIP(hipMallocAsync((void**)&dd, dim * sizeof(double), r->stream));
+        s = qs::profiled(r, QS_K_REDUCE, [&](int*) {
+            return dbl ? qs::launch_diag_dm<double>(L, r->amp, n, dd) : qs::launch_diag_dm<float>(L, r->amp, n, dd);
+        });
+        std::vector<double> diag(dim);
+        if (!s) {
+            hipError_t e = hipMemcpyAsync(diag.data(), dd, dim * sizeof(double), hipMemcpyDeviceToHost, r->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+            if (e != hipSuccess) s = qs::hip_error(e, "diagonal copy");
+        }
+        (void)hipFreeAsync(dd, r->stream);
+        if (s) return s;
+        std::vector<double> w(2 * dim, 0.0);  // (value, 0) pairs: the walk over all N qubits at once
+        for (uint64_t j = 0; j < dim; ++j) w[2 * j] = diag[j];
+        if ((s = walk(w, n, 0))) return s;
+    } else {
+        const int kb = qs::kHistBlocks;
+        double* buf = nullptr;
+        QS_HIP(hipMallocAsync((void**)&buf, (2 * 1024 * (size_t)kb + 2 * 1024) * sizeof(double), r->stream));
+        double* dev_out = buf + 2 * 1024 * (size_t)kb;
+        std::vector<double> w;
+        for (int shift = 0; shift < n && !s; shift += 10) {
+            const int mb = std::min(10, n - shift);
+            s = qs::profiled(r, QS_K_REDUCE, [&](int*) {
+                return dbl ? qs::launch_hist_sv<double>(L, r->amp, r->nbits, shift, pattern, mb, buf, kb, dev_out)
+                           : qs::launch_hist_sv<float>(L, r->amp, r->nbits, shift, pattern, mb, buf, kb, dev_out);
+            });
+            if (s) break;
+            w.assign(2ull << mb, 0.0);
+            hipError_t e = hipMemcpyAsync(w.data(), dev_out, w.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                          r->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+            if (e != hipSuccess) s = qs::hip_error(e, "histogram copy");
+            if (!s) s = walk(w, mb, shift);
+        }
+        (void)hipFreeAsync(buf, r->stream);
+        if (s) return s;
+    }
+    // the kept entry, scaled in double precision
+    const uint64_t pos = r->kind == QS_DENSITY ? pattern + (pattern << n) : pattern;
+    double re = 0.0, im = 0.0;
+    if (dbl) {
+        double v[2];
+        QS_HIP(hipMemcpyAsync(v, (const double*)r->amp + 2 * pos, sizeof(v), hipMemcpyDeviceToHost, r->stream));
+        if ((s = sync_stream(r))) return s;
+        re = v[0];
+        im = v[1];
+    } else {
+        float v[2];
+        QS_HIP(hipMemcpyAsync(v, (const float*)r->amp + 2 * pos, sizeof(v), hipMemcpyDeviceToHost, r->stream));
+        if ((s = sync_stream(r))) return s;
+        re = v[0];
+        im = v[1];
+    }
+    const double scale = r->kind == QS_DENSITY ? g : sqrt(g);
+    s = qs::profiled(r, QS_K_COLLAPSE, [&](int*) {
+        const uint64_t len = 1ull << r->nbits;
+        return dbl ? qs::launch_init_basis<double>(L, r->amp, len, pos, re * scale, im * scale)
+                   : qs::launch_init_basis<float>(L, r->amp, len, pos, re * scale, im * scale);
+    });
+    if (s) return s;
+    for (int k = 0; k < n; ++k) {
+        if (outcomes) outcomes[k] = out_o[k];
+        if (probs) probs[k] = out_p[k];
+    }
     return QS_OK;
 }
 

@@ -31,7 +31,9 @@ struct Launch {
 BitInsert make_insert(const int* positions, int count, uint64_t ones);
 
 // --- state-vector kernels -------------------------------------------------
-template <typename T> hipError_t launch_init_basis(const Launch& L, void* amp, uint64_t len, uint64_t index);
+// Every amplitude 0 except `index`, which becomes (re, im).  Write-only.
+template <typename T> hipError_t launch_init_basis(const Launch& L, void* amp, uint64_t len, uint64_t index,
+                                                   double re, double im);
 template <typename T> hipError_t launch_gate(const Launch& L, void* amp, int nbits, int t,
                                              const int* ctrls, int nc, const Mat2<T>& u, int* klass);
 template <typename T> hipError_t launch_not(const Launch& L, void* amp, int nbits, int t,
@@ -60,5 +62,17 @@ template <typename T> hipError_t launch_collapse_sv(const Launch& L, void* amp, 
                                                     int outcome, double scale);
 template <typename T> hipError_t launch_collapse_dm(const Launch& L, void* rho, int N, int q,
                                                     int outcome, double scale);
+
+// --- measure-all ----------------------------------------------------------
+// |alpha|^2 of the items j < 2^(nbits - shift) at index fixed + (j << shift),
+// summed per bin j mod 2^mbits (mbits <= 10) with compensated sums: dev_out
+// receives 2^mbits (sum, compensation) pairs.  `partials` holds
+// 2 * 1024 * max_blocks doubles.
+constexpr int kHistBlocks = 256;
+template <typename T> hipError_t launch_hist_sv(const Launch& L, const void* amp, int nbits, int shift,
+                                                uint64_t fixed, int mbits, double* partials, int max_blocks,
+                                                double* dev_out);
+// Real parts of the 2^N diagonal entries of a density matrix, as doubles.
+template <typename T> hipError_t launch_diag_dm(const Launch& L, const void* rho, int N, double* dev_out);
 
 }  // namespace qs

@@ -28,17 +28,17 @@ BitInsert make_insert(const int* positions, int count, uint64_t ones)
 namespace {
 
 // ---------------------------------------------------------------------------
-// Initialisation: every amplitude 0 except `index`, which is 1.
+// Initialisation: every amplitude 0 except `index`, which is (re, im).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_init_basis(typename C2<T>::type* __restrict__ amp,
-                                                       uint64_t len, uint64_t index)
+                                                       uint64_t len, uint64_t index, T re, T im)
 {
     using V = typename C2<T>::type;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < len; i += stride) {
         V v;
-        v.x = (i == index) ? T(1) : T(0);
-        v.y = T(0);
+        v.x = (i == index) ? re : T(0);
+        v.y = (i == index) ? im : T(0);
         amp[i] = v;
     }
 }
@@ -507,17 +507,115 @@ __global__ __launch_bounds__(kBlock) void k_collapse_dm(typename C2<T>::type* __
     }
 }
 
+// ---------------------------------------------------------------------------
+// Measure-all.  The items j < count of a subspace sit at index
+// fixed + (j << shift); item j falls in bin j mod 2^mbits (mbits <= 10).
+// Each block writes 2^mbits Neumaier partials (sum, compensation) of
+// |alpha|^2.  Steps are multiples of 1024 items, so with the alternating
+// step order the thread's j-th element lies in bin ((j >> 1) & 3) * kBlock +
+// tid (mod 2^mbits): four accumulators per thread, folded through LDS.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_hist_sv(const typename C2<T>::type* __restrict__ amp,
+                                                    uint64_t count, int shift, uint64_t fixed, int mbits,
+                                                    double* __restrict__ partials)
+{
+    using V = typename C2<T>::type;
+    constexpr int U = kPer<T>;
+    static_assert((kBlock * U / 2) % 1024 == 0, "steps must be whole multiples of 1024 bins");
+    __shared__ double ls[4 * kBlock], lc[4 * kBlock];
+    NSum acc[4] = {};
+    const uint64_t ps = (uint64_t)kBlock * U;
+    for (uint64_t s = blockIdx.x; step_base(s, ps) < count; s += gridDim.x) {
+        const uint64_t c = step_base(s, ps);
+        V v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t item = step_item(c, j, ps);
+            v[j] = ldnt(amp + (fixed + ((item < count ? item : count - 1) << shift)));
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const double p = step_item(c, j, ps) < count
+                                 ? (double)v[j].x * (double)v[j].x + (double)v[j].y * (double)v[j].y
+                                 : 0.0;
+            nadd(acc[(j >> 1) & 3], p);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        ls[k * kBlock + threadIdx.x] = acc[k].s;
+        lc[k * kBlock + threadIdx.x] = acc[k].c;
+    }
+    __syncthreads();
+    const int nb = 1 << mbits;
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
+        NSum a = {0.0, 0.0};
+        for (int e = b; e < 4 * kBlock; e += nb) a = nmerge(a, NSum{ls[e], lc[e]});
+        partials[2 * ((uint64_t)blockIdx.x * nb + b)] = a.s;
+        partials[2 * ((uint64_t)blockIdx.x * nb + b) + 1] = a.c;
+    }
+}
+
+// Fold the per-block partials of each bin; out[2b], out[2b+1] = (sum, compensation).
+__global__ __launch_bounds__(kBlock) void k_hist_final(const double* __restrict__ partials, int nblocks,
+                                                       int nb, double* __restrict__ out)
+{
+    const int b = blockIdx.x * kBlock + threadIdx.x;
+    if (b >= nb) return;
+    NSum a = {0.0, 0.0};
+    for (int k = 0; k < nblocks; ++k)
+        a = nmerge(a, NSum{partials[2 * ((uint64_t)k * nb + b)], partials[2 * ((uint64_t)k * nb + b) + 1]});
+    out[2 * b] = a.s;
+    out[2 * b + 1] = a.c;
+}
+
+// Real parts of the diagonal rho[j][j] (entry j (2^N + 1) of the vector).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_diag_dm(const typename C2<T>::type* __restrict__ rho, uint64_t dim,
+                                                    double* __restrict__ out)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < dim; j += stride)
+        out[j] = (double)rho[j * (dim + 1)].x;
+}
+
 }  // namespace
 
 // ===========================================================================
 // Launchers
 
 template <typename T>
-hipError_t launch_init_basis(const Launch& L, void* amp, uint64_t len, uint64_t index)
+hipError_t launch_init_basis(const Launch& L, void* amp, uint64_t len, uint64_t index, double re, double im)
 {
     using V = typename C2<T>::type;
     hipLaunchKernelGGL(k_init_basis<T>, dim3(grid_for(len, 4)), dim3(kBlock), 0, L.stream,
-                       (V*)amp, len, index);
+                       (V*)amp, len, index, (T)re, (T)im);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_hist_sv(const Launch& L, const void* amp, int nbits, int shift, uint64_t fixed, int mbits,
+                          double* partials, int max_blocks, double* dev_out)
+{
+    using V = typename C2<T>::type;
+    const uint64_t count = 1ull << (nbits - shift);
+    int grid = grid_for(count, kPer<T>);
+    if (grid > max_blocks) grid = max_blocks;
+    const int nb = 1 << mbits;
+    hipLaunchKernelGGL(k_hist_sv<T>, dim3(grid), dim3(kBlock), 0, L.stream, (const V*)amp, count, shift, fixed,
+                       mbits, partials);
+    hipLaunchKernelGGL(k_hist_final, dim3((nb + kBlock - 1) / kBlock), dim3(kBlock), 0, L.stream, partials, grid,
+                       nb, dev_out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_diag_dm(const Launch& L, const void* rho, int N, double* dev_out)
+{
+    using V = typename C2<T>::type;
+    const uint64_t dim = 1ull << N;
+    hipLaunchKernelGGL(k_diag_dm<T>, dim3(grid_for(dim, 1)), dim3(kBlock), 0, L.stream, (const V*)rho, dim,
+                       dev_out);
     return hipGetLastError();
 }
 
@@ -693,7 +791,10 @@ hipError_t launch_collapse_dm(const Launch& L, void* rho, int N, int q, int outc
 }
 
 #define QS_INSTANTIATE(T)                                                                              \
-    template hipError_t launch_init_basis<T>(const Launch&, void*, uint64_t, uint64_t);                \
+    template hipError_t launch_init_basis<T>(const Launch&, void*, uint64_t, uint64_t, double, double); \
+    template hipError_t launch_hist_sv<T>(const Launch&, const void*, int, int, uint64_t, int, double*, int, \
+                                          double*);                                                    \
+    template hipError_t launch_diag_dm<T>(const Launch&, const void*, int, double*);                   \
     template hipError_t launch_gate<T>(const Launch&, void*, int, int, const int*, int, const Mat2<T>&, \
                                        int*);                                                          \
     template hipError_t launch_not<T>(const Launch&, void*, int, int, const int*, int);                \

@@ -71,6 +71,7 @@ SIGNATURES = {
     'qs_calc_total_prob': (_i, [_vp, _PD]),
     'qs_calc_prob_of_outcome': (_i, [_vp, _i, _i, _PD]),
     'qs_measure': (_i, [_vp, _i, _d, _PI, _PD]),
+    'qs_measure_all': (_i, [_vp, _PD, _PI, _PD]),
     'qs_circuit_create': (_i, [C.POINTER(_vp)]),
     'qs_circuit_destroy': (_i, [_vp]),
     'qs_circuit_add_unitary': (_i, [_vp, _vp, _i, _i, _vp]),
@@ -278,6 +279,17 @@ class Register:
         o, p = C.c_int(), C.c_double()
         _check(lib().qs_measure(self.h, qubit, float(u01), C.byref(o), C.byref(p)))
         return o.value, p.value
+
+    def measure_all(self, draws):
+        """Measure qubits 0..n-1 in order with one draw each; returns
+        (outcomes, probabilities) as lists."""
+        d = np.ascontiguousarray(np.asarray(draws, dtype=np.float64)[:self.n])
+        if d.size != self.n:
+            raise ValueError(f'need {self.n} draws, got {d.size}')
+        o = (C.c_int * self.n)()
+        p = (C.c_double * self.n)()
+        _check(lib().qs_measure_all(self.h, d.ctypes.data_as(_PD), o, p))
+        return list(o), list(p)
 
 
 class Circuit:

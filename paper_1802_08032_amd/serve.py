@@ -57,7 +57,8 @@ class Result:
 class GpuExecutor:
     """Runs one request: register on the slot's stream, |0..0>, the circuit
     (fused for state vectors of at least `min_fused` qubits, one kernel per
-    op otherwise), then measures qubits 0..n-1 in order."""
+    op otherwise), then measures qubits 0..n-1 in order (one measure-all
+    call: a histogram walk and a single collapse)."""
 
     def __init__(self, env: Q.Env, prec: int = Q.C128, slots: int = 8, fusion: int = 12,
                  min_fused: int = 12, keep_amps: bool = False):
@@ -81,11 +82,7 @@ class GpuExecutor:
                 fused = req.kind == Q.STATEVEC and req.n >= self.min_fused
                 circ.run(reg, self.fusion if fused else 0)
                 circ.close()
-                outs, probs = [], []
-                for q in range(req.n):
-                    o, p = reg.measure(q, float(req.draws[q]))
-                    outs.append(o)
-                    probs.append(p)
+                outs, probs = reg.measure_all(req.draws[:req.n])
                 amps = reg.get_amps() if self.keep_amps else None
             finally:
                 reg.close()

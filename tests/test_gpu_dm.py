@@ -194,3 +194,24 @@ def test_full_size_dm_14_qubits_fused(q, env):
         assert abs(a - np.conj(b)) <= 1e-14
     c.close()
     reg.close()
+
+
+@pytest.mark.parametrize('N', [1, 3, 6])
+def test_dm_measure_all_matches_sequential_measurement(q, env, N):
+    ops = noisy_circuit(N, 4, 20 + N)
+    rho = O.run_dm(N, ops)
+    draws = measurement_draws(6, N, N)
+    ref = rho.copy()
+    outs, probs = [], []
+    for k in range(N):
+        o, p = O.dm_measure(ref, N, k, draws[k])
+        outs.append(o)
+        probs.append(p)
+    reg = q.Register(env, N, q.DENSITY)
+    reg.set_amps(rho)
+    log(f'dm measure_all N={N}')
+    o, p = reg.measure_all(draws)
+    assert o == outs
+    assert max(abs(a - b) for a, b in zip(p, probs)) <= TOL128
+    assert max_abs(reg.get_amps(), ref) <= TOL128
+    reg.close()

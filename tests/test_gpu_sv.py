@@ -297,3 +297,68 @@ def test_compiled_passes_match_oracle(q, env, prec_name, tile, tb, contig):
     assert max_abs(got2, got) == 0.0
     c.close()
     reg.close()
+
+
+def oracle_measure_all(state, n, draws):
+    """The definition: qubits 0..n-1 measured one after another."""
+    ref = state.copy()
+    outs, probs = [], []
+    for k in range(n):
+        o, p = O.sv_measure(ref, n, k, draws[k])
+        outs.append(o)
+        probs.append(p)
+    return ref, outs, probs
+
+
+@pytest.mark.parametrize('n', [1, 2, 5, 10, 11, 13, 21, 23])
+def test_measure_all_matches_sequential_measurement(q, env, n):
+    """One histogram stage (n <= 10), two (11..20) and three (21..30)."""
+    state = random_state(n, 40 + n)
+    draws = measurement_draws(9, n, n)
+    ref, outs, probs = oracle_measure_all(state, n, draws)
+    reg = q.Register(env, n)
+    reg.set_amps(state)
+    log(f'measure_all n={n}')
+    o, p = reg.measure_all(draws)
+    assert o == outs
+    assert max(abs(a - b) for a, b in zip(p, probs)) <= TOL128
+    assert max_abs(reg.get_amps(), ref) <= TOL128
+    reg.close()
+
+
+def test_measure_all_circuit_basis_and_errors(q, env):
+    n = 12
+    ops = layered_circuit(n, 6, 3, mcphase=True)
+    state = O.run_sv(n, ops)
+    draws = measurement_draws(4, 1, n)
+    ref, outs, probs = oracle_measure_all(state, n, draws)
+    reg = q.Register(env, n)
+    reg.set_amps(state)
+    # a draw outside [0, 1) is rejected before anything runs
+    with pytest.raises(q.QStateError):
+        reg.measure_all(np.concatenate([draws[:-1], [1.0]]))
+    assert max_abs(reg.get_amps(), state) == 0.0
+    o, p = reg.measure_all(draws)
+    assert o == outs and max(abs(a - b) for a, b in zip(p, probs)) <= TOL128
+    assert max_abs(reg.get_amps(), ref) <= TOL128
+    # a basis state measures to its own bits with probability 1
+    reg.init_basis(0b101100111001)
+    o, p = reg.measure_all(measurement_draws(4, 2, n))
+    assert o == [(0b101100111001 >> k) & 1 for k in range(n)]
+    assert all(abs(v - 1.0) <= 1e-15 for v in p)
+    reg.close()
+
+
+def test_measure_all_complex64(q, env):
+    n = 15
+    state = random_state(n, 77)
+    draws = measurement_draws(5, 3, n)
+    ref, outs, probs = oracle_measure_all(state, n, draws)
+    reg = q.Register(env, n, q.STATEVEC, q.C64)
+    reg.set_amps(state)
+    o, p = reg.measure_all(draws)
+    # outcomes agree unless a draw falls within the c64 error of p0
+    assert o == outs
+    assert max(abs(a - b) for a, b in zip(p, probs)) <= 1e-5
+    assert fidelity_deficit(ref, reg.get_amps()) <= TOL64_FID
+    reg.close()
