@@ -24,6 +24,8 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+# fused-pass tile shape timed by default: tile qubits, thread bits, contiguous qubits
+DEFAULT_TILE = (13, 9, 4)
 
 
 def log(msg):
@@ -190,7 +192,8 @@ def main():
     ap.add_argument('--warmup', type=int, default=1)
     ap.add_argument('--qubits', type=int, default=32)
     ap.add_argument('--depth', type=int, default=10)
-    ap.add_argument('--tile', default='13,9,4', help="K,TB,contig of the fused passes, or 'auto' (autotuner)")
+    ap.add_argument('--tile', default=','.join(map(str, DEFAULT_TILE)),
+                    help="K,TB,contig of the fused passes, or 'auto' (autotuner)")
     ap.add_argument('--no-extras', action='store_true', help='skip unfused / per-target / CPU legs')
     ap.add_argument('--copy-calibration', action='store_true',
                     help='only run a device copy of 16 GiB (HBM counter calibration)')

@@ -1,6 +1,7 @@
-"""Full-size state vectors in the bench's launch configuration: 32 qubits
-complex128 (64 GiB) and 33 qubits complex64 (64 GiB), fused at the widest
-tile.  Outputs the oracle can produce one by one are sampled: a product
+"""Full-size state vectors: 32 qubits complex128 (64 GiB) and 33 qubits
+complex64 (64 GiB), through the run-time compiled passes in the bench's
+launch configuration (13-qubit tiles of 512 threads, 4 contiguous qubits),
+the generic fused interpreter and the per-gate kernels.  Outputs the oracle can produce one by one are sampled: a product
 state (one Haar gate on every target) followed by CNOTs, phases and a few
 controlled dense gates; and a random circuit followed by its inverse must
 return to |0..0>."""
@@ -14,6 +15,9 @@ from tests.gpu_util import log
 from workloads import Op, haar_unitary, inverse, layered_circuit, product_layer
 
 pytestmark = pytest.mark.gpu
+
+# tile qubits, thread bits and contiguous qubits of the fused passes bench.py times
+from bench import DEFAULT_TILE as BENCH_TILE  # noqa: E402
 
 
 @pytest.fixture(scope='module')
@@ -62,12 +66,15 @@ def test_product_state_and_tail_sampled(q, env, n, prec_name, fusion, tol):
     vecs = np.array([op.u[:, 0] for op in prod])
     idx = sample_indices(n, 2048, n)
     ref = O.amps_after(n, vecs, tail, idx)
-    for mode in (fusion, None):
+    for mode in ('compiled', fusion, None):
         log(f'large n={n} {prec_name} fusion={mode}')
         reg = q.Register(env, n, q.STATEVEC, prec)
         reg.init_zero()
         c = q.Circuit(prod + tail)
-        c.run(reg, mode or 0)
+        if mode == 'compiled':  # the run-time compiled passes, in the bench's tile shape
+            c.run_compiled(reg, *BENCH_TILE[:2], 0, BENCH_TILE[2])
+        else:
+            c.run(reg, mode or 0)
         c.close()
         got = np.array([reg.get_amps(i, 1)[0] for i in idx])
         scale = 2.0 ** (-n / 2)
@@ -83,15 +90,19 @@ def test_product_state_and_tail_sampled(q, env, n, prec_name, fusion, tol):
         assert scale > 0
 
 
-def test_circuit_then_inverse_returns_to_zero_32q(q, env):
+@pytest.mark.parametrize('mode', ['compiled', 'fused'])
+def test_circuit_then_inverse_returns_to_zero_32q(q, env, mode):
     n = 32
     ops = layered_circuit(n, 2, 9, mcphase=True)
     ops = ops + inverse(ops)
-    log('large inverse n=32 fusion=13')
+    log(f'large inverse n=32 {mode}')
     reg = q.Register(env, n)
     reg.init_zero()
     c = q.Circuit(ops)
-    passes = c.run(reg, 13)
+    if mode == 'compiled':
+        passes = c.run_compiled(reg, *BENCH_TILE[:2], 0, BENCH_TILE[2])
+    else:
+        passes = c.run(reg, 13)
     c.close()
     assert passes < len(ops)
     a0 = reg.get_amps(0, 1)[0]
