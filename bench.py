@@ -4,7 +4,7 @@ Workload: one 32-qubit complex128 state vector (64 GiB) and a depth-10
 layered random circuit (per layer: a Haar-random unitary on every qubit, a
 CNOT brick, one phase gate with 3 controls + 1 target), 485 gates.  One step
 = init |0..0> + the whole circuit (fused into HBM round trips of 2^K-
-amplitude tiles by run-time compiled pass kernels; 13-qubit tiles of 512
+amplitude tiles by run-time compiled pass kernels; 12-qubit tiles of 256
 threads by default, or the autotuner's choice with --tile auto) + total
 probability + probability of an outcome + one measurement.  Inputs are seeded and synthetic; the register is resident
 in HBM before the timed region starts.
@@ -25,7 +25,7 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0
 # fused-pass tile shape timed by default: tile qubits, thread bits, contiguous qubits
-DEFAULT_TILE = (13, 9, 4)
+DEFAULT_TILE = (12, 8, 4)
 
 
 def log(msg):

@@ -140,39 +140,74 @@ void plan_phases(PassPlan& P, const std::vector<OpRec>& all, int TB, int RB, int
     P.store = coalesced(P.phases.back().lay, contig) ? P.phases.back().lay : P.phases.front().lay;
 }
 
-}  // namespace
+// One pass's ops: walk the remaining ops in order and take an op when no
+// earlier untaken op shares a qubit with it and its targets lie in S.  With
+// `grow`, S may take in new target qubits up to K of them.
+std::vector<int> scan_pass(const std::vector<OpRec>& all, const std::vector<char>& done, size_t first,
+                           uint64_t& S, int& ssize, int K, int max_ops, bool grow)
+{
+    uint64_t blocked = 0;
+    std::vector<int> take;
+    for (size_t i = first; i < all.size() && (int)take.size() < max_ops; ++i) {
+        if (done[i]) continue;
+        const OpRec& op = all[i];
+        const uint64_t m = qubit_mask(op);
+        if (m & blocked) {
+            blocked |= m;
+            continue;
+        }
+        const uint64_t need = target_mask(op) & ~S;
+        const int extra = __builtin_popcountll(need);
+        if (extra == 0 || (grow && ssize + extra <= K)) {
+            S |= need;
+            ssize += extra;
+            take.push_back((int)i);
+        } else {
+            blocked |= m;
+        }
+    }
+    return take;
+}
 
-// Greedy pass partition: walk the remaining ops in order; take an op when
-// no earlier untaken op shares a qubit with it and its target fits in S.
-std::vector<PassPlan> plan_passes(const std::vector<OpRec>& all, int n, int TB, int RB, int max_phases,
-                                  int max_ops, int contig)
+// Pass partition with candidate tile sets.  Each pass's tile qubits S
+// hold global qubits 0..contig-1 plus K - contig more.  Candidates: S grown
+// greedily from the targets in op order; with windows >= 1 every run of
+// K - contig consecutive qubits; with windows == 2 also every pair of runs
+// n/2 apart (the row and column qubits of a density matrix's vector); the
+// candidate that
+// admits the most ops wins (the greedy one on ties).  Runs suit circuits
+// with nearest-neighbour two-qubit gates, whose light cones are intervals.
+std::vector<PassPlan> partition(const std::vector<OpRec>& all, int n, int TB, int RB, int max_phases,
+                                int max_ops, int contig, int windows)
 {
     const int K = TB + RB;
     std::vector<PassPlan> passes;
     std::vector<char> done(all.size(), 0);
     size_t ndone = 0, first = 0;
+    const uint64_t low = (1ull << contig) - 1;  // first lanes: global qubits 0..contig-1
+    const int w = K - contig;
+    std::vector<uint64_t> cands;
+    auto run = [](int s, int len) { return len > 0 ? ((1ull << len) - 1) << s : 0ull; };
+    if (windows >= 1)
+        for (int s = contig; s + w <= n; ++s) cands.push_back(low | run(s, w));
+    if (windows >= 2) {
+        const int h = n / 2, a = w / 2;
+        for (int s = contig; s + a <= h && s + h + (w - a) <= n; ++s)
+            cands.push_back(low | run(s, a) | run(s + h, w - a));
+    }
     while (ndone < all.size()) {
         while (done[first]) ++first;
-        uint64_t S = (1ull << contig) - 1;  // first lanes: global qubits 0..contig-1
+        uint64_t S = low;
         int ssize = contig;
-        uint64_t blocked = 0;
-        std::vector<int> take;
-        for (size_t i = first; i < all.size() && (int)take.size() < max_ops; ++i) {
-            if (done[i]) continue;
-            const OpRec& op = all[i];
-            const uint64_t m = qubit_mask(op);
-            if (m & blocked) {
-                blocked |= m;
-                continue;
-            }
-            const uint64_t need = target_mask(op) & ~S;
-            const int extra = __builtin_popcountll(need);
-            if (ssize + extra <= K) {
-                S |= need;
-                ssize += extra;
-                take.push_back((int)i);
-            } else {
-                blocked |= m;
+        std::vector<int> take = scan_pass(all, done, first, S, ssize, K, max_ops, true);
+        for (uint64_t c : cands) {
+            uint64_t Sw = c;
+            int sz = __builtin_popcountll(c);
+            std::vector<int> tw = scan_pass(all, done, first, Sw, sz, K, max_ops, false);
+            if (tw.size() > take.size()) {
+                take.swap(tw);
+                S = Sw;
+                ssize = sz;
             }
         }
         // fill S up to K qubits with the lowest unused ones
@@ -193,6 +228,22 @@ std::vector<PassPlan> plan_passes(const std::vector<OpRec>& all, int n, int TB, 
         passes.push_back(std::move(P));
     }
     return passes;
+}
+
+}  // namespace
+
+// Three partitions (greedy only, with runs, with runs and pairs of runs);
+// the one with the fewest passes is kept (a pass costs one HBM round trip
+// of the state), the later one on ties.
+std::vector<PassPlan> plan_passes(const std::vector<OpRec>& all, int n, int TB, int RB, int max_phases,
+                                  int max_ops, int contig)
+{
+    std::vector<PassPlan> best = partition(all, n, TB, RB, max_phases, max_ops, contig, 0);
+    for (int mode = 1; mode <= 2; ++mode) {
+        std::vector<PassPlan> p = partition(all, n, TB, RB, max_phases, max_ops, contig, mode);
+        if (p.size() <= best.size()) best.swap(p);
+    }
+    return best;
 }
 
 namespace {

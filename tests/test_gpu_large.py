@@ -1,6 +1,6 @@
 """Full-size state vectors: 32 qubits complex128 (64 GiB) and 33 qubits
 complex64 (64 GiB), through the run-time compiled passes in the bench's
-launch configuration (13-qubit tiles of 512 threads, 4 contiguous qubits),
+launch configuration (bench.DEFAULT_TILE),
 the generic fused interpreter and the per-gate kernels.  Outputs the oracle can produce one by one are sampled: a product
 state (one Haar gate on every target) followed by CNOTs, phases and a few
 controlled dense gates; and a random circuit followed by its inverse must
