@@ -24,8 +24,10 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
-# fused-pass tile shape timed by default: tile qubits, thread bits, contiguous qubits
+# fused-pass tile shapes: tile qubits, thread bits, contiguous qubits (complex128
+# default, and the complex64 run of the 33-qubit leg)
 DEFAULT_TILE = (12, 8, 4)
+C64_TILE = (13, 9, 4)
 
 
 def log(msg):
@@ -94,6 +96,55 @@ def cpu_baseline(ops_full, n_full, sample_qubits=28, budget_s=12.0):
         'sample': f'first {done} gates of the same circuit on a {n}-qubit complex128 register '
                   f'({dt:.1f} s), scaled by 2^{n_full - n} to {n_full} qubits',
     }
+
+
+def fidelity_deficit(torch, ref, cur, chunk=1 << 28):
+    """1 - |<ref|cur>|^2 of two registers' tensors (cur not renormalised),
+    accumulated in complex128 over chunks."""
+    acc = 0j
+    for s in range(0, ref.numel(), chunk):
+        a = ref[s:s + chunk]
+        b = cur[s:s + chunk].to(torch.complex128)
+        acc += complex(torch.vdot(a, b).item())
+    return 1.0 - abs(acc) ** 2
+
+
+def c64_33q_leg(q, torch, log, depth=10):
+    """33-qubit depth-10 layered circuit (the 32-qubit workload's generator)
+    in complex64 (64 GiB), scored against a complex128 run of the same
+    circuit (128 GiB) by fidelity; both through the compiled passes."""
+    from workloads import layered_circuit
+    n = 33
+    ops = layered_circuit(n, depth, seed=1, mcphase=True)
+    env = q.Env(0)
+    c = q.Circuit(ops)
+    out = {'qubits': n, 'gates': len(ops)}
+    ref = q.Register(env, n, q.STATEVEC, q.C128)
+    ref.init_zero()
+    c.run_compiled(ref, DEFAULT_TILE[0], DEFAULT_TILE[1], 0, DEFAULT_TILE[2])
+    cur = q.Register(env, n, q.STATEVEC, q.C64)
+    cur.init_zero()
+    c.run_compiled(cur, C64_TILE[0], C64_TILE[1], 0, C64_TILE[2])  # compile + warm
+    times = []
+    for _ in range(2):
+        cur.init_zero()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.run_compiled(cur, C64_TILE[0], C64_TILE[1], 0, C64_TILE[2])
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    out['c64_gates_per_s'] = len(ops) / min(times)
+    out['c64_tile'] = list(C64_TILE)
+    out['c64_vs_c128_fidelity_deficit'] = fidelity_deficit(torch, ref.tensor, cur.tensor)
+    out['c128_total_prob_error'] = abs(ref.calc_total_prob() - 1.0)
+    log(f"33q c64: {out['c64_gates_per_s']:.1f} gates/s, fidelity deficit vs c128 "
+        f"{out['c64_vs_c128_fidelity_deficit']:.2e}")
+    cur.close()
+    ref.close()
+    c.close()
+    env.close()
+    torch.cuda.empty_cache()
+    return out
 
 
 def batched_leg(q, torch, log, reps=5):
@@ -335,6 +386,8 @@ def main():
     if not args.no_extras:
         del reg
         torch.cuda.empty_cache()
+        log('33-qubit complex64 vs complex128')
+        out['c64_33q'] = c64_33q_leg(q, torch, log)
         log('batched registers')
         out['batched'] = batched_leg(q, torch, log)
         log('serving')

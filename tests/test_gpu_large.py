@@ -114,3 +114,33 @@ def test_circuit_then_inverse_returns_to_zero_32q(q, env, mode):
     reg.close()
     del reg
     release()
+
+
+def test_c64_33q_fidelity_against_c128_reference(q, env):
+    """The 33-qubit depth-10 circuit in complex64 (64 GiB) against the same
+    circuit in complex128 (128 GiB), both through the compiled passes:
+    fidelity deficit 1 - |<ref|psi>|^2 (psi not renormalised) <= 1e-5."""
+    import torch
+    from bench import C64_TILE, fidelity_deficit
+    n = 33
+    ops = layered_circuit(n, 10, 1, mcphase=True)
+    c = q.Circuit(ops)
+    log('33q c128 reference')
+    ref = q.Register(env, n, q.STATEVEC, q.C128)
+    ref.init_zero()
+    c.run_compiled(ref, BENCH_TILE[0], BENCH_TILE[1], 0, BENCH_TILE[2])
+    assert abs(ref.calc_total_prob() - 1.0) <= 1e-12
+    log('33q c64')
+    cur = q.Register(env, n, q.STATEVEC, q.C64)
+    cur.init_zero()
+    c.run_compiled(cur, C64_TILE[0], C64_TILE[1], 0, C64_TILE[2])
+    torch.cuda.synchronize()
+    deficit = fidelity_deficit(torch, ref.tensor, cur.tensor)
+    log(f'33q fidelity deficit {deficit:.3e}')
+    assert abs(deficit) <= 1e-5
+    assert abs(cur.calc_total_prob() - 1.0) <= 1e-5
+    cur.close()
+    ref.close()
+    c.close()
+    del cur, ref
+    release()
