@@ -48,13 +48,13 @@ __global__ __launch_bounds__(kBlock) void k_init_basis(typename C2<T>::type* __r
 // row (t >= 6): each lane owns a pair (a, a + 2^t); 64 consecutive lanes
 // touch two contiguous 1 KiB (c128) runs.  `ins` inserts a 0 at t and a 1
 // at every control.
-template <typename T>
+template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void k_gate_pair(typename C2<T>::type* __restrict__ amp,
                                                       uint64_t npairs, uint64_t tb, BitInsert ins,
                                                       Mat2<T> u)
 {
     using V = typename C2<T>::type;
-    constexpr int P = kPer<T> / 2;
+    static_assert(P % 2 == 0, "the step order alternates two half-runs");
     const uint64_t ps = (uint64_t)kBlock * P;
     for (uint64_t s = blockIdx.x; step_base(s, ps) < npairs; s += gridDim.x) {
         const uint64_t c = step_base(s, ps);
@@ -112,11 +112,12 @@ __device__ __forceinline__ float xchg(float v, int lane)
 // and writes its own new value, so loads and stores stay fully contiguous.
 // Controls at bits >= 6 are folded into the chunk index (`hi`); controls at
 // bits < 6 become a lane mask.
-template <typename T, int TT>
+template <typename T, int TT, int U>
 __global__ __launch_bounds__(kBlock) void k_gate_low(typename C2<T>::type* __restrict__ amp,
                                                      uint64_t nchunks, BitInsert hi,
                                                      uint32_t lowmask, Mat2<T> u)
 {
+    static_assert(U % 2 == 0, "the step order alternates two half-runs");
     using V = typename C2<T>::type;
     const int lane = threadIdx.x & 63;
     const bool up = (lane >> TT) & 1;
@@ -127,7 +128,6 @@ __global__ __launch_bounds__(kBlock) void k_gate_low(typename C2<T>::type* __res
     // chunks play the role of items: a workgroup step of PS = 4 * kPer
     // chunks is two half-runs PS apart, alternated as in step_item (with
     // the 4 waves in place of the threads)
-    constexpr int U = kPer<T>;
     const int w = threadIdx.x >> 6;
     const uint64_t ps = (uint64_t)(kBlock / 64) * U;
     auto chunk = [&](uint64_t base, int j) {
@@ -156,12 +156,12 @@ __global__ __launch_bounds__(kBlock) void k_gate_low(typename C2<T>::type* __res
 }
 
 // Multi-controlled NOT: swap each pair whose controls are set.
-template <typename T>
+template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void k_not(typename C2<T>::type* __restrict__ amp,
                                                 uint64_t npairs, uint64_t tb, BitInsert ins)
 {
     using V = typename C2<T>::type;
-    constexpr int P = kPer<T> / 2;
+    static_assert(P % 2 == 0, "the step order alternates two half-runs");
     const uint64_t ps = (uint64_t)kBlock * P;
     for (uint64_t s = blockIdx.x; step_base(s, ps) < npairs; s += gridDim.x) {
         const uint64_t c = step_base(s, ps);
@@ -185,13 +185,13 @@ __global__ __launch_bounds__(kBlock) void k_not(typename C2<T>::type* __restrict
 
 // Diagonal phase on the amplitudes whose `ins.ones` bits are all set,
 // except those that also have every bit of `skip` set (skip != 0).
-template <typename T>
+template <typename T, int U>
 __global__ __launch_bounds__(kBlock) void k_phase(typename C2<T>::type* __restrict__ amp,
                                                   uint64_t count, BitInsert ins, uint64_t skip,
                                                   T fr, T fi)
 {
+    static_assert(U % 2 == 0, "the step order alternates two half-runs");
     using V = typename C2<T>::type;
-    constexpr int U = kPer<T>;
     const uint64_t ps = (uint64_t)kBlock * U;
     for (uint64_t s = blockIdx.x; step_base(s, ps) < count; s += gridDim.x) {
         const uint64_t c = step_base(s, ps);
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(typename C2<T>::type* __restri
 // (rho[r][c]) with row bit t = r and column bit t+N = c; the gate is
 // rho -> (R ? U : I) rho (C ? U^dagger : I), R / C = row / column controls
 // all set.  Columns multiplied by U^dagger is conj(U) on the column qubit.
-template <typename T>
+template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_dm_gate(typename C2<T>::type* __restrict__ rho,
                                                     uint64_t ngroups, uint64_t tb, uint64_t cb,
                                                     BitInsert ins, uint64_t rmask, uint64_t cmask,
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_dm_gate(typename C2<T>::type* __rest
     T uc[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) uc[k] = (k & 1) ? -u.m[k] : u.m[k];
-    constexpr int G = kPer<T> / 4;
+    static_assert(G % 2 == 0, "the step order alternates two half-runs");
     const uint64_t ps = (uint64_t)kBlock * G;
     for (uint64_t s = blockIdx.x; step_base(s, ps) < ngroups; s += gridDim.x) {
         const uint64_t c = step_base(s, ps);
@@ -272,13 +272,13 @@ __global__ __launch_bounds__(kBlock) void k_dm_gate(typename C2<T>::type* __rest
 //   damping g:       r00 <- r00 + g r11, r11 <- (1-g) r11,
 //                    off-diagonals * sqrt(1-g)
 // a, b: diagonal mixing (r00' = a r00 + b r11 ... per channel), f: off-diagonal factor.
-template <typename T, int CH>
+template <typename T, int CH, int G>
 __global__ __launch_bounds__(kBlock) void k_dm_channel(typename C2<T>::type* __restrict__ rho,
                                                        uint64_t ngroups, uint64_t tb, uint64_t cb,
                                                        BitInsert ins, double p0, double p1, double f)
 {
     using V = typename C2<T>::type;
-    constexpr int G = kPer<T> / 4;
+    static_assert(G % 2 == 0, "the step order alternates two half-runs");
     const uint64_t ps = (uint64_t)kBlock * G;
     for (uint64_t s = blockIdx.x; step_base(s, ps) < ngroups; s += gridDim.x) {
         const uint64_t c = step_base(s, ps);
@@ -369,12 +369,12 @@ __device__ __forceinline__ void block_store2(NSum s0, NSum s1, double* partials)
 }
 
 // Sum |alpha_i|^2 split by bit q of i (q < 0: everything in the first sum).
-template <typename T>
+template <typename T, int U>
 __global__ __launch_bounds__(kBlock) void k_prob_sv(const typename C2<T>::type* __restrict__ amp,
                                                     uint64_t len, int q, double* partials)
 {
+    static_assert(U % 2 == 0, "the step order alternates two half-runs");
     using V = typename C2<T>::type;
-    constexpr int U = kPer<T>;
     NSum s0 = {0.0, 0.0}, s1 = {0.0, 0.0};
     const uint64_t ps = (uint64_t)kBlock * U;
     for (uint64_t s = blockIdx.x; step_base(s, ps) < len; s += gridDim.x) {
@@ -445,12 +445,12 @@ __global__ __launch_bounds__(kBlock) void k_reduce_final(const double* __restric
 
 // Collapse: keep amplitudes with bit q == outcome (scaled in double), zero
 // the rest without reading them.
-template <typename T>
+template <typename T, int U>
 __global__ __launch_bounds__(kBlock) void k_collapse_sv(typename C2<T>::type* __restrict__ amp,
                                                         uint64_t len, int q, int outcome, double scale)
 {
+    static_assert(U % 2 == 0, "the step order alternates two half-runs");
     using V = typename C2<T>::type;
-    constexpr int U = kPer<T>;
     const uint64_t ps = (uint64_t)kBlock * U;
     for (uint64_t s = blockIdx.x; step_base(s, ps) < len; s += gridDim.x) {
         const uint64_t c = step_base(s, ps);
@@ -476,13 +476,13 @@ __global__ __launch_bounds__(kBlock) void k_collapse_sv(typename C2<T>::type* __
 
 // Density-matrix collapse: keep rho[j][k] when bit q of j and of k both
 // equal the outcome (bits q and q+N of the vector index), scaled by 1/p.
-template <typename T>
+template <typename T, int U>
 __global__ __launch_bounds__(kBlock) void k_collapse_dm(typename C2<T>::type* __restrict__ rho,
                                                         uint64_t len, int q, int N, int outcome,
                                                         double scale)
 {
+    static_assert(U % 2 == 0, "the step order alternates two half-runs");
     using V = typename C2<T>::type;
-    constexpr int U = kPer<T>;
     const uint64_t ps = (uint64_t)kBlock * U;
     for (uint64_t s = blockIdx.x; step_base(s, ps) < len; s += gridDim.x) {
         const uint64_t c = step_base(s, ps);
@@ -584,6 +584,14 @@ __global__ __launch_bounds__(kBlock) void k_diag_dm(const typename C2<T>::type* 
 // ===========================================================================
 // Launchers
 
+// Small registers take kSmallPer items (amplitudes, pairs or 4-groups) per
+// thread per step instead of 256 bytes' worth, so that the grid still
+// spreads over the CUs (below 512 blocks with the large steps).  The step
+// order needs an even count.
+constexpr int kSmallPer = 2;
+
+inline bool wide(uint64_t items, int per) { return items >= (uint64_t)512 * kBlock * per; }
+
 template <typename T>
 hipError_t launch_init_basis(const Launch& L, void* amp, uint64_t len, uint64_t index, double re, double im)
 {
@@ -640,11 +648,18 @@ hipError_t launch_gate(const Launch& L, void* amp, int nbits, int t, const int* 
         }
         const BitInsert hi = make_insert(hp, nh, ones);
         const uint64_t nchunks = 1ull << (nbits - 6 - nh);
-        // one wave-row of 64 lanes per chunk, kPer chunks per wave per step
-        const int grid = grid_for(nchunks * 64, kPer<T>);
+        // one wave-row of 64 lanes per chunk, U chunks per wave per step
+        const bool big = wide(nchunks * 64, kPer<T>);
+        const int grid = grid_for(nchunks * 64, big ? kPer<T> : kSmallPer);
         switch (t) {
-#define QS_LOW(TT) case TT: hipLaunchKernelGGL((k_gate_low<T, TT>), dim3(grid), dim3(kBlock), 0, L.stream, \
-                                         (V*)amp, nchunks, hi, lowmask, u); break;
+#define QS_LOW(TT) case TT:                                                                              \
+    if (big)                                                                                             \
+        hipLaunchKernelGGL((k_gate_low<T, TT, kPer<T>>), dim3(grid), dim3(kBlock), 0, L.stream, (V*)amp, \
+                           nchunks, hi, lowmask, u);                                                     \
+    else                                                                                                 \
+        hipLaunchKernelGGL((k_gate_low<T, TT, kSmallPer>), dim3(grid), dim3(kBlock), 0, L.stream, (V*)amp, \
+                           nchunks, hi, lowmask, u);                                                     \
+    break;
             QS_LOW(0) QS_LOW(1) QS_LOW(2) QS_LOW(3) QS_LOW(4) QS_LOW(5)
 #undef QS_LOW
         }
@@ -660,8 +675,12 @@ hipError_t launch_gate(const Launch& L, void* amp, int nbits, int t, const int* 
     pos[nc] = t;
     const BitInsert ins = make_insert(pos, nc + 1, ones);
     const uint64_t npairs = 1ull << (nbits - 1 - nc);
-    hipLaunchKernelGGL(k_gate_pair<T>, dim3(grid_for(npairs, kPer<T> / 2)), dim3(kBlock), 0, L.stream,
-                       (V*)amp, npairs, 1ull << t, ins, u);
+    if (wide(npairs, kPer<T> / 2))
+        hipLaunchKernelGGL((k_gate_pair<T, kPer<T> / 2>), dim3(grid_for(npairs, kPer<T> / 2)), dim3(kBlock), 0, L.stream,
+                           (V*)amp, npairs, 1ull << t, ins, u);
+    else
+        hipLaunchKernelGGL((k_gate_pair<T, kSmallPer>), dim3(grid_for(npairs, kSmallPer)), dim3(kBlock), 0,
+                           L.stream, (V*)amp, npairs, 1ull << t, ins, u);
     if (klass) *klass = QS_K_GATE;
     return hipGetLastError();
 }
@@ -679,8 +698,12 @@ hipError_t launch_not(const Launch& L, void* amp, int nbits, int t, const int* c
     pos[nc] = t;
     const BitInsert ins = make_insert(pos, nc + 1, ones);
     const uint64_t npairs = 1ull << (nbits - 1 - nc);
-    hipLaunchKernelGGL(k_not<T>, dim3(grid_for(npairs, kPer<T> / 2)), dim3(kBlock), 0, L.stream,
-                       (V*)amp, npairs, 1ull << t, ins);
+    if (wide(npairs, kPer<T> / 2))
+        hipLaunchKernelGGL((k_not<T, kPer<T> / 2>), dim3(grid_for(npairs, kPer<T> / 2)), dim3(kBlock), 0, L.stream,
+                           (V*)amp, npairs, 1ull << t, ins);
+    else
+        hipLaunchKernelGGL((k_not<T, kSmallPer>), dim3(grid_for(npairs, kSmallPer)), dim3(kBlock), 0, L.stream,
+                           (V*)amp, npairs, 1ull << t, ins);
     return hipGetLastError();
 }
 
@@ -695,8 +718,12 @@ hipError_t launch_phase(const Launch& L, void* amp, int nbits, uint64_t mask, ui
         if ((mask >> q) & 1) pos[np++] = q;
     const BitInsert ins = make_insert(pos, np, mask);
     const uint64_t count = 1ull << (nbits - np);
-    hipLaunchKernelGGL(k_phase<T>, dim3(grid_for(count, kPer<T>)), dim3(kBlock), 0, L.stream,
-                       (V*)amp, count, ins, skip, (T)fre, (T)fim);
+    if (wide(count, kPer<T>))
+        hipLaunchKernelGGL((k_phase<T, kPer<T>>), dim3(grid_for(count, kPer<T>)), dim3(kBlock), 0, L.stream,
+                           (V*)amp, count, ins, skip, (T)fre, (T)fim);
+    else
+        hipLaunchKernelGGL((k_phase<T, kSmallPer>), dim3(grid_for(count, kSmallPer)), dim3(kBlock), 0, L.stream,
+                           (V*)amp, count, ins, skip, (T)fre, (T)fim);
     return hipGetLastError();
 }
 
@@ -710,8 +737,12 @@ hipError_t launch_dm_gate(const Launch& L, void* rho, int N, int t, const int* c
     uint64_t rmask = 0;
     for (int k = 0; k < nc; ++k) rmask |= 1ull << ctrls[k];
     const uint64_t ngroups = 1ull << (2 * N - 2);
-    hipLaunchKernelGGL(k_dm_gate<T>, dim3(grid_for(ngroups, kPer<T> / 4)), dim3(kBlock), 0, L.stream,
-                       (V*)rho, ngroups, 1ull << t, 1ull << (t + N), ins, rmask, rmask << N, u);
+    if (wide(ngroups, kPer<T> / 4))
+        hipLaunchKernelGGL((k_dm_gate<T, kPer<T> / 4>), dim3(grid_for(ngroups, kPer<T> / 4)), dim3(kBlock), 0,
+                           L.stream, (V*)rho, ngroups, 1ull << t, 1ull << (t + N), ins, rmask, rmask << N, u);
+    else
+        hipLaunchKernelGGL((k_dm_gate<T, kSmallPer>), dim3(grid_for(ngroups, kSmallPer)), dim3(kBlock), 0, L.stream,
+                           (V*)rho, ngroups, 1ull << t, 1ull << (t + N), ins, rmask, rmask << N, u);
     return hipGetLastError();
 }
 
@@ -722,21 +753,35 @@ hipError_t launch_dm_channel(const Launch& L, void* rho, int N, int t, int chann
     const int pos[2] = {t, t + N};
     const BitInsert ins = make_insert(pos, 2, 0);
     const uint64_t ngroups = 1ull << (2 * N - 2);
-    const dim3 grid(grid_for(ngroups, kPer<T> / 4)), block(kBlock);
+    const bool big = wide(ngroups, kPer<T> / 4);
+    const dim3 grid(grid_for(ngroups, big ? kPer<T> / 4 : kSmallPer)), block(kBlock);
     const uint64_t tb = 1ull << t, cb = 1ull << (t + N);
     switch (channel) {
     case QS_DEPHASING:
-        hipLaunchKernelGGL((k_dm_channel<T, QS_DEPHASING>), grid, block, 0, L.stream, (V*)rho,
-                           ngroups, tb, cb, ins, 0.0, 0.0, 1.0 - 2.0 * p);
+        if (big)
+            hipLaunchKernelGGL((k_dm_channel<T, QS_DEPHASING, kPer<T> / 4>), grid, block, 0, L.stream, (V*)rho, ngroups,
+                               tb, cb, ins, 0.0, 0.0, 1.0 - 2.0 * p);
+        else
+            hipLaunchKernelGGL((k_dm_channel<T, QS_DEPHASING, kSmallPer>), grid, block, 0, L.stream, (V*)rho, ngroups,
+                               tb, cb, ins, 0.0, 0.0, 1.0 - 2.0 * p);
         break;
     case QS_DEPOLARISING:
-        hipLaunchKernelGGL((k_dm_channel<T, QS_DEPOLARISING>), grid, block, 0, L.stream, (V*)rho,
-                           ngroups, tb, cb, ins, 1.0 - 2.0 * p / 3.0, 2.0 * p / 3.0,
+        if (big)
+            hipLaunchKernelGGL((k_dm_channel<T, QS_DEPOLARISING, kPer<T> / 4>), grid, block, 0, L.stream, (V*)rho, ngroups,
+                               tb, cb, ins, 1.0 - 2.0 * p / 3.0, 2.0 * p / 3.0,
+                           1.0 - 4.0 * p / 3.0);
+        else
+            hipLaunchKernelGGL((k_dm_channel<T, QS_DEPOLARISING, kSmallPer>), grid, block, 0, L.stream, (V*)rho, ngroups,
+                               tb, cb, ins, 1.0 - 2.0 * p / 3.0, 2.0 * p / 3.0,
                            1.0 - 4.0 * p / 3.0);
         break;
     default:
-        hipLaunchKernelGGL((k_dm_channel<T, QS_DAMPING>), grid, block, 0, L.stream, (V*)rho,
-                           ngroups, tb, cb, ins, p, 1.0 - p, sqrt(1.0 - p));
+        if (big)
+            hipLaunchKernelGGL((k_dm_channel<T, QS_DAMPING, kPer<T> / 4>), grid, block, 0, L.stream, (V*)rho, ngroups,
+                               tb, cb, ins, p, 1.0 - p, sqrt(1.0 - p));
+        else
+            hipLaunchKernelGGL((k_dm_channel<T, QS_DAMPING, kSmallPer>), grid, block, 0, L.stream, (V*)rho, ngroups,
+                               tb, cb, ins, p, 1.0 - p, sqrt(1.0 - p));
         break;
     }
     return hipGetLastError();
@@ -748,10 +793,15 @@ hipError_t launch_prob_sv(const Launch& L, const void* amp, int nbits, int q, do
 {
     using V = typename C2<T>::type;
     const uint64_t len = 1ull << nbits;
-    int grid = grid_for(len, kPer<T>);
+    const bool big = wide(len, kPer<T>);
+    int grid = grid_for(len, big ? kPer<T> : kSmallPer);
     if (grid > kReduceBlocks) grid = kReduceBlocks;
-    hipLaunchKernelGGL(k_prob_sv<T>, dim3(grid), dim3(kBlock), 0, L.stream, (const V*)amp, len, q,
-                       partials);
+    if (big)
+        hipLaunchKernelGGL((k_prob_sv<T, kPer<T>>), dim3(grid), dim3(kBlock), 0, L.stream, (const V*)amp, len, q,
+                           partials);
+    else
+        hipLaunchKernelGGL((k_prob_sv<T, kSmallPer>), dim3(grid), dim3(kBlock), 0, L.stream, (const V*)amp, len, q,
+                           partials);
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, L.stream, partials, grid, dev_out);
     return hipGetLastError();
 }
@@ -775,8 +825,12 @@ hipError_t launch_collapse_sv(const Launch& L, void* amp, int nbits, int q, int 
 {
     using V = typename C2<T>::type;
     const uint64_t len = 1ull << nbits;
-    hipLaunchKernelGGL(k_collapse_sv<T>, dim3(grid_for(len, kPer<T>)), dim3(kBlock), 0, L.stream, (V*)amp,
-                       len, q, outcome, scale);
+    if (wide(len, kPer<T>))
+        hipLaunchKernelGGL((k_collapse_sv<T, kPer<T>>), dim3(grid_for(len, kPer<T>)), dim3(kBlock), 0, L.stream,
+                           (V*)amp, len, q, outcome, scale);
+    else
+        hipLaunchKernelGGL((k_collapse_sv<T, kSmallPer>), dim3(grid_for(len, kSmallPer)), dim3(kBlock), 0, L.stream,
+                           (V*)amp, len, q, outcome, scale);
     return hipGetLastError();
 }
 
@@ -785,8 +839,12 @@ hipError_t launch_collapse_dm(const Launch& L, void* rho, int N, int q, int outc
 {
     using V = typename C2<T>::type;
     const uint64_t len = 1ull << (2 * N);
-    hipLaunchKernelGGL(k_collapse_dm<T>, dim3(grid_for(len, kPer<T>)), dim3(kBlock), 0, L.stream, (V*)rho,
-                       len, q, N, outcome, scale);
+    if (wide(len, kPer<T>))
+        hipLaunchKernelGGL((k_collapse_dm<T, kPer<T>>), dim3(grid_for(len, kPer<T>)), dim3(kBlock), 0, L.stream,
+                           (V*)rho, len, q, N, outcome, scale);
+    else
+        hipLaunchKernelGGL((k_collapse_dm<T, kSmallPer>), dim3(grid_for(len, kSmallPer)), dim3(kBlock), 0, L.stream,
+                           (V*)rho, len, q, N, outcome, scale);
     return hipGetLastError();
 }
 
