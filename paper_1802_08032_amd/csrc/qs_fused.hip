@@ -464,7 +464,8 @@ void serialize(const std::vector<PassPlan>& plan, const std::vector<OpRec>& ops,
 struct Shape {
     int TB, RB;
 };
-constexpr Shape kShapes128[] = {{6, 3}, {7, 3}, {8, 3}, {8, 4}, {9, 3}, {8, 5}, {9, 4}, {10, 3}};
+// (8, 5) in complex128 would need 32 double2 registers per thread and spills
+constexpr Shape kShapes128[] = {{6, 3}, {7, 3}, {8, 3}, {8, 4}, {9, 3}, {9, 4}, {10, 3}};
 constexpr Shape kShapes64[] = {{6, 3}, {7, 3}, {8, 3}, {8, 4}, {9, 3}, {8, 5}, {9, 4}, {10, 3},
                                {9, 5}, {10, 4}};
 
@@ -486,9 +487,9 @@ hipError_t launch_fused_pass(hipStream_t s, const FusedConfig& c, void* amp, con
 #define QS_SHAPE(tb, rb) \
     if (c.TB == tb && c.RB == rb) return launch_cfg<T, tb, rb>(s, amp, P, ops, ntiles);
     QS_SHAPE(6, 3) QS_SHAPE(7, 3) QS_SHAPE(8, 3) QS_SHAPE(8, 4) QS_SHAPE(9, 3)
-    QS_SHAPE(8, 5) QS_SHAPE(9, 4) QS_SHAPE(10, 3)
+    QS_SHAPE(9, 4) QS_SHAPE(10, 3)
     if constexpr (sizeof(T) == 4) {
-        QS_SHAPE(9, 5) QS_SHAPE(10, 4)
+        QS_SHAPE(8, 5) QS_SHAPE(9, 5) QS_SHAPE(10, 4)
     }
 #undef QS_SHAPE
     return hipErrorInvalidValue;
@@ -516,6 +517,7 @@ FusedConfig default_fused_config(int prec, int k, int n)
     if (K < 9) return c;
     static const int tb_of[15] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 6, 7, 8, 8, 8, 9};
     c.TB = tb_of[K];
+    if (prec == QS_C128 && K == 13) c.TB = 9;  // 16 registers per thread, not 32
     c.RB = K - c.TB;
     return c;
 }
@@ -601,9 +603,9 @@ hipError_t batch_launch_p(qs_batch_s* b, int init)
 {
 #define QS_B(tb, rb) \
     if (b->TB == tb && b->RB == rb) return batch_launch_t<T, tb, rb>(b, init);
-    QS_B(6, 3) QS_B(7, 3) QS_B(8, 3) QS_B(8, 4) QS_B(9, 3) QS_B(8, 5) QS_B(9, 4) QS_B(10, 3)
+    QS_B(6, 3) QS_B(7, 3) QS_B(8, 3) QS_B(8, 4) QS_B(9, 3) QS_B(9, 4) QS_B(10, 3)
     if constexpr (sizeof(T) == 4) {
-        QS_B(9, 5) QS_B(10, 4)
+        QS_B(8, 5) QS_B(9, 5) QS_B(10, 4)
     }
 #undef QS_B
     return hipErrorInvalidValue;
@@ -622,9 +624,9 @@ int batch_occupancy_p(int TB, int RB)
 {
 #define QS_O(tb, rb) \
     if (TB == tb && RB == rb) return batch_occupancy<T, tb, rb>();
-    QS_O(6, 3) QS_O(7, 3) QS_O(8, 3) QS_O(8, 4) QS_O(9, 3) QS_O(8, 5) QS_O(9, 4) QS_O(10, 3)
+    QS_O(6, 3) QS_O(7, 3) QS_O(8, 3) QS_O(8, 4) QS_O(9, 3) QS_O(9, 4) QS_O(10, 3)
     if constexpr (sizeof(T) == 4) {
-        QS_O(9, 5) QS_O(10, 4)
+        QS_O(8, 5) QS_O(9, 5) QS_O(10, 4)
     }
 #undef QS_O
     return 1;

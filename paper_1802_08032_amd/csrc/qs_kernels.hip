@@ -29,17 +29,24 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // Initialisation: every amplitude 0 except `index`, which is (re, im).
-template <typename T>
+template <typename T, int U>
 __global__ __launch_bounds__(kBlock) void k_init_basis(typename C2<T>::type* __restrict__ amp,
                                                        uint64_t len, uint64_t index, T re, T im)
 {
     using V = typename C2<T>::type;
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < len; i += stride) {
-        V v;
-        v.x = (i == index) ? re : T(0);
-        v.y = (i == index) ? im : T(0);
-        amp[i] = v;
+    static_assert(U % 2 == 0, "the step order alternates two half-runs");
+    const uint64_t ps = (uint64_t)kBlock * U;
+    for (uint64_t s = blockIdx.x; step_base(s, ps) < len; s += gridDim.x) {
+        const uint64_t c = step_base(s, ps);
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t i = step_item(c, j, ps);
+            if (i >= len) continue;
+            V v;  // plain stores: measured faster than non-temporal ones for write-only streams
+            v.x = (i == index) ? re : T(0);
+            v.y = (i == index) ? im : T(0);
+            amp[i] = v;
+        }
     }
 }
 
@@ -47,11 +54,12 @@ __global__ __launch_bounds__(kBlock) void k_init_basis(typename C2<T>::type* __r
 // Eq. 1 pair update for targets whose pair partner lies in another wavefront
 // row (t >= 6): each lane owns a pair (a, a + 2^t); 64 consecutive lanes
 // touch two contiguous 1 KiB (c128) runs.  `ins` inserts a 0 at t and a 1
-// at every control.
+// at every control of at least kLineBits; lower controls are the bits of
+// `lowmask`, tested per pair.
 template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void k_gate_pair(typename C2<T>::type* __restrict__ amp,
                                                       uint64_t npairs, uint64_t tb, BitInsert ins,
-                                                      Mat2<T> u)
+                                                      uint64_t lowmask, Mat2<T> u)
 {
     using V = typename C2<T>::type;
     static_assert(P % 2 == 0, "the step order alternates two half-runs");
@@ -64,17 +72,33 @@ __global__ __launch_bounds__(kBlock) void k_gate_pair(typename C2<T>::type* __re
         for (int j = 0; j < P; ++j) {
             const uint64_t i = step_item(c, j, ps);
             a[j] = expand(i < npairs ? i : npairs - 1, ins);  // a clamped lane only reads
-            x[j] = ldnt(amp + a[j]);
-            y[j] = ldnt(amp + a[j] + tb);
         }
+        // all low halves, then all high halves: each run of loads alternates
+        // between the step's two half-runs
+#pragma unroll
+        for (int j = 0; j < P; ++j) x[j] = ldnt(amp + a[j]);
+#pragma unroll
+        for (int j = 0; j < P; ++j) y[j] = ldnt(amp + a[j] + tb);
 #pragma unroll
         for (int j = 0; j < P; ++j) {
-            apply2<T, V>(u.m, x[j], y[j]);
-            if (step_item(c, j, ps) < npairs) {
-                stnt(amp + a[j], x[j]);
-                stnt(amp + a[j] + tb, y[j]);
-            }
+            // controls below the line size are tested per pair: unselected
+            // pairs are written back unchanged, so every store is a full line
+            V nx = x[j], ny = y[j];
+            apply2<T, V>(u.m, nx, ny);
+            const bool ok = (a[j] & lowmask) == lowmask;
+            // component-wise selects: a select of whole vector structs puts
+            // the arrays in scratch memory
+            x[j].x = ok ? nx.x : x[j].x;
+            x[j].y = ok ? nx.y : x[j].y;
+            y[j].x = ok ? ny.x : y[j].x;
+            y[j].y = ok ? ny.y : y[j].y;
         }
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+            if (step_item(c, j, ps) < npairs) stnt(amp + a[j], x[j]);
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+            if (step_item(c, j, ps) < npairs) stnt(amp + a[j] + tb, y[j]);
     }
 }
 
@@ -150,15 +174,21 @@ __global__ __launch_bounds__(kBlock) void k_gate_low(typename C2<T>::type* __res
             p.x = xchg<TT>(v[j].x, lane);
             p.y = xchg<TT>(v[j].y, lane);
             const V r = cmac2<T, V>(sr, si, v[j], pr, pi, p);
-            if (ok && chunk(c0, j) < nchunks) stnt(amp + e[j], r);
+            // lanes whose low controls are not all set store their value
+            // unchanged, so that every store is a full wave-wide line
+            V o;
+            o.x = ok ? r.x : v[j].x;
+            o.y = ok ? r.y : v[j].y;
+            if (chunk(c0, j) < nchunks) stnt(amp + e[j], o);
         }
     }
 }
 
-// Multi-controlled NOT: swap each pair whose controls are set.
+// Multi-controlled NOT: swap each pair whose controls are set (controls
+// below kLineBits tested per pair, as in k_gate_pair).
 template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void k_not(typename C2<T>::type* __restrict__ amp,
-                                                uint64_t npairs, uint64_t tb, BitInsert ins)
+                                                uint64_t npairs, uint64_t tb, BitInsert ins, uint64_t lowmask)
 {
     using V = typename C2<T>::type;
     static_assert(P % 2 == 0, "the step order alternates two half-runs");
@@ -170,16 +200,29 @@ __global__ __launch_bounds__(kBlock) void k_not(typename C2<T>::type* __restrict
 #pragma unroll
         for (int j = 0; j < P; ++j) {
             const uint64_t i = step_item(c, j, ps);
-            a[j] = expand(i < npairs ? i : npairs - 1, ins);
-            x[j] = ldnt(amp + a[j]);
-            y[j] = ldnt(amp + a[j] + tb);
+            a[j] = expand(i < npairs ? i : npairs - 1, ins);  // a clamped lane only reads
+        }
+        // all low halves, then all high halves: each run of loads alternates
+        // between the step's two half-runs
+#pragma unroll
+        for (int j = 0; j < P; ++j) x[j] = ldnt(amp + a[j]);
+#pragma unroll
+        for (int j = 0; j < P; ++j) y[j] = ldnt(amp + a[j] + tb);
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const bool ok = (a[j] & lowmask) == lowmask;  // unselected pairs keep their order
+            const T x0 = x[j].x, x1 = x[j].y;
+            x[j].x = ok ? y[j].x : x0;
+            x[j].y = ok ? y[j].y : x1;
+            y[j].x = ok ? x0 : y[j].x;
+            y[j].y = ok ? x1 : y[j].y;
         }
 #pragma unroll
         for (int j = 0; j < P; ++j)
-            if (step_item(c, j, ps) < npairs) {
-                stnt(amp + a[j], y[j]);
-                stnt(amp + a[j] + tb, x[j]);
-            }
+            if (step_item(c, j, ps) < npairs) stnt(amp + a[j], x[j]);
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+            if (step_item(c, j, ps) < npairs) stnt(amp + a[j] + tb, y[j]);
     }
 }
 
@@ -187,8 +230,8 @@ __global__ __launch_bounds__(kBlock) void k_not(typename C2<T>::type* __restrict
 // except those that also have every bit of `skip` set (skip != 0).
 template <typename T, int U>
 __global__ __launch_bounds__(kBlock) void k_phase(typename C2<T>::type* __restrict__ amp,
-                                                  uint64_t count, BitInsert ins, uint64_t skip,
-                                                  T fr, T fi)
+                                                  uint64_t count, BitInsert ins, uint64_t lowmask,
+                                                  uint64_t skip, T fr, T fi)
 {
     static_assert(U % 2 == 0, "the step order alternates two half-runs");
     using V = typename C2<T>::type;
@@ -202,12 +245,21 @@ __global__ __launch_bounds__(kBlock) void k_phase(typename C2<T>::type* __restri
         for (int j = 0; j < U; ++j) {
             const uint64_t i = step_item(c, j, ps);
             e[j] = expand(i < count ? i : count - 1, ins);
-            on[j] = i < count && !(skip != 0 && (e[j] & skip) == skip);
+            on[j] = i < count;
             if (on[j]) v[j] = ldnt(amp + e[j]);
         }
 #pragma unroll
-        for (int j = 0; j < U; ++j)
-            if (on[j]) stnt(amp + e[j], cmul<T, V>(fr, fi, v[j]));
+        for (int j = 0; j < U; ++j) {
+            if (!on[j]) continue;
+            // phase bits below kLineBits are tested per element; the others
+            // are written back unchanged so that every store is a full line
+            const bool hit = (e[j] & lowmask) == lowmask && !(skip != 0 && (e[j] & skip) == skip);
+            const V m = cmul<T, V>(fr, fi, v[j]);
+            V r;
+            r.x = hit ? m.x : v[j].x;
+            r.y = hit ? m.y : v[j].y;
+            stnt(amp + e[j], r);
+        }
     }
 }
 
@@ -584,6 +636,12 @@ __global__ __launch_bounds__(kBlock) void k_diag_dm(const typename C2<T>::type* 
 // ===========================================================================
 // Launchers
 
+// Controls (and phase bits) below kLineBits select within a 128-byte line:
+// the pair and phase kernels walk those bits too and test them per item, so
+// that loads and stores stay contiguous.
+template <typename T>
+constexpr int kLineBits = sizeof(T) == 8 ? 3 : 4;
+
 // Small registers take kSmallPer items (amplitudes, pairs or 4-groups) per
 // thread per step instead of 256 bytes' worth, so that the grid still
 // spreads over the CUs (below 512 blocks with the large steps).  The step
@@ -596,8 +654,12 @@ template <typename T>
 hipError_t launch_init_basis(const Launch& L, void* amp, uint64_t len, uint64_t index, double re, double im)
 {
     using V = typename C2<T>::type;
-    hipLaunchKernelGGL(k_init_basis<T>, dim3(grid_for(len, 4)), dim3(kBlock), 0, L.stream,
-                       (V*)amp, len, index, (T)re, (T)im);
+    if (wide(len, kPer<T>))
+        hipLaunchKernelGGL((k_init_basis<T, kPer<T>>), dim3(grid_for(len, kPer<T>)), dim3(kBlock), 0, L.stream,
+                           (V*)amp, len, index, (T)re, (T)im);
+    else
+        hipLaunchKernelGGL((k_init_basis<T, kSmallPer>), dim3(grid_for(len, kSmallPer)), dim3(kBlock), 0,
+                           L.stream, (V*)amp, len, index, (T)re, (T)im);
     return hipGetLastError();
 }
 
@@ -667,20 +729,25 @@ hipError_t launch_gate(const Launch& L, void* amp, int nbits, int t, const int* 
         return hipGetLastError();
     }
     int pos[64];
-    uint64_t ones = 0;
+    int np = 0;
+    uint64_t ones = 0, lowmask = 0;
     for (int k = 0; k < nc; ++k) {
-        pos[k] = ctrls[k];
+        if (ctrls[k] < kLineBits<T>) {
+            lowmask |= 1ull << ctrls[k];
+            continue;
+        }
+        pos[np++] = ctrls[k];
         ones |= 1ull << ctrls[k];
     }
-    pos[nc] = t;
-    const BitInsert ins = make_insert(pos, nc + 1, ones);
-    const uint64_t npairs = 1ull << (nbits - 1 - nc);
+    pos[np] = t;
+    const BitInsert ins = make_insert(pos, np + 1, ones);
+    const uint64_t npairs = 1ull << (nbits - 1 - np);
     if (wide(npairs, kPer<T> / 2))
         hipLaunchKernelGGL((k_gate_pair<T, kPer<T> / 2>), dim3(grid_for(npairs, kPer<T> / 2)), dim3(kBlock), 0, L.stream,
-                           (V*)amp, npairs, 1ull << t, ins, u);
+                           (V*)amp, npairs, 1ull << t, ins, lowmask, u);
     else
         hipLaunchKernelGGL((k_gate_pair<T, kSmallPer>), dim3(grid_for(npairs, kSmallPer)), dim3(kBlock), 0,
-                           L.stream, (V*)amp, npairs, 1ull << t, ins, u);
+                           L.stream, (V*)amp, npairs, 1ull << t, ins, lowmask, u);
     if (klass) *klass = QS_K_GATE;
     return hipGetLastError();
 }
@@ -690,20 +757,25 @@ hipError_t launch_not(const Launch& L, void* amp, int nbits, int t, const int* c
 {
     using V = typename C2<T>::type;
     int pos[64];
-    uint64_t ones = 0;
+    int np = 0;
+    uint64_t ones = 0, lowmask = 0;
     for (int k = 0; k < nc; ++k) {
-        pos[k] = ctrls[k];
+        if (ctrls[k] < kLineBits<T>) {
+            lowmask |= 1ull << ctrls[k];
+            continue;
+        }
+        pos[np++] = ctrls[k];
         ones |= 1ull << ctrls[k];
     }
-    pos[nc] = t;
-    const BitInsert ins = make_insert(pos, nc + 1, ones);
-    const uint64_t npairs = 1ull << (nbits - 1 - nc);
+    pos[np] = t;
+    const BitInsert ins = make_insert(pos, np + 1, ones);
+    const uint64_t npairs = 1ull << (nbits - 1 - np);
     if (wide(npairs, kPer<T> / 2))
         hipLaunchKernelGGL((k_not<T, kPer<T> / 2>), dim3(grid_for(npairs, kPer<T> / 2)), dim3(kBlock), 0, L.stream,
-                           (V*)amp, npairs, 1ull << t, ins);
+                           (V*)amp, npairs, 1ull << t, ins, lowmask);
     else
         hipLaunchKernelGGL((k_not<T, kSmallPer>), dim3(grid_for(npairs, kSmallPer)), dim3(kBlock), 0, L.stream,
-                           (V*)amp, npairs, 1ull << t, ins);
+                           (V*)amp, npairs, 1ull << t, ins, lowmask);
     return hipGetLastError();
 }
 
@@ -714,16 +786,17 @@ hipError_t launch_phase(const Launch& L, void* amp, int nbits, uint64_t mask, ui
     using V = typename C2<T>::type;
     int pos[64];
     int np = 0;
-    for (int q = 0; q < nbits; ++q)
+    const uint64_t lowmask = mask & ((1ull << kLineBits<T>) - 1);
+    for (int q = kLineBits<T>; q < nbits; ++q)
         if ((mask >> q) & 1) pos[np++] = q;
-    const BitInsert ins = make_insert(pos, np, mask);
+    const BitInsert ins = make_insert(pos, np, mask & ~lowmask);
     const uint64_t count = 1ull << (nbits - np);
     if (wide(count, kPer<T>))
         hipLaunchKernelGGL((k_phase<T, kPer<T>>), dim3(grid_for(count, kPer<T>)), dim3(kBlock), 0, L.stream,
-                           (V*)amp, count, ins, skip, (T)fre, (T)fim);
+                           (V*)amp, count, ins, lowmask, skip, (T)fre, (T)fim);
     else
         hipLaunchKernelGGL((k_phase<T, kSmallPer>), dim3(grid_for(count, kSmallPer)), dim3(kBlock), 0, L.stream,
-                           (V*)amp, count, ins, skip, (T)fre, (T)fim);
+                           (V*)amp, count, ins, lowmask, skip, (T)fre, (T)fim);
     return hipGetLastError();
 }
 

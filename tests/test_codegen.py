@@ -87,3 +87,30 @@ def test_pass_merges_and_deferred_flips_in_source():
     rc, log, _ = compile_src(srcs[pick])
     assert rc == 0, log
     c.close()
+
+
+def test_library_kernels_use_no_scratch():
+    """Every kernel of the streaming and fused sources compiles for gfx950
+    without a private (scratch) segment: spills or arrays the compiler
+    could not keep in registers would turn into per-lane memory traffic."""
+    import re
+    import subprocess
+    import tempfile
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    csrc = os.path.join(root, 'paper_1802_08032_amd', 'csrc')
+    for src in ('qs_kernels.hip', 'qs_fused.hip'):
+        with tempfile.TemporaryDirectory() as d:
+            out = os.path.join(d, 'k.s')
+            cmd = ['/opt/rocm/bin/hipcc', '--offload-arch=gfx950', '-O3', '-std=c++17', '--cuda-device-only', '-S',
+                   '-Xclang', '-target-feature', '-Xclang', '-packed-fp32-ops',
+                   '-I', os.path.join(root, 'include'), os.path.join(csrc, src), '-o', out]
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            if r.returncode != 0 and 'not found' in r.stderr and 'hipcc' in r.stderr:
+                pytest.skip('hipcc not available')
+            assert r.returncode == 0, r.stderr[-2000:]
+            asm = open(out).read()
+        kernels = re.findall(r'\.amdhsa_kernel (\S+)(.*?)\.end_amdhsa_kernel', asm, re.S)
+        assert kernels
+        for name, body in kernels:
+            size = int(re.search(r'\.amdhsa_private_segment_fixed_size (\d+)', body).group(1))
+            assert size == 0, f'{src}: {name} uses {size} bytes of scratch'
