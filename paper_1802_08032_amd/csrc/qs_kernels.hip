@@ -755,6 +755,13 @@ hipError_t launch_gate(const Launch& L, void* amp, int nbits, int t, const int* 
 template <typename T>
 hipError_t launch_not(const Launch& L, void* amp, int nbits, int t, const int* ctrls, int nc)
 {
+    if (t < 6 && nbits >= 6) {
+        // the in-wave exchange path of dense gates keeps every access a full
+        // line; X costs a few multiply-adds there
+        Mat2<T> x;
+        for (int k = 0; k < 8; ++k) x.m[k] = (k == 2 || k == 4) ? T(1) : T(0);
+        return launch_gate<T>(L, amp, nbits, t, ctrls, nc, x, nullptr);
+    }
     using V = typename C2<T>::type;
     int pos[64];
     int np = 0;
