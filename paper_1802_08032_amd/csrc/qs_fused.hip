@@ -534,7 +534,7 @@ qs_status run_fused_sv(qs_reg r, const std::vector<OpRec>& ops, FusedConfig cfg,
         return QS_OK;
     }
     const int TB = cfg.TB, RB = cfg.RB, K = TB + RB;
-    std::vector<PassPlan> plan = plan_passes(ops, r->n, TB, RB, cfg.max_phases, 1 << 12, 6);
+    std::vector<PassPlan> plan = plan_passes(ops, r->n, TB, RB, cfg.max_phases, 1 << 12, std::min(4, TB));
 
     // serialise passes + ops
     std::vector<FPass> hp;
