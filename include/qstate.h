@@ -146,6 +146,9 @@ qs_status qs_mix_depolarising(qs_reg r, int target, double p);
 qs_status qs_mix_damping(qs_reg r, int target, double gamma);
 
 /* ---- probabilities and measurement -------------------------------------- */
+/* The paper states no probability or measurement routine; these read the
+ * state of Sec. II.B.1 in the standard way (Born rule), with the rounding
+ * and draw conventions stated per call. */
 
 /* sum |alpha|^2 (state vector) or trace (density matrix), accumulated in
  * double precision with compensated sums.  Synchronous. */
