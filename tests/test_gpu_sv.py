@@ -362,3 +362,37 @@ def test_measure_all_complex64(q, env):
     assert max(abs(a - b) for a, b in zip(p, probs)) <= 1e-5
     assert fidelity_deficit(ref, reg.get_amps()) <= TOL64_FID
     reg.close()
+
+
+COMPILED_SHAPES = [(12, 8, 4), (13, 9, 4), (12, 9, 4), (13, 10, 4), (11, 8, 4), (12, 9, 6), (10, 7, 3), (9, 6, 6),
+                   (12, 8, 5), (13, 8, 5)]
+
+
+@pytest.mark.parametrize('seed', range(8))
+def test_compiled_random_sweep(q, env, seed):
+    """Tile shapes and circuit families in turn, seeded register sizes, through
+    the compiled passes (pass partition with window candidates, merged
+    register-only ops, deferred flips), against the oracle."""
+    rng = np.random.default_rng(500 + seed)
+    K, TB, L = COMPILED_SHAPES[(3 * seed + 1) % len(COMPILED_SHAPES)]
+    n = int(rng.integers(max(K, 12), 17))
+    fam = seed % 4
+    if fam == 0:
+        ops = layered_circuit(n, int(rng.integers(3, 9)), seed, mcphase=True)
+    elif fam == 1:
+        ops = param_circuit(n, int(rng.integers(3, 9)), seed)
+    elif fam == 2:
+        ops = random_gate_ops(n, 250, seed, max_controls=3)
+    else:
+        ops = layered_circuit(n, 4, seed) + random_gate_ops(n, 120, seed + 1, max_controls=2) + flip_circuit(n, seed)
+    state = random_state(n, 900 + seed)
+    ref = oracle_run(n, ops, state)
+    reg = q.Register(env, n)
+    reg.set_amps(state)
+    c = q.Circuit(ops)
+    log(f'sweep seed={seed} n={n} tile={K},{TB},{L} family={fam} ops={len(ops)}')
+    passes = c.run_compiled(reg, K, TB, 0, L)
+    assert 1 <= passes <= len(ops)
+    assert max_abs(reg.get_amps(), ref) <= TOL128
+    c.close()
+    reg.close()
