@@ -48,6 +48,22 @@ def algorithmic_bytes(ops, n, elem):
     return total
 
 
+FP64_PEAK_TFLOPS = 78.6
+
+
+def algorithmic_flops(ops, n):
+    """Real floating-point operations of the gates: a dense 2x2 gate costs
+    14 per amplitude it may change (two complex products and a complex
+    sum), a phase 6 per amplitude it multiplies, a NOT none."""
+    total = 0
+    for o in ops:
+        if o.kind == 'u':
+            total += 14 * (1 << (n - len(o.controls)))
+        elif o.kind == 'phase':
+            total += 6 * (1 << (n - len(o.qubits)))
+    return total
+
+
 def recorded_traffic(n, K, TB, L):
     """HBM bytes per fused pass from the committed rocprofv3 counter summary,
     or None when that summary was taken for another shape or an older version
@@ -344,6 +360,13 @@ def main():
             'frac': achieved / HBM_PEAK_GBS, 'traffic': recorded_traffic(n, K, TB, L),
             'kernel': f'qs_pass (run-time compiled fused pass, {K}-qubit tile)', 'launches': launches,
             'avg_ms': avg_ms,
+            # the same launches against the FP64 vector peak: the gates'
+            # algorithmic flops per launch (circuit total / passes)
+            'alu': {
+                'achieved': algorithmic_flops(ops, n) / max(1, passes) / (avg_ms * 1e-3) / 1e12,
+                'peak': FP64_PEAK_TFLOPS, 'unit': 'TFLOP/s',
+                'frac': algorithmic_flops(ops, n) / max(1, passes) / (avg_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+            },
         },
     }
 
