@@ -87,11 +87,9 @@ __device__ __forceinline__ void dense_rb(typename C2<T>::type (&v)[1 << RB], con
     for (int r0 = 0; r0 < (1 << RB); ++r0) {
         if (r0 & (1 << RBIT)) continue;
         if constexpr (MASKED) {
-            const bool pc = ((uint32_t)r0 & rmask) == rmask;
-            T mm[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) mm[k] = pc ? m[k] : ident<T>(k);
-            apply2<T, V>(mm, v[r0], v[r0 | (1 << RBIT)]);
+            // the register-control test is the same for every lane: a scalar
+            // branch skips the pairs it excludes
+            if (((uint32_t)r0 & rmask) == rmask) apply2<T, V>(m, v[r0], v[r0 | (1 << RBIT)]);
         } else {
             apply2<T, V>(m, v[r0], v[r0 | (1 << RBIT)]);
         }
@@ -108,10 +106,11 @@ __device__ __forceinline__ void not_rb(typename C2<T>::type (&v)[1 << RB], uint3
     for (int r0 = 0; r0 < (1 << RB); ++r0) {
         if (r0 & (1 << RBIT)) continue;
         const int r1 = r0 | (1 << RBIT);
-        bool c = true;
-        if constexpr (MASKED) c = ((uint32_t)r0 & rmask) == rmask;
-        if constexpr (LANE) c = c && sel;
-        if constexpr (!MASKED && !LANE) {
+        if constexpr (MASKED) {  // uniform over the wave: skip excluded pairs by a branch
+            if (((uint32_t)r0 & rmask) != rmask) continue;
+        }
+        const bool c = LANE ? sel : true;
+        if constexpr (!LANE) {
             const V t = v[r0];
             v[r0] = v[r1];
             v[r1] = t;
@@ -132,11 +131,8 @@ __device__ __forceinline__ void phase_op(typename C2<T>::type (&v)[1 << RB], T f
 {
     using V = typename C2<T>::type;
 #pragma unroll
-    for (int r = 0; r < (1 << RB); ++r) {
-        const bool pc = ((uint32_t)r & rmask) == rmask;
-        const T ar = pc ? fr : T(1), ai = pc ? fi : T(0);
-        v[r] = cmul<T, V>(ar, ai, v[r]);
-    }
+    for (int r = 0; r < (1 << RB); ++r)
+        if (((uint32_t)r & rmask) == rmask) v[r] = cmul<T, V>(fr, fi, v[r]);  // uniform branch
 }
 
 // Op codes: the host specialises every op so that the device dispatches with
@@ -145,7 +141,8 @@ __device__ __forceinline__ void phase_op(typename C2<T>::type (&v)[1 << RB], T f
 //                                  bit 1 thread-bit controls)
 //   code = 32 + 4 * rb + variant   NOT
 //   code = 64 + lane               phase (lane: thread-bit controls present)
-enum : int { kDense = 0, kNot = 32, kPhase = 64 };
+//   code = 96 + 4 * rb + variant   diagonal dense gate (u01 = u10 = 0)
+enum : int { kDense = 0, kNot = 32, kPhase = 64, kDiag = 96 };
 
 template <typename T, int RB, int RBIT, int VAR>
 __device__ __forceinline__ void dense_case(typename C2<T>::type (&v)[1 << RB], const FOp& op, uint32_t tid)
@@ -158,6 +155,31 @@ __device__ __forceinline__ void dense_case(typename C2<T>::type (&v)[1 << RB], c
         for (int k = 0; k < 8; ++k) m[k] = sel ? m[k] : ident<T>(k);
     }
     dense_rb<T, RB, RBIT, (VAR & 1) != 0>(v, m, op.rmask);
+}
+
+// Diagonal 2x2 on register bit RBIT: each amplitude of a pair is multiplied
+// by its diagonal entry (half the work of a dense product).
+template <typename T, int RB, int RBIT, int VAR>
+__device__ __forceinline__ void diag_case(typename C2<T>::type (&v)[1 << RB], const FOp& op, uint32_t tid)
+{
+    using V = typename C2<T>::type;
+    T d0r = (T)op.m[0], d0i = (T)op.m[1], d1r = (T)op.m[6], d1i = (T)op.m[7];
+    if constexpr (VAR & 2) {
+        const bool sel = (tid & op.tmask) == op.tmask;
+        d0r = sel ? d0r : T(1);
+        d0i = sel ? d0i : T(0);
+        d1r = sel ? d1r : T(1);
+        d1i = sel ? d1i : T(0);
+    }
+#pragma unroll
+    for (int r0 = 0; r0 < (1 << RB); ++r0) {
+        if (r0 & (1 << RBIT)) continue;
+        if constexpr (VAR & 1) {  // register controls: uniform over the wave
+            if (((uint32_t)r0 & op.rmask) != op.rmask) continue;
+        }
+        v[r0] = cmul<T, V>(d0r, d0i, v[r0]);
+        v[r0 | (1 << RBIT)] = cmul<T, V>(d1r, d1i, v[r0 | (1 << RBIT)]);
+    }
 }
 
 template <typename T, int RB, int RBIT, int VAR>
@@ -191,7 +213,11 @@ __device__ __forceinline__ void apply_op(typename C2<T>::type (&v)[1 << RB], con
     case kNot + 4 * RBIT + 0: if constexpr (RB > RBIT) not_case<T, RB, RBIT, 0>(v, op, tid); break;     \
     case kNot + 4 * RBIT + 1: if constexpr (RB > RBIT) not_case<T, RB, RBIT, 1>(v, op, tid); break;     \
     case kNot + 4 * RBIT + 2: if constexpr (RB > RBIT) not_case<T, RB, RBIT, 2>(v, op, tid); break;     \
-    case kNot + 4 * RBIT + 3: if constexpr (RB > RBIT) not_case<T, RB, RBIT, 3>(v, op, tid); break;
+    case kNot + 4 * RBIT + 3: if constexpr (RB > RBIT) not_case<T, RB, RBIT, 3>(v, op, tid); break;     \
+    case kDiag + 4 * RBIT + 0: if constexpr (RB > RBIT) diag_case<T, RB, RBIT, 0>(v, op, tid); break;   \
+    case kDiag + 4 * RBIT + 1: if constexpr (RB > RBIT) diag_case<T, RB, RBIT, 1>(v, op, tid); break;   \
+    case kDiag + 4 * RBIT + 2: if constexpr (RB > RBIT) diag_case<T, RB, RBIT, 2>(v, op, tid); break;   \
+    case kDiag + 4 * RBIT + 3: if constexpr (RB > RBIT) diag_case<T, RB, RBIT, 3>(v, op, tid); break;
     QS_DENSE(0) QS_DENSE(1) QS_DENSE(2) QS_DENSE(3) QS_DENSE(4)
 #undef QS_DENSE
     case kPhase + 0: phase_case<T, RB, false>(v, op, tid); break;
@@ -416,7 +442,8 @@ FOp encode_op(const OpRec& op, const PassPlan& P, const Layout& L)
     for (size_t b = 0; b < L.reg.size(); ++b)
         if (L.reg[b] == jt) f.rb = (int)b;
     const int var = (f.rmask ? 1 : 0) | (f.tmask ? 2 : 0);
-    f.kind = (op.kind == 0 ? kDense : kNot) + 4 * f.rb + var;
+    const bool diag = op.kind == 0 && op.u[2] == 0.0 && op.u[3] == 0.0 && op.u[4] == 0.0 && op.u[5] == 0.0;
+    f.kind = (op.kind == 0 ? (diag ? kDiag : kDense) : kNot) + 4 * f.rb + var;
     if (op.kind == 0)
         for (int k = 0; k < 8; ++k) f.m[k] = op.u[k];
     return f;

@@ -405,10 +405,16 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
                   << "              m[0] = f ? m[6] : t0; m[1] = f ? m[7] : t1; m[6] = f ? t0 : m[6]; m[7] = f ? t1 : m[7];\n"
                   << "              m[2] = f ? m[4] : t2; m[3] = f ? m[5] : t3; m[4] = f ? t2 : m[4]; m[5] = f ? t3 : m[5]; }\n";
             }
+            // a diagonal matrix (u01 = u10 = 0, e.g. a Z rotation) multiplies
+            // each amplitude of the pair by its own entry: half the work
+            const bool diag = op.u[2] == 0.0 && op.u[3] == 0.0 && op.u[4] == 0.0 && op.u[5] == 0.0;
             for (int r0 = 0; r0 < E; ++r0) {
                 if ((r0 >> b) & 1) continue;
                 if (((uint32_t)r0 & rmask) != rmask) continue;
-                s << "            qs_ap(m, " << vn(r0) << ", " << vn(r0 | (1 << b)) << ");\n";
+                if (diag)
+                    s << "            qs_cm(m[0], m[1], " << vn(r0) << "); qs_cm(m[6], m[7], " << vn(r0 | (1 << b)) << ");\n";
+                else
+                    s << "            qs_ap(m, " << vn(r0) << ", " << vn(r0 | (1 << b)) << ");\n";
             }
             s << "        }\n";
         }
