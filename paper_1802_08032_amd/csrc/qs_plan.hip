@@ -109,14 +109,58 @@ void plan_phases(PassPlan& P, const std::vector<OpRec>& all, int TB, int RB, int
         for (int idx : ops_left) push_targets(all[idx]);
         return pref;
     };
+    // number of remaining ops a phase with register qubits `regm` admits
+    auto admitted = [&](uint32_t regm) {
+        uint32_t blocked = 0;
+        int count = 0;
+        for (int idx : rem) {
+            const OpRec& op = all[idx];
+            const uint32_t m = lmask(op);
+            if (!(m & blocked) && (ltargets(op) & ~regm) == 0) {
+                ++count;
+            } else {
+                blocked |= m;
+            }
+        }
+        return count;
+    };
     bool first = true;
     while (!rem.empty()) {
         if ((int)P.phases.size() == max_phases) break;
         PhasePlan ph;
-        ph.lay = make_layout(TB, RB, pick_regs(TB, RB, preferred(rem), first, contig));
+        // the preferred register set, unless another RB-subset of the tile
+        // qubits admits more ops (fewer phases, fewer re-layouts)
+        std::vector<int> regs = pick_regs(TB, RB, preferred(rem), first, contig);
+        uint32_t best = 0;
+        for (int j : regs) best |= 1u << j;
+        int best_n = admitted(best);
+        const uint32_t allowed = ((1u << K) - 1) & ~(first ? (1u << contig) - 1 : 0u);
+        for (uint32_t s = allowed; s; s = (s - 1) & allowed) {
+            if (__builtin_popcount(s) != RB) continue;
+            const int c = admitted(s);
+            if (c > best_n) {
+                best_n = c;
+                best = s;
+            }
+        }
+        // a phase that takes every remaining op is the last one: keep qubits
+        // 0..contig-1 on the lanes if that costs nothing, so it can be stored
+        // without a final re-layout
+        const uint32_t low = (1u << contig) - 1;
+        if (best_n == (int)rem.size() && (best & low)) {
+            const uint32_t hi = allowed & ~low;
+            for (uint32_t s = hi; s; s = (s - 1) & hi)
+                if (__builtin_popcount(s) == RB && admitted(s) == best_n) {
+                    best = s;
+                    break;
+                }
+        }
+        regs.clear();
+        for (int j = 0; j < K; ++j)
+            if ((best >> j) & 1) regs.push_back(j);
+        ph.lay = make_layout(TB, RB, regs);
         first = false;
-        uint32_t regm = 0;
-        for (int j : ph.lay.reg) regm |= 1u << j;
+        uint32_t regm = best;
         uint32_t blocked = 0;
         std::vector<int> next;
         for (int idx : rem) {

@@ -81,8 +81,9 @@ def test_pass_merges_and_deferred_flips_in_source():
     assert any('qs_ap4(m' in s for s in srcs)
     flips = sum(s.count('const bool f') - s.count('const bool f =') for s in srcs)
     swaps = sum(s.count('const V ta =') for s in srcs)
-    # a materialised flip swaps the 8 register pairs of a 16-register thread
-    assert flips > 50 and swaps / 8 < flips / 4
+    # a materialised flip swaps the 8 register pairs of a 16-register thread;
+    # most thread-controlled NOTs stay flips
+    assert flips > 30 and swaps / 8 < flips
     pick = max(range(npass), key=lambda p: srcs[p].count('twf') + srcs[p].count(' ^ sf)'))
     rc, log, _ = compile_src(srcs[pick])
     assert rc == 0, log
