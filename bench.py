@@ -221,6 +221,74 @@ def batched_leg(q, torch, log, reps=5):
     return out
 
 
+def dm_leg(q, torch, log, N=14, depth=10, seed=2):
+    """14-qubit density matrix (its Eq. 2 vector has 2^28 entries, 4 GiB
+    complex128): the depth-10 layered circuit with depolarising, dephasing
+    and damping after every gate on each touched qubit, run one kernel per
+    op and as fused passes of the 28-qubit vector; trace, per-qubit outcome
+    probabilities, Hermiticity on sampled entry pairs, and fused vs per-op
+    agreement."""
+    from workloads import noisy_circuit
+    ops = noisy_circuit(N, depth, seed)
+    elem = 16
+    chans = sum(1 for o in ops if o.kind in ('dephasing', 'depolarising', 'damping'))
+    # one-pass-per-op byte model: a gate (Eq. 2 fused into one pass) or a
+    # channel reads and writes the whole vector, dephasing only its
+    # off-diagonal half of each 2x2 block
+    dm_bytes = sum(elem * (1 << (2 * N)) * (1 if o.kind == 'dephasing' else 2) for o in ops)
+    env = q.Env(0)
+    reg = q.Register(env, N, q.DENSITY, q.C128)
+    c = q.Circuit(ops)
+    out = {'qubits': N, 'vector_entries': 1 << (2 * N), 'ops': len(ops), 'gates': len(ops) - chans,
+           'channels': chans, 'tile': list(DEFAULT_TILE)}
+    times = []
+    for _ in range(2):
+        reg.init_zero()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.run(reg, 0)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    per_op = reg.tensor.clone()
+    out['per_op_s'] = min(times)
+    out['per_op_effective_gbps'] = dm_bytes / min(times) / 1e9
+    K, TB, L = DEFAULT_TILE
+    reg.init_zero()
+    c.run_compiled(reg, K, TB, 0, L)  # compile + warm
+    times = []
+    for _ in range(3):
+        reg.init_zero()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        passes = c.run_compiled(reg, K, TB, 0, L)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    out['fused_s'] = min(times)
+    out['fused_passes'] = passes
+    out['fused_speedup'] = out['per_op_s'] / out['fused_s']
+    out['fused_ops_per_s'] = len(ops) / out['fused_s']
+    out['fused_vs_per_op_max_abs'] = float((reg.tensor - per_op).abs().max())
+    del per_op
+    out['trace_error'] = abs(reg.calc_total_prob() - 1.0)
+    out['prob0_per_qubit'] = [reg.calc_prob_of_outcome(k, 0) for k in range(N)]
+    g = torch.Generator().manual_seed(seed)
+    j = torch.randint(0, 1 << N, (1 << 16,), generator=g).to(reg.tensor.device)
+    k = torch.randint(0, 1 << N, (1 << 16,), generator=g).to(reg.tensor.device)
+    a = reg.tensor[j + (k << N)]
+    b = reg.tensor[k + (j << N)]
+    out['max_hermiticity_error'] = float((a - b.conj()).abs().max())
+    log(f"density matrix {N} q: per-op {out['per_op_s']:.3f} s, fused {out['fused_s'] * 1e3:.1f} ms "
+        f"({passes} passes), trace error {out['trace_error']:.1e}")
+    c.close()
+    reg.close()
+    env.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+EXTRAS = ('unfused', 'pertarget', 'cpu', 'c64', 'batched', 'serving', 'dm')
+
+
 def serving_leg(q, torch, log, count=40):
     """Mixed request stream (80 % state vectors of 12..30 qubits, 20 % noisy
     density matrices of 8..13 qubits, log-uniform sizes, depth 5..40, every
@@ -261,10 +329,15 @@ def main():
     ap.add_argument('--depth', type=int, default=10)
     ap.add_argument('--tile', default=','.join(map(str, DEFAULT_TILE)),
                     help="K,TB,contig of the fused passes, or 'auto' (autotuner)")
-    ap.add_argument('--no-extras', action='store_true', help='skip unfused / per-target / CPU legs')
+    ap.add_argument('--no-extras', action='store_true', help='skip every leg beyond the timed steps')
+    ap.add_argument('--extras', default='all',
+                    help='comma-separated legs to run after the timed steps: ' + ','.join(EXTRAS) + ' (default all)')
     ap.add_argument('--copy-calibration', action='store_true',
                     help='only run a device copy of 16 GiB (HBM counter calibration)')
     args = ap.parse_args()
+    legs = set() if args.no_extras else (set(EXTRAS) if args.extras == 'all' else set(args.extras.split(',')))
+    if legs - set(EXTRAS):
+        sys.exit(f'unknown legs {sorted(legs - set(EXTRAS))}; choose from {",".join(EXTRAS)}')
     if args.gpus != 1:
         sys.exit('bench.py measures one GPU only: the method runs on one MI355X with the whole '
                  'state resident; --gpus above 1 is not supported.')
@@ -316,7 +389,7 @@ def main():
     env.profile_reset()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step(args.warmup + i)
+        passes = step(args.warmup + i)
         log(f'step {i} done')
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -370,7 +443,7 @@ def main():
         },
     }
 
-    if not args.no_extras:
+    if 'unfused' in legs:
         # unfused circuit (one kernel per gate, the paper's one pass per gate)
         log('unfused circuit')
         reg.init_zero()
@@ -382,9 +455,10 @@ def main():
         out['unfused_gates_per_s'] = gates / t_unf
         out['unfused_effective_gbps'] = algorithmic_bytes(ops, n, elem) / t_unf / 1e9
         out['fused_pass_speedup'] = t_unf / (fused_ms / max(1, launches) * passes * 1e-3)
-        if tuned is not None:
-            out['autotune_trials'] = [{k: t[k] for k in ('tile_qubits', 'thread_bits', 'contig_qubits', 'passes',
-                                                          'seconds')} for t in tuned.get('trials', [])]
+    if tuned is not None:
+        out['autotune_trials'] = [{k: t[k] for k in ('tile_qubits', 'thread_bits', 'contig_qubits', 'passes',
+                                                      'seconds')} for t in tuned.get('trials', [])]
+    if 'pertarget' in legs:
         # per-target effective bandwidth of one dense gate (median of 5)
         log('per-target sweep')
         u = ops[0].u
@@ -401,18 +475,24 @@ def main():
                 times.append(s.elapsed_time(e))
             per_t.append(round(2 * elem * (1 << n) / (sorted(times)[2] * 1e-3) / 1e9, 1))
         out['per_target_gbps'] = per_t
+    if 'cpu' in legs:
         log('cpu baseline')
         out['cpu_baseline'] = cpu_baseline(ops, n)
     circ.close()
     reg.close()
     env.close()
-    if not args.no_extras:
-        del reg
-        torch.cuda.empty_cache()
+    del reg
+    torch.cuda.empty_cache()
+    if 'c64' in legs:
         log('33-qubit complex64 vs complex128')
         out['c64_33q'] = c64_33q_leg(q, torch, log)
+    if 'dm' in legs:
+        log('14-qubit noisy density matrix')
+        out['density_matrix'] = dm_leg(q, torch, log)
+    if 'batched' in legs:
         log('batched registers')
         out['batched'] = batched_leg(q, torch, log)
+    if 'serving' in legs:
         log('serving')
         out['serving'] = serving_leg(q, torch, log)
     print(json.dumps(out), flush=True)
