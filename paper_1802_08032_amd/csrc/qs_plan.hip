@@ -222,7 +222,7 @@ std::vector<int> scan_pass(const std::vector<OpRec>& all, const std::vector<char
 // admits the most ops wins (the greedy one on ties).  Runs suit circuits
 // with nearest-neighbour two-qubit gates, whose light cones are intervals.
 std::vector<PassPlan> partition(const std::vector<OpRec>& all, int n, int TB, int RB, int max_phases,
-                                int max_ops, int contig, int windows)
+                                int max_ops, int contig, int windows, bool lookahead)
 {
     const int K = TB + RB;
     std::vector<PassPlan> passes;
@@ -239,16 +239,45 @@ std::vector<PassPlan> partition(const std::vector<OpRec>& all, int n, int TB, in
         for (int s = contig; s + a <= h && s + h + (w - a) <= n; ++s)
             cands.push_back(low | run(s, a) | run(s + h, w - a));
     }
+    // ops the best candidate admits on top of `done` (lookahead)
+    auto best_next = [&](std::vector<char>& d) {
+        size_t f = 0;
+        while (f < all.size() && d[f]) ++f;
+        if (f == all.size()) return (size_t)0;
+        uint64_t S = low;
+        int ssize = contig;
+        size_t best = scan_pass(all, d, f, S, ssize, K, max_ops, true).size();
+        for (uint64_t c : cands) {
+            uint64_t Sw = c;
+            int sz = __builtin_popcountll(c);
+            best = std::max(best, scan_pass(all, d, f, Sw, sz, K, max_ops, false).size());
+        }
+        return best;
+    };
     while (ndone < all.size()) {
         while (done[first]) ++first;
         uint64_t S = low;
         int ssize = contig;
         std::vector<int> take = scan_pass(all, done, first, S, ssize, K, max_ops, true);
+        size_t score = 0;
+        if (lookahead) {
+            for (int idx : take) done[idx] = 1;
+            score = take.size() + best_next(done);
+            for (int idx : take) done[idx] = 0;
+        }
         for (uint64_t c : cands) {
             uint64_t Sw = c;
             int sz = __builtin_popcountll(c);
             std::vector<int> tw = scan_pass(all, done, first, Sw, sz, K, max_ops, false);
-            if (tw.size() > take.size()) {
+            bool better = tw.size() > take.size();
+            if (lookahead) {
+                for (int idx : tw) done[idx] = 1;
+                const size_t sc = tw.size() + best_next(done);
+                for (int idx : tw) done[idx] = 0;
+                better = sc > score || (sc == score && tw.size() > take.size());
+                if (better) score = sc;
+            }
+            if (better) {
                 take.swap(tw);
                 S = Sw;
                 ssize = sz;
@@ -282,10 +311,14 @@ std::vector<PassPlan> partition(const std::vector<OpRec>& all, int n, int TB, in
 std::vector<PassPlan> plan_passes(const std::vector<OpRec>& all, int n, int TB, int RB, int max_phases,
                                   int max_ops, int contig)
 {
-    std::vector<PassPlan> best = partition(all, n, TB, RB, max_phases, max_ops, contig, 0);
+    std::vector<PassPlan> best = partition(all, n, TB, RB, max_phases, max_ops, contig, 0, false);
     for (int mode = 1; mode <= 2; ++mode) {
-        std::vector<PassPlan> p = partition(all, n, TB, RB, max_phases, max_ops, contig, mode);
+        std::vector<PassPlan> p = partition(all, n, TB, RB, max_phases, max_ops, contig, mode, false);
         if (p.size() <= best.size()) best.swap(p);
+    }
+    {
+        std::vector<PassPlan> p = partition(all, n, TB, RB, max_phases, max_ops, contig, 2, true);
+        if (p.size() < best.size()) best.swap(p);
     }
     return best;
 }
