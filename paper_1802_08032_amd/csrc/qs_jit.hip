@@ -624,7 +624,9 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
             c->jit = nullptr;
         }
         const bool dbl = r->prec == QS_C128;
-        std::vector<PassPlan> plan = plan_passes(ops, nbits, cfg.TB, cfg.RB, cfg.max_phases, 1 << 12, cfg.contig);
+        // compiled plans are reused: worth the slower lookahead partition
+        std::vector<PassPlan> plan =
+            plan_passes(ops, nbits, cfg.TB, cfg.RB, cfg.max_phases, 1 << 12, cfg.contig, true);
         std::vector<OpRec> ext(ops);
         for (PassPlan& P : plan) merge_phase_ops(P, ext);
         std::vector<std::string> srcs;
@@ -695,7 +697,7 @@ qs_status generate_sources(const std::vector<OpRec>& circuit_ops, int n, int kin
     if (kind == QS_DENSITY) dm_ops = dm_vector_ops(circuit_ops, n);
     const std::vector<OpRec>& ops = kind == QS_DENSITY ? dm_ops : circuit_ops;
     if (kind == QS_DENSITY) n *= 2;
-    std::vector<PassPlan> plan = plan_passes(ops, n, cfg.TB, cfg.RB, cfg.max_phases, 1 << 12, cfg.contig);
+    std::vector<PassPlan> plan = plan_passes(ops, n, cfg.TB, cfg.RB, cfg.max_phases, 1 << 12, cfg.contig, true);
     std::vector<OpRec> ext(ops);
     for (PassPlan& P : plan) merge_phase_ops(P, ext);
     out.clear();

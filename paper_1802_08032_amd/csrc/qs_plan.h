@@ -34,8 +34,10 @@ uint64_t qubit_mask(const OpRec& op);
 bool coalesced(const Layout& L, int contig);
 // contig: global qubits 0..contig-1 sit on the first lanes whenever the tile
 // is read from or written to HBM (contiguous runs of 2^contig amplitudes).
+// lookahead: also try a partition whose tile sets look one pass ahead
+// (slower planning; for plans that are compiled and reused).
 std::vector<PassPlan> plan_passes(const std::vector<OpRec>& all, int n, int TB, int RB, int max_phases,
-                                  int max_ops, int contig);
+                                  int max_ops, int contig, bool lookahead = false);
 // Within every phase of P, replace runs of ops that act on at most two
 // register qubits and carry no thread or tile condition by their product
 // (a 2x2 dense op or a 4x4 kind-4 op), wherever that takes fewer

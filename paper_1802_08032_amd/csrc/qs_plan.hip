@@ -307,16 +307,20 @@ std::vector<PassPlan> partition(const std::vector<OpRec>& all, int n, int TB, in
 
 // Three partitions (greedy only, with runs, with runs and pairs of runs);
 // the one with the fewest passes is kept (a pass costs one HBM round trip
-// of the state), the later one on ties.
+// of the state), the later one on ties.  With `lookahead`, a fourth
+// partition picks each pass's tile set by the ops it admits plus the most
+// the next pass could then admit; it is kept only if it needs fewer passes.
+// That costs about as many scans as the candidates squared per pass (tens
+// of milliseconds for a few hundred ops), worth it where a plan is reused.
 std::vector<PassPlan> plan_passes(const std::vector<OpRec>& all, int n, int TB, int RB, int max_phases,
-                                  int max_ops, int contig)
+                                  int max_ops, int contig, bool lookahead)
 {
     std::vector<PassPlan> best = partition(all, n, TB, RB, max_phases, max_ops, contig, 0, false);
     for (int mode = 1; mode <= 2; ++mode) {
         std::vector<PassPlan> p = partition(all, n, TB, RB, max_phases, max_ops, contig, mode, false);
         if (p.size() <= best.size()) best.swap(p);
     }
-    {
+    if (lookahead) {
         std::vector<PassPlan> p = partition(all, n, TB, RB, max_phases, max_ops, contig, 2, true);
         if (p.size() < best.size()) best.swap(p);
     }
