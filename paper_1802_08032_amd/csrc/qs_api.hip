@@ -628,6 +628,24 @@ qs_status qs_calc_prob_of_outcome(qs_reg r, int qubit, int outcome, double* out)
     qs_status s = check_target(qubit, r->n);
     if (s) return s;
     if (outcome != 0 && outcome != 1) return qs::set_error(QS_E_ARG, "outcome must be 0 or 1");
+    // A state-vector qubit at or above the 128-byte line (8 complex128 or 16
+    // complex64 amplitudes) splits the state into halves of whole lines:
+    // read only the outcome's half.
+    if (r->kind == QS_STATEVEC && qubit >= (r->prec == QS_C128 ? 3 : 4)) {
+        const qs::Launch L = launch_of(r);
+        double* partials = r->scratch;
+        double* dev_out = r->scratch + 4 * qs::kReduceBlocks;
+        s = qs::profiled(r, QS_K_REDUCE, [&](int*) {
+            return r->prec == QS_C128
+                       ? qs::launch_prob_half_sv<double>(L, r->amp, r->nbits, qubit, outcome, partials, dev_out)
+                       : qs::launch_prob_half_sv<float>(L, r->amp, r->nbits, qubit, outcome, partials, dev_out);
+        });
+        if (s) return s;
+        QS_HIP(hipMemcpyAsync(r->host_res, dev_out, 2 * sizeof(double), hipMemcpyDeviceToHost, r->stream));
+        if ((s = sync_stream(r))) return s;
+        *out = r->host_res[0];
+        return QS_OK;
+    }
     double v[2];
     if ((s = probs(r, qubit, v))) return s;
     *out = v[outcome];

@@ -56,6 +56,11 @@ template <typename T> hipError_t launch_dm_channel(const Launch& L, void* rho, i
 constexpr int kReduceBlocks = 1024;
 template <typename T> hipError_t launch_prob_sv(const Launch& L, const void* amp, int nbits, int q,
                                                 double* partials, double* dev_out);
+// Sum of |alpha|^2 over the indices whose bit q equals `outcome`, reading
+// only those (half the state when q is at least the line bits: 3 for
+// complex128, 4 for complex64).  Writes {sum, 0} to `dev_out`.
+template <typename T> hipError_t launch_prob_half_sv(const Launch& L, const void* amp, int nbits, int q,
+                                                     int outcome, double* partials, double* dev_out);
 template <typename T> hipError_t launch_prob_dm(const Launch& L, const void* rho, int N, int q,
                                                 double* partials, double* dev_out);
 template <typename T> hipError_t launch_collapse_sv(const Launch& L, void* amp, int nbits, int q,

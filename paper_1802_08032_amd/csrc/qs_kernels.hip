@@ -449,6 +449,39 @@ __global__ __launch_bounds__(kBlock) void k_prob_sv(const typename C2<T>::type* 
     block_store2(s0, s1, partials);
 }
 
+// Sum |alpha_i|^2 over the indices i whose bit q equals o, reading only
+// those: item k stands for k with bit o inserted at position q.  With q at
+// or above the line bits every 128-byte line lies in one half, so half the
+// state is read.
+template <typename T, int U>
+__global__ __launch_bounds__(kBlock) void k_prob_half_sv(const typename C2<T>::type* __restrict__ amp,
+                                                         uint64_t half, int q, int o, double* partials)
+{
+    static_assert(U % 2 == 0, "the step order alternates two half-runs");
+    using V = typename C2<T>::type;
+    NSum s0 = {0.0, 0.0}, s1 = {0.0, 0.0};
+    const uint64_t ps = (uint64_t)kBlock * U;
+    const uint64_t low = (1ull << q) - 1, bit = (uint64_t)o << q;
+    for (uint64_t s = blockIdx.x; step_base(s, ps) < half; s += gridDim.x) {
+        const uint64_t c = step_base(s, ps);
+        V v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t k0 = step_item(c, j, ps);
+            const uint64_t k = k0 < half ? k0 : half - 1;
+            v[j] = ldnt(amp + (((k & ~low) << 1) | bit | (k & low)));
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const double p = step_item(c, j, ps) < half
+                                 ? (double)v[j].x * (double)v[j].x + (double)v[j].y * (double)v[j].y
+                                 : 0.0;
+            nadd(s0, p);
+        }
+    }
+    block_store2(s0, s1, partials);
+}
+
 // Sum Re rho[j][j] split by bit q of j (the diagonal is entry j (2^N + 1)).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prob_dm(const typename C2<T>::type* __restrict__ rho,
@@ -887,6 +920,25 @@ hipError_t launch_prob_sv(const Launch& L, const void* amp, int nbits, int q, do
 }
 
 template <typename T>
+hipError_t launch_prob_half_sv(const Launch& L, const void* amp, int nbits, int q, int outcome, double* partials,
+                               double* dev_out)
+{
+    using V = typename C2<T>::type;
+    const uint64_t half = 1ull << (nbits - 1);
+    const bool big = wide(half, kPer<T>);
+    int grid = grid_for(half, big ? kPer<T> : kSmallPer);
+    if (grid > kReduceBlocks) grid = kReduceBlocks;
+    if (big)
+        hipLaunchKernelGGL((k_prob_half_sv<T, kPer<T>>), dim3(grid), dim3(kBlock), 0, L.stream, (const V*)amp, half,
+                           q, outcome, partials);
+    else
+        hipLaunchKernelGGL((k_prob_half_sv<T, kSmallPer>), dim3(grid), dim3(kBlock), 0, L.stream, (const V*)amp, half,
+                           q, outcome, partials);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, L.stream, partials, grid, dev_out);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_prob_dm(const Launch& L, const void* rho, int N, int q, double* partials,
                           double* dev_out)
 {
@@ -941,6 +993,7 @@ hipError_t launch_collapse_dm(const Launch& L, void* rho, int N, int q, int outc
                                           const Mat2<T>&);                                             \
     template hipError_t launch_dm_channel<T>(const Launch&, void*, int, int, int, double);             \
     template hipError_t launch_prob_sv<T>(const Launch&, const void*, int, int, double*, double*);     \
+    template hipError_t launch_prob_half_sv<T>(const Launch&, const void*, int, int, int, double*, double*); \
     template hipError_t launch_prob_dm<T>(const Launch&, const void*, int, int, double*, double*);     \
     template hipError_t launch_collapse_sv<T>(const Launch&, void*, int, int, int, double);            \
     template hipError_t launch_collapse_dm<T>(const Launch&, void*, int, int, int, double);

@@ -138,6 +138,24 @@ def test_probabilities_and_measurement_bit_exact(q, env):
     reg.close()
 
 
+@pytest.mark.parametrize('prec,n', [('C128', 4), ('C128', 23), ('C64', 5), ('C64', 23)])
+def test_prob_of_outcome_half_and_full_reads(q, env, prec, n):
+    """calcProbOfOutcome for every qubit and outcome.  Qubits below the
+    128-byte line sum over the whole state; the others read only the
+    outcome's half: a register whose half is shorter than one workgroup
+    step, and 23 qubits, where the large-step kernel instance runs."""
+    log(f'prob of outcome {prec} n={n}')
+    state = random_state(n, 40 + n)
+    reg = q.Register(env, n, q.STATEVEC, getattr(q, prec))
+    reg.set_amps(state)
+    # the register holds the state rounded to its precision
+    ref = state if prec == 'C128' else state.astype(np.complex64).astype(np.complex128)
+    for qb in range(n):
+        for o in (0, 1):
+            assert abs(reg.calc_prob_of_outcome(qb, o) - O.sv_prob_outcome(ref, n, qb, o)) <= TOL128, (qb, o)
+    reg.close()
+
+
 def test_measure_deterministic_edges(q, env):
     reg = q.Register(env, 4)
     reg.init_basis(0b0101)
