@@ -85,32 +85,55 @@ def recorded_traffic(n, K, TB, L):
     return None
 
 
-def cpu_baseline(ops_full, n_full, sample_qubits=28, budget_s=12.0):
+def cpu_model():
+    try:
+        for line in open('/proc/cpuinfo'):
+            if line.startswith('model name'):
+                return line.split(':', 1)[1].strip()
+    except OSError:
+        pass
+    return 'unknown'
+
+
+def cpu_baseline(ops_full, n_full, sample_qubits=28, budget_s=12.0, single_qubits=26, single_budget_s=6.0):
     """Oracle (plain CPU code) applying the same circuit's gates to a
     sample_qubits register until ~budget_s elapses; scaled to n_full by the
     2^(n_full - sample_qubits) amplitude ratio (the cost per gate is linear
-    in the number of amplitudes)."""
+    in the number of amplitudes).  Timed with the process's OpenMP threads,
+    then on one thread over a smaller sample."""
     import oracle as O
-    n = sample_qubits
-    amp = O.zero_state(n)
-    ops = [o for o in ops_full if max(o.touched()) < n][:200]
-    t0 = time.perf_counter()
-    done = 0
-    for op in ops:
-        O.apply_sv(amp, n, op)
-        done += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    per_gate_full = dt / done * (1 << (n_full - n))
+
+    def sample(n, budget):
+        amp = O.zero_state(n)
+        ops = [o for o in ops_full if max(o.touched()) < n][:200]
+        t0 = time.perf_counter()
+        done = 0
+        for op in ops:
+            O.apply_sv(amp, n, op)
+            done += 1
+            if time.perf_counter() - t0 > budget:
+                break
+        dt = time.perf_counter() - t0
+        return 1.0 / (dt / done * (1 << (n_full - n))), (f'first {done} gates of the same circuit on a {n}-qubit '
+                                                        f'complex128 register ({dt:.1f} s), scaled by '
+                                                        f'2^{n_full - n} to {n_full} qubits')
+
     threads = int(os.environ.get('OMP_NUM_THREADS', os.cpu_count() or 1))
+    value, text = sample(sample_qubits, budget_s)
+    prev = O.set_threads(1)
+    try:
+        value1, text1 = sample(single_qubits, single_budget_s)
+    finally:
+        O.set_threads(prev)
     return {
-        'value': 1.0 / per_gate_full,
+        'value': value,
         'unit': 'gates/s',
         'cores': threads,
         'kind': 'oracle',
-        'sample': f'first {done} gates of the same circuit on a {n}-qubit complex128 register '
-                  f'({dt:.1f} s), scaled by 2^{n_full - n} to {n_full} qubits',
+        'sample': text,
+        'cpu_model': cpu_model(),
+        'logical_cpus': os.cpu_count(),
+        'single_thread': {'value': value1, 'unit': 'gates/s', 'cores': 1, 'sample': text1},
     }
 
 

@@ -67,6 +67,7 @@ def lib():
             'or_dm_prob_outcome': (d, [vp, i, i, i]),
             'or_dm_measure': (i, [vp, i, i, d, C.POINTER(d)]),
             'or_neumaier_sum': (d, [vp, u64]),
+            'or_set_threads': (i, [i]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -282,3 +283,9 @@ def amps_after(n, product_vectors, ops, indices) -> np.ndarray:
 def neumaier_sum(x) -> float:
     a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
     return lib().or_neumaier_sum(_p(a), a.size)
+
+
+def set_threads(n: int) -> int:
+    """Thread count of the oracle's OpenMP loops (timing only); returns the
+    previous count."""
+    return lib().or_set_threads(int(n))

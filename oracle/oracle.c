@@ -10,6 +10,7 @@
 #include "oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 
 static uint64_t mask_of(const int* qs, int nq)
@@ -291,4 +292,11 @@ or_cplx or_sv_amp_after(int n, const or_cplx* v, const or_gate* gates, int ng,
                         uint64_t index)
 {
     return amp_rec(n, v, gates, ng, index);
+}
+
+int or_set_threads(int n)
+{
+    const int prev = omp_get_max_threads();
+    omp_set_num_threads(n);
+    return prev;
 }

@@ -74,6 +74,10 @@ int or_dm_measure(or_cplx* rho, int N, int q, double r, double* prob);
 or_cplx or_sv_amp_after(int n, const or_cplx* v, const or_gate* gates, int ng,
                         uint64_t index);
 
+/* Thread count of the OpenMP loops, for timing only (results do not depend
+ * on it).  Returns the previous count. */
+int or_set_threads(int n);
+
 /* Neumaier-compensated sum of x[0..len) (exposed for its own pin). */
 double or_neumaier_sum(const double* x, uint64_t len);
 

@@ -213,3 +213,19 @@ def test_haar_inputs_are_unitary_and_uniform():
     m = np.mean([abs(u[0, 0]) ** 2 for u in us])
     assert abs(m - 0.5) < 0.02
     assert np.array_equal(X @ X, np.eye(2))
+
+
+def test_oracle_result_independent_of_thread_count():
+    """Every amplitude pair is computed by one expression whatever the
+    OpenMP split, so one thread and all threads give identical bits (17
+    qubits: large enough for the parallel loops)."""
+    n = 17
+    ops = layered_circuit(n, 2, 5, mcphase=True)
+    prev = O.set_threads(1)
+    try:
+        one = O.run_sv(n, ops)
+    finally:
+        O.set_threads(prev)
+    many = O.run_sv(n, ops)
+    assert np.array_equal(one, many)
+    assert O.sv_prob_outcome(one, n, 16, 1) == O.sv_prob_outcome(many, n, 16, 1)
