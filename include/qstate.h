@@ -173,6 +173,29 @@ qs_status qs_measure(qs_reg r, int qubit, double u01, int* outcome, double* prob
  * zero probability; the register is unchanged then.  Synchronous. */
 qs_status qs_measure_all(qs_reg r, const double* u01, int* outcomes, double* probs);
 
+/* ---- seeded draws (the paper leaves the source of measurement randomness
+ * open; these calls give reproducible draws without caller-side RNG) ----- */
+
+/* Uniform doubles in [0, 1) from the counter-based generator Philox4x64-10
+ * (Salmon, Moraes, Dror and Shaw, SC'11) under key (seed, stream): draw k
+ * is word k mod 4 of the ten-round Philox bijection of the 256-bit counter
+ * k / 4 + 1, taken as (x >> 11) * 2^-53.  This is the stream of
+ * numpy.random.Philox(key=[seed, stream]).  Writes out[0..count) = draws
+ * first .. first + count - 1.  Host only; needs no device.  QS_E_ARG for a
+ * NULL out or a negative count. */
+qs_status qs_philox_draws(uint64_t seed, uint64_t stream, uint64_t first, int count, double* out);
+/* Give `env` the draw stream (seed, stream) and rewind it to draw 0.  An
+ * environment never seeded uses (0, 0). */
+qs_status qs_env_seed(qs_env env, uint64_t seed, uint64_t stream);
+/* qs_measure with the next draw of the register's environment stream.  The
+ * stream advances by one draw when the call succeeds and not otherwise.
+ * Registers sharing an environment take draws in call order (calls from
+ * several threads at once take them in an unspecified order). */
+qs_status qs_measure_seeded(qs_reg r, int qubit, int* outcome, double* prob);
+/* qs_measure_all with the next n draws of the register's environment
+ * stream (n = register qubits); advances the stream by n on success. */
+qs_status qs_measure_all_seeded(qs_reg r, int* outcomes, double* probs);
+
 /* ---- circuits: recorded gate lists with optional gate fusion ------------ */
 
 qs_status qs_circuit_create(qs_circuit* out);

@@ -289,6 +289,59 @@ extern "C" {
 
 const char* qs_last_error(void) { return g_error.c_str(); }
 
+// ---- seeded draws: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel
+// random numbers: as easy as 1, 2, 3", SC'11) -------------------------------
+namespace {
+
+struct Ctr4 {
+    uint64_t v[4];
+};
+
+// The ten-round Philox bijection of a 256-bit counter under a 128-bit key:
+// each round multiplies words 0 and 2 by the round constants into 128-bit
+// products and mixes their halves with words 1 and 3 and the key; the key
+// is bumped by the Weyl constants between rounds.
+Ctr4 philox4x64_10(Ctr4 c, uint64_t k0, uint64_t k1)
+{
+    const uint64_t m0 = 0xD2E7470EE14C6C93ull, m1 = 0xCA5A826395121157ull;
+    const uint64_t w0 = 0x9E3779B97F4A7C15ull, w1 = 0xBB67AE8584CAA73Bull;
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += w0;
+            k1 += w1;
+        }
+        const unsigned __int128 p0 = (unsigned __int128)m0 * c.v[0];
+        const unsigned __int128 p1 = (unsigned __int128)m1 * c.v[2];
+        const uint64_t h0 = (uint64_t)(p0 >> 64), l0 = (uint64_t)p0;
+        const uint64_t h1 = (uint64_t)(p1 >> 64), l1 = (uint64_t)p1;
+        c = Ctr4{{h1 ^ c.v[1] ^ k0, l1, h0 ^ c.v[3] ^ k1, l0}};
+    }
+    return c;
+}
+
+void philox_fill(uint64_t seed, uint64_t stream, uint64_t first, int count, double* out)
+{
+    for (int i = 0; i < count;) {
+        const uint64_t k = first + (uint64_t)i;
+        // block counter k / 4 + 1 (a 256-bit integer whose upper words stay
+        // 0, since k / 4 + 1 < 2^62)
+        Ctr4 c = {{k / 4 + 1, 0, 0, 0}};
+        c = philox4x64_10(c, seed, stream);
+        for (uint64_t w = k % 4; w < 4 && i < count; ++w, ++i)
+            out[i] = (double)(c.v[w] >> 11) * (1.0 / 9007199254740992.0);
+    }
+}
+
+}  // namespace
+
+qs_status qs_philox_draws(uint64_t seed, uint64_t stream, uint64_t first, int count, double* out)
+{
+    if (count < 0) return qs::set_error(QS_E_ARG, "negative count");
+    if (count > 0 && !out) return qs::set_error(QS_E_ARG, "NULL output");
+    philox_fill(seed, stream, first, count, out);
+    return QS_OK;
+}
+
 qs_status qs_env_create(int device, qs_env* out)
 {
     if (!out) return qs::set_error(QS_E_ARG, "NULL output");
@@ -306,6 +359,16 @@ qs_status qs_env_create(int device, qs_env* out)
     }
     handle_add(e);
     *out = e;
+    return QS_OK;
+}
+
+qs_status qs_env_seed(qs_env env, uint64_t seed, uint64_t stream)
+{
+    if (!valid_env(env)) return qs::set_error(QS_E_HANDLE, "invalid environment handle");
+    std::lock_guard<std::mutex> g(env->mu);
+    env->rng_seed = seed;
+    env->rng_stream = stream;
+    env->rng_next = 0;
     return QS_OK;
 }
 
@@ -805,6 +868,45 @@ qs_status qs_measure_all(qs_reg r, const double* u01, int* outcomes, double* pro
         if (probs) probs[k] = out_p[k];
     }
     return QS_OK;
+}
+
+// Draws [first, first + count) of the register's environment stream, and
+// the first index; the stream is advanced by the caller on success.
+namespace {
+uint64_t next_draws(qs_reg r, int count, double* out)
+{
+    std::lock_guard<std::mutex> g(r->env->mu);
+    philox_fill(r->env->rng_seed, r->env->rng_stream, r->env->rng_next, count, out);
+    return r->env->rng_next;
+}
+
+void advance_draws(qs_reg r, uint64_t first, int count)
+{
+    std::lock_guard<std::mutex> g(r->env->mu);
+    // another call may have advanced the stream meanwhile: move on from
+    // whichever is further
+    r->env->rng_next = std::max(r->env->rng_next, first + (uint64_t)count);
+}
+}  // namespace
+
+qs_status qs_measure_seeded(qs_reg r, int qubit, int* outcome, double* prob)
+{
+    QS_CHECK_REG(r);
+    double u = 0.0;
+    const uint64_t first = next_draws(r, 1, &u);
+    const qs_status s = qs_measure(r, qubit, u, outcome, prob);
+    if (s == QS_OK) advance_draws(r, first, 1);
+    return s;
+}
+
+qs_status qs_measure_all_seeded(qs_reg r, int* outcomes, double* probs)
+{
+    QS_CHECK_REG(r);
+    std::vector<double> u(r->n);
+    const uint64_t first = next_draws(r, r->n, u.data());
+    const qs_status s = qs_measure_all(r, u.data(), outcomes, probs);
+    if (s == QS_OK) advance_draws(r, first, r->n);
+    return s;
 }
 
 // --- circuits ----------------------------------------------------------------

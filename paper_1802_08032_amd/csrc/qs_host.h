@@ -23,6 +23,8 @@ struct qs_env_s {
     uint64_t launches[QS_K_COUNT];
     double ms[QS_K_COUNT];
     std::mutex mu;
+    // measurement draw stream (qs_env_seed): Philox key and next draw index
+    uint64_t rng_seed = 0, rng_stream = 0, rng_next = 0;
     // reduction scratch of destroyed registers, reused by new ones so that
     // register turnover never frees device memory (which would synchronise
     // the whole device)

@@ -72,6 +72,10 @@ SIGNATURES = {
     'qs_calc_prob_of_outcome': (_i, [_vp, _i, _i, _PD]),
     'qs_measure': (_i, [_vp, _i, _d, _PI, _PD]),
     'qs_measure_all': (_i, [_vp, _PD, _PI, _PD]),
+    'qs_philox_draws': (_i, [_u64, _u64, _u64, _i, _PD]),
+    'qs_env_seed': (_i, [_vp, _u64, _u64]),
+    'qs_measure_seeded': (_i, [_vp, _i, _PI, _PD]),
+    'qs_measure_all_seeded': (_i, [_vp, _PI, _PD]),
     'qs_circuit_create': (_i, [C.POINTER(_vp)]),
     'qs_circuit_destroy': (_i, [_vp]),
     'qs_circuit_add_unitary': (_i, [_vp, _vp, _i, _i, _vp]),
@@ -125,6 +129,14 @@ def _mat(u):
     return (Cplx * 4)(*[Cplx(float(z.real), float(z.imag)) for z in m])
 
 
+def philox_draws(seed: int, stream: int, first: int, count: int) -> np.ndarray:
+    """Draws first .. first + count - 1 of the library's Philox4x64-10 stream
+    (seed, stream), as doubles in [0, 1)."""
+    out = np.empty(max(count, 0), dtype=np.float64)  # the library rejects a negative count
+    _check(lib().qs_philox_draws(seed & (2**64 - 1), stream & (2**64 - 1), first, count, out.ctypes.data_as(_PD)))
+    return out
+
+
 def reg_bytes(n: int, kind: int = STATEVEC, prec: int = C128) -> int:
     return lib().qs_reg_bytes(n, kind, prec)
 
@@ -140,6 +152,11 @@ class Env:
 
     def sync(self):
         _check(lib().qs_env_sync(self.h))
+
+    def seed(self, seed: int, stream: int = 0):
+        """Measurement draw stream (seed, stream) for the *_seeded calls,
+        rewound to its first draw."""
+        _check(lib().qs_env_seed(self.h, seed & (2**64 - 1), stream & (2**64 - 1)))
 
     def profile(self, enable: bool = True):
         _check(lib().qs_profile_enable(self.h, int(enable)))
@@ -289,6 +306,19 @@ class Register:
         o = (C.c_int * self.n)()
         p = (C.c_double * self.n)()
         _check(lib().qs_measure_all(self.h, d.ctypes.data_as(_PD), o, p))
+        return list(o), list(p)
+
+    def measure_seeded(self, qubit: int):
+        """qs_measure with the next draw of the environment's stream."""
+        o, p = C.c_int(), C.c_double()
+        _check(lib().qs_measure_seeded(self.h, qubit, C.byref(o), C.byref(p)))
+        return o.value, p.value
+
+    def measure_all_seeded(self):
+        """qs_measure_all with the environment stream's next n draws."""
+        o = (C.c_int * self.n)()
+        p = (C.c_double * self.n)()
+        _check(lib().qs_measure_all_seeded(self.h, o, p))
         return list(o), list(p)
 
 

@@ -53,3 +53,19 @@ def test_paper_memory_figures():
             assert need > limit, r
         else:
             assert need == limit, r
+
+
+def test_philox_draws_are_numpy_philox4x64_stream():
+    """qs_philox_draws (host only) is the Philox4x64-10 stream of Salmon et
+    al. (SC'11) as numpy implements it: the same doubles, bit for bit, from
+    the start and from an offset inside a 4-word block, for small keys and
+    keys near 2^64."""
+    import numpy as np
+    import paper_1802_08032_amd as q
+    for seed, stream in ((0, 0), (7, 3), (2**64 - 1, 2**63 + 5)):
+        ref = np.random.Generator(np.random.Philox(key=[seed, stream])).random(40)
+        assert np.array_equal(q.philox_draws(seed, stream, 0, 40), ref)
+        assert np.array_equal(q.philox_draws(seed, stream, 5, 30), ref[5:35])
+    assert q.philox_draws(1, 2, 0, 0).size == 0
+    with pytest.raises(q.QStateError):
+        q.philox_draws(1, 2, 0, -1)

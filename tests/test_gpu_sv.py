@@ -414,3 +414,39 @@ def test_compiled_random_sweep(q, env, seed):
     assert max_abs(reg.get_amps(), ref) <= TOL128
     c.close()
     reg.close()
+
+
+def test_seeded_measurement_takes_the_environment_stream(q):
+    """qs_measure_seeded / qs_measure_all_seeded give exactly what
+    qs_measure / qs_measure_all give with numpy's Philox draws of the same
+    (seed, stream); a rejected call does not advance the stream, and
+    reseeding rewinds it."""
+    n = 10
+    ops = layered_circuit(n, 4, 12, mcphase=True)
+    e = q.Env(0)
+    e.seed(21, 4)
+    draws = measurement_draws(21, 4, 3 + n + 1)
+
+    def fresh():
+        r = q.Register(e, n, q.STATEVEC, q.C128)
+        r.init_zero()
+        c = q.Circuit(ops)
+        c.run(r, 0)
+        c.close()
+        return r
+
+    a, b = fresh(), fresh()
+    for k, qb in enumerate((3, 7, 0)):
+        assert a.measure_seeded(qb) == b.measure(qb, draws[k])
+    with pytest.raises(q.QStateError):
+        a.measure_seeded(n)  # no such qubit: rejected, no draw taken
+    assert max_abs(a.get_amps(), b.get_amps()) == 0.0
+    c, d = fresh(), fresh()
+    assert c.measure_all_seeded() == d.measure_all(draws[3:3 + n])
+    assert max_abs(c.get_amps(), d.get_amps()) == 0.0
+    e.seed(21, 4)
+    f, g = fresh(), fresh()
+    assert f.measure_seeded(5) == g.measure(5, draws[0])
+    for r in (a, b, c, d, f, g):
+        r.close()
+    e.close()
