@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 # fused-pass tile shapes: tile qubits, thread bits, contiguous qubits (complex128
 # default, and the complex64 run of the 33-qubit leg)
 DEFAULT_TILE = (12, 8, 4)
-C64_TILE = (13, 9, 4)
+C64_TILE = (14, 10, 5)
 
 
 def log(msg):

@@ -20,7 +20,7 @@ from . import qstate as Q
 # (tile qubits, thread bits, contiguous qubits), most promising first
 CANDIDATES = {
     Q.C128: [(12, 8, 4), (13, 9, 4), (12, 9, 4), (13, 10, 4), (12, 9, 6), (11, 8, 4)],
-    Q.C64: [(13, 9, 4), (14, 10, 4), (12, 8, 4), (13, 10, 4), (14, 10, 6)],
+    Q.C64: [(14, 10, 5), (13, 9, 4), (14, 10, 4), (12, 8, 4), (13, 10, 4), (14, 10, 6)],
 }
 
 

@@ -263,7 +263,7 @@ def flip_circuit(n: int, seed: int):
 
 
 @pytest.mark.parametrize('prec_name,tile,tb,contig', [('C128', 12, 8, 4), ('C128', 13, 9, 4), ('C128', 11, 8, 6),
-                                                      ('C64', 13, 9, 4)])
+                                                      ('C64', 13, 9, 4), ('C64', 14, 10, 5)])
 def test_compiled_deferred_flips(q, env, prec_name, tile, tb, contig):
     """Thread- and tile-controlled NOTs kept as per-lane flips: folded into
     later gate matrices, applied before their target is used as a control,
