@@ -309,7 +309,7 @@ def dm_leg(q, torch, log, N=14, depth=10, seed=2):
     return out
 
 
-EXTRAS = ('unfused', 'pertarget', 'cpu', 'c64', 'batched', 'serving', 'dm')
+EXTRAS = ('unfused', 'pertarget', 'measure', 'cpu', 'c64', 'batched', 'serving', 'dm')
 
 
 def serving_leg(q, torch, log, count=40):
@@ -498,6 +498,35 @@ def main():
                 times.append(s.elapsed_time(e))
             per_t.append(round(2 * elem * (1 << n) / (sorted(times)[2] * 1e-3) / 1e9, 1))
         out['per_target_gbps'] = per_t
+    if 'measure' in legs:
+        # measurement of every qubit on the circuit's output: qs_measure_all
+        # (histogram walk, one write-only collapse) against n successive
+        # qs_measure calls with the same draws, from the same snapshot
+        log('measure all qubits')
+        reg.init_zero()
+        circ.run_compiled(reg, K, TB, 0, L)
+        snap = reg.tensor.clone()
+        mdraws = measurement_draws(2, 0, n)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        outs_all, probs_all = reg.measure_all(mdraws)
+        torch.cuda.synchronize()  # the collapse is queued after the outcomes return
+        t_all = time.perf_counter() - t1
+        reg.tensor.copy_(snap)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        seq = [reg.measure(k, float(mdraws[k])) for k in range(n)]
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t1
+        del snap
+        torch.cuda.empty_cache()
+        out['measure_all'] = {
+            'qubits': n, 'measure_all_ms': t_all * 1e3, 'sequential_ms': t_seq * 1e3,
+            'speedup': t_seq / t_all,
+            'outcomes_equal': [o for o, _ in seq] == outs_all,
+            'max_prob_rel_diff': max(abs(p - ps) / ps for (_, ps), p in zip(seq, probs_all)),
+        }
+        log(f"measure all {n} qubits: {t_all * 1e3:.1f} ms vs {t_seq * 1e3:.1f} ms sequential")
     if 'cpu' in legs:
         log('cpu baseline')
         out['cpu_baseline'] = cpu_baseline(ops, n)

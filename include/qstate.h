@@ -26,7 +26,9 @@
  *     register unchanged.  qs_last_error() gives the calling thread's last
  *     message.  Nothing in the library exits or aborts the process.
  *   - Gates, channels and initialisation are asynchronous on the register's
- *     HIP stream.  qs_calc_*, qs_measure* and qs_get_amps synchronise it.
+ *     HIP stream.  qs_calc_*, qs_measure* and qs_get_amps synchronise it
+ *     (qs_measure* return once the outcome is known; the collapse that
+ *     follows is queued on the stream like a gate).
  *   - The library is thread-safe across different registers; calls on one
  *     register must not overlap.
  */
@@ -159,7 +161,9 @@ qs_status qs_calc_prob_of_outcome(qs_reg r, int qubit, int outcome, double* out)
  * p0 = P(qubit = 0) clamped to [0, 1]; outcome = (u01 < p0) ? 0 : 1; the
  * other branch is zeroed and the kept one scaled by 1/sqrt(p) (state
  * vector) or 1/p (density matrix), with the scale formed in double
- * precision.  *prob receives P(outcome).  Synchronous. */
+ * precision.  *prob receives P(outcome).  Returns once the outcome is known
+ * (the probabilities are read back); the collapse is queued on the
+ * register's stream, so every later call sees the collapsed state. */
 qs_status qs_measure(qs_reg r, int qubit, double u01, int* outcome, double* prob);
 /* Measure every qubit, 0..n-1 in order, with draws u01[0..n-1] in [0, 1):
  * the result is that of n successive qs_measure calls (each qubit's
@@ -170,7 +174,9 @@ qs_status qs_measure(qs_reg r, int qubit, double u01, int* outcome, double* prob
  * measured basis entry.  outcomes[k] and probs[k] (either may be NULL)
  * receive qubit k's outcome and P(outcome).  u01 is read during the call
  * only.  QS_E_ARG for a NULL u01, a draw outside [0, 1) or an outcome of
- * zero probability; the register is unchanged then.  Synchronous. */
+ * zero probability; the register is unchanged then.  Returns once the
+ * outcomes are known; the final collapse is queued on the register's
+ * stream, as in qs_measure. */
 qs_status qs_measure_all(qs_reg r, const double* u01, int* outcomes, double* probs);
 
 /* ---- seeded draws (the paper leaves the source of measurement randomness
