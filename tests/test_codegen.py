@@ -115,3 +115,24 @@ def test_library_kernels_use_no_scratch():
         for name, body in kernels:
             size = int(re.search(r'\.amdhsa_private_segment_fixed_size (\d+)', body).group(1))
             assert size == 0, f'{src}: {name} uses {size} bytes of scratch'
+
+
+def test_planner_pass_counts():
+    """The compiled path's partition (candidate tile sets with a one-pass
+    lookahead) fits the 32-qubit depth-10 layered circuit (485 gates) into
+    at most 12 HBM round trips with 12- or 13-qubit tiles, the same circuit
+    at 33 qubits in complex64 into at most 11 with 14-qubit tiles, and the
+    14-qubit noisy density matrix (1015 ops on its 28-qubit vector) into at
+    most 10.  Guards against planner changes that add passes."""
+    import paper_1802_08032_amd as q
+    from workloads import noisy_circuit
+    c = q.Circuit(layered_circuit(32, 10, seed=1, mcphase=True))
+    for tile, tb in ((12, 8), (13, 9)):
+        assert c.source(32, q.C128, tile, tb, 0, 0, 4)[1] <= 12, tile
+    c.close()
+    c = q.Circuit(layered_circuit(33, 10, seed=1, mcphase=True))
+    assert c.source(33, q.C64, 14, 10, 0, 0, 5)[1] <= 11
+    c.close()
+    c = q.Circuit(noisy_circuit(14, 10, 2))
+    assert c.source(14, q.C128, 12, 8, 0, 0, 4, kind=q.DENSITY)[1] <= 10
+    c.close()
