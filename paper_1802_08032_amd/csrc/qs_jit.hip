@@ -84,12 +84,21 @@ __device__ __forceinline__ void qs_ap4(const R (&m)[32], V& a, V& b, V& c, V& d)
     V y[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        R re = 0, im = 0;
+        // one product or multiply-add per statement, so that every term is
+        // a fused multiply-add (1 multiply + 7 FMAs per component; an
+        // accumulation of two-product terms costs 4 multiplies, 4 FMAs and
+        // 4 adds)
+        R re = m[8 * i] * x[0].x;
+        R im = m[8 * i] * x[0].y;
+        re = -m[8 * i + 1] * x[0].y + re;
+        im = m[8 * i + 1] * x[0].x + im;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 1; j < 4; ++j) {
             const R mr = m[2 * (4 * i + j)], mi = m[2 * (4 * i + j) + 1];
-            re += mr * x[j].x - mi * x[j].y;
-            im += mr * x[j].y + mi * x[j].x;
+            re = mr * x[j].x + re;
+            re = -mi * x[j].y + re;
+            im = mr * x[j].y + im;
+            im = mi * x[j].x + im;
         }
         y[i].x = re;
         y[i].y = im;
