@@ -138,6 +138,22 @@ qs_status qs_multi_controlled_not(qs_reg r, const int* controls, int n_controls,
  * multiplied by exp(i angle) (CZ is angle = pi on two qubits). */
 qs_status qs_multi_controlled_phase(qs_reg r, const int* qubits, int n_qubits, double angle);
 
+/* Named gates: thin wrappers over the calls above, with the same argument
+ * checks and errors.
+ *   qs_hadamard   H = [[1, 1], [1, -1]] / sqrt 2 on `target`
+ *   qs_cnot       NOT on `target` where `control` is 1
+ *   qs_cz         phase -1 where qubits q1 and q2 are both 1 (symmetric)
+ *   qs_rotate_x   exp(-i theta X / 2) = [[c, -i s], [-i s, c]]
+ *   qs_rotate_y   exp(-i theta Y / 2) = [[c, -s], [s, c]]
+ *   qs_rotate_z   exp(-i theta Z / 2) = diag(e^(-i theta/2), e^(i theta/2))
+ * with c = cos(theta / 2), s = sin(theta / 2). */
+qs_status qs_hadamard(qs_reg r, int target);
+qs_status qs_cnot(qs_reg r, int control, int target);
+qs_status qs_cz(qs_reg r, int q1, int q2);
+qs_status qs_rotate_x(qs_reg r, int target, double theta);
+qs_status qs_rotate_y(qs_reg r, int target, double theta);
+qs_status qs_rotate_z(qs_reg r, int target, double theta);
+
 /* ---- decoherence channels (density matrices only) ---------------------- */
 
 /* rho -> (1-p) rho + p Z rho Z,                       0 <= p <= 1/2 */

@@ -660,6 +660,47 @@ qs_status qs_multi_controlled_phase(qs_reg r, const int* qubits, int n_qubits, d
                               : do_phase<float>(r, qubits, n_qubits, angle);
 }
 
+// ---- named gates ----------------------------------------------------------
+
+qs_status qs_hadamard(qs_reg r, int target)
+{
+    const double s = 1.0 / sqrt(2.0);
+    const qs_cplx u[4] = {{s, 0.0}, {s, 0.0}, {s, 0.0}, {-s, 0.0}};
+    return qs_unitary(r, target, u);
+}
+
+qs_status qs_cnot(qs_reg r, int control, int target)
+{
+    return qs_multi_controlled_not(r, &control, 1, target);
+}
+
+qs_status qs_cz(qs_reg r, int q1, int q2)
+{
+    const int qubits[2] = {q1, q2};
+    return qs_multi_controlled_phase(r, qubits, 2, M_PI);
+}
+
+qs_status qs_rotate_x(qs_reg r, int target, double theta)
+{
+    const double c = cos(0.5 * theta), s = sin(0.5 * theta);
+    const qs_cplx u[4] = {{c, 0.0}, {0.0, -s}, {0.0, -s}, {c, 0.0}};
+    return qs_unitary(r, target, u);
+}
+
+qs_status qs_rotate_y(qs_reg r, int target, double theta)
+{
+    const double c = cos(0.5 * theta), s = sin(0.5 * theta);
+    const qs_cplx u[4] = {{c, 0.0}, {-s, 0.0}, {s, 0.0}, {c, 0.0}};
+    return qs_unitary(r, target, u);
+}
+
+qs_status qs_rotate_z(qs_reg r, int target, double theta)
+{
+    const double c = cos(0.5 * theta), s = sin(0.5 * theta);
+    const qs_cplx u[4] = {{c, -s}, {0.0, 0.0}, {0.0, 0.0}, {c, s}};
+    return qs_unitary(r, target, u);
+}
+
 static qs_status mix(qs_reg r, int channel, int target, double p)
 {
     QS_CHECK_REG(r);

@@ -72,6 +72,12 @@ SIGNATURES = {
     'qs_calc_prob_of_outcome': (_i, [_vp, _i, _i, _PD]),
     'qs_measure': (_i, [_vp, _i, _d, _PI, _PD]),
     'qs_measure_all': (_i, [_vp, _PD, _PI, _PD]),
+    'qs_hadamard': (_i, [_vp, _i]),
+    'qs_cnot': (_i, [_vp, _i, _i]),
+    'qs_cz': (_i, [_vp, _i, _i]),
+    'qs_rotate_x': (_i, [_vp, _i, _d]),
+    'qs_rotate_y': (_i, [_vp, _i, _d]),
+    'qs_rotate_z': (_i, [_vp, _i, _d]),
     'qs_philox_draws': (_i, [_u64, _u64, _u64, _i, _PD]),
     'qs_env_seed': (_i, [_vp, _u64, _u64]),
     'qs_measure_seeded': (_i, [_vp, _i, _PI, _PD]),
@@ -254,6 +260,24 @@ class Register:
     def multi_controlled_phase(self, qubits, angle: float):
         arr, k = _ints(qubits)
         _check(lib().qs_multi_controlled_phase(self.h, arr, k, float(angle)))
+
+    def hadamard(self, target: int):
+        _check(lib().qs_hadamard(self.h, target))
+
+    def cnot(self, control: int, target: int):
+        _check(lib().qs_cnot(self.h, control, target))
+
+    def cz(self, q1: int, q2: int):
+        _check(lib().qs_cz(self.h, q1, q2))
+
+    def rotate_x(self, target: int, theta: float):
+        _check(lib().qs_rotate_x(self.h, target, float(theta)))
+
+    def rotate_y(self, target: int, theta: float):
+        _check(lib().qs_rotate_y(self.h, target, float(theta)))
+
+    def rotate_z(self, target: int, theta: float):
+        _check(lib().qs_rotate_z(self.h, target, float(theta)))
 
     def mix_dephasing(self, target: int, p: float):
         _check(lib().qs_mix_dephasing(self.h, target, float(p)))

@@ -450,3 +450,47 @@ def test_seeded_measurement_takes_the_environment_stream(q):
     for r in (a, b, c, d, f, g):
         r.close()
     e.close()
+
+
+def test_named_gates_match_the_oracle(q, env):
+    """qs_hadamard, qs_cnot, qs_cz and qs_rotate_x/y/z apply the matrices they
+    name: on a state vector from a random state, and on a density matrix
+    (Eq. 2) from a basis state; argument errors pass through."""
+    from workloads import ry, rz
+    th = 0.7
+    c, s = math.cos(th / 2), math.sin(th / 2)
+    rx = np.array([[c, -1j * s], [-1j * s, c]])
+
+    def seq(n):
+        return [('hadamard', (3,), Op('u', target=3, u=H)),
+                ('cnot', (2, n - 2), Op('x', target=n - 2, controls=(2,))),
+                ('cz', (n - 1, 1), Op('phase', qubits=(n - 1, 1), angle=math.pi)),
+                ('rotate_x', (0, th), Op('u', target=0, u=rx)),
+                ('rotate_y', (n - 3, th), Op('u', target=n - 3, u=ry(th))),
+                ('rotate_z', (1, th), Op('u', target=1, u=rz(th))),
+                ('hadamard', (n - 1,), Op('u', target=n - 1, u=H))]
+
+    n = 9
+    state = random_state(n, 77)
+    reg = q.Register(env, n)
+    reg.set_amps(state)
+    ref = state.copy()
+    for name, args, op in seq(n):
+        getattr(reg, name)(*args)
+        O.apply_sv(ref, n, op)
+    assert max_abs(reg.get_amps(), ref) <= TOL128
+    for bad in (lambda: reg.cnot(3, 3), lambda: reg.hadamard(n), lambda: reg.cz(2, 2)):
+        with pytest.raises(q.QStateError):
+            bad()
+    assert max_abs(reg.get_amps(), ref) <= TOL128  # rejected calls change nothing
+    reg.close()
+
+    N = 5
+    rho = q.Register(env, N, q.DENSITY, q.C128)
+    rho.init_basis(6)
+    ref = O.dm_zero(N, 6)
+    for name, args, op in seq(N):
+        getattr(rho, name)(*args)
+        O.apply_dm(ref, N, op)
+    assert max_abs(rho.get_amps(), ref) <= TOL128
+    rho.close()
