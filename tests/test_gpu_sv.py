@@ -494,3 +494,24 @@ def test_named_gates_match_the_oracle(q, env):
         O.apply_dm(ref, N, op)
     assert max_abs(rho.get_amps(), ref) <= TOL128
     rho.close()
+
+
+def test_compiled_ragged_and_empty_circuits(q, env):
+    """Compiled passes on degenerate circuits: an empty circuit launches no
+    pass and leaves the state untouched; a lone phase gate and a lone gate on
+    the top qubit match the oracle."""
+    n = 14
+    state = random_state(n, 9)
+    reg = q.Register(env, n)
+    reg.set_amps(state)
+    c = q.Circuit([])
+    assert c.run_compiled(reg, 12, 8, 0, 4) == 0
+    assert max_abs(reg.get_amps(), state) == 0.0
+    c.close()
+    for ops in ([Op('phase', qubits=(3, 13), angle=0.3)], [Op('u', target=n - 1, u=H)]):
+        reg.set_amps(state)
+        c = q.Circuit(ops)
+        assert c.run_compiled(reg, 12, 8, 0, 4) == 1
+        assert max_abs(reg.get_amps(), oracle_run(n, ops, state)) <= TOL128
+        c.close()
+    reg.close()
