@@ -146,6 +146,13 @@ __global__ __launch_bounds__(kBlock) void k_gate_low(typename C2<T>::type* __res
     const int lane = threadIdx.x & 63;
     const bool up = (lane >> TT) & 1;
     const bool ok = ((uint32_t)lane & lowmask) == lowmask;
+    // A lane whose controls at or above the 128-byte line are not all set
+    // holds a whole line the gate leaves unchanged: it loads and stores
+    // nothing.  Its pair partner (lane ^ 2^TT; the target is never a
+    // control) has the same control bits, so no active lane reads it.
+    constexpr uint32_t kLine = sizeof(T) == 8 ? 3 : 4;
+    const uint32_t linemask = lowmask & ~((1u << kLine) - 1);
+    const bool act = ((uint32_t)lane & linemask) == linemask;
     // new = s * self + p * partner
     const T sr = up ? u.m[6] : u.m[0], si = up ? u.m[7] : u.m[1];
     const T pr = up ? u.m[4] : u.m[2], pi = up ? u.m[5] : u.m[3];
@@ -165,7 +172,9 @@ __global__ __launch_bounds__(kBlock) void k_gate_low(typename C2<T>::type* __res
         for (int j = 0; j < U; ++j) {
             const uint64_t c = chunk(c0, j);
             e[j] = (expand(c < nchunks ? c : nchunks - 1, hi) << 6) | (uint64_t)lane;
-            v[j] = ldnt(amp + e[j]);
+            v[j].x = T(0);
+            v[j].y = T(0);
+            if (act) v[j] = ldnt(amp + e[j]);
         }
 #pragma unroll
         for (int j = 0; j < U; ++j) {
@@ -174,12 +183,13 @@ __global__ __launch_bounds__(kBlock) void k_gate_low(typename C2<T>::type* __res
             p.x = xchg<TT>(v[j].x, lane);
             p.y = xchg<TT>(v[j].y, lane);
             const V r = cmac2<T, V>(sr, si, v[j], pr, pi, p);
-            // lanes whose low controls are not all set store their value
-            // unchanged, so that every store is a full wave-wide line
+            // active lanes whose controls below the line are not all set
+            // store their value unchanged, so that every store covers whole
+            // lines
             V o;
             o.x = ok ? r.x : v[j].x;
             o.y = ok ? r.y : v[j].y;
-            if (chunk(c0, j) < nchunks) stnt(amp + e[j], o);
+            if (act && chunk(c0, j) < nchunks) stnt(amp + e[j], o);
         }
     }
 }
