@@ -146,13 +146,20 @@ qs_status qs_multi_controlled_phase(qs_reg r, const int* qubits, int n_qubits, d
  *   qs_rotate_x   exp(-i theta X / 2) = [[c, -i s], [-i s, c]]
  *   qs_rotate_y   exp(-i theta Y / 2) = [[c, -s], [s, c]]
  *   qs_rotate_z   exp(-i theta Z / 2) = diag(e^(-i theta/2), e^(i theta/2))
- * with c = cos(theta / 2), s = sin(theta / 2). */
+ *   qs_t_gate     diag(1, e^(i pi/4))
+ *   qs_sqrt_x     [[1+i, 1-i], [1-i, 1+i]] / 2   (its square is X)
+ *   qs_sqrt_y     [[1+i, -1-i], [1+i, 1+i]] / 2  (its square is Y)
+ * with c = cos(theta / 2), s = sin(theta / 2).  H, T, CZ, sqrt X and sqrt Y
+ * are the gate set of the paper's random circuits (Sec. III.A). */
 qs_status qs_hadamard(qs_reg r, int target);
 qs_status qs_cnot(qs_reg r, int control, int target);
 qs_status qs_cz(qs_reg r, int q1, int q2);
 qs_status qs_rotate_x(qs_reg r, int target, double theta);
 qs_status qs_rotate_y(qs_reg r, int target, double theta);
 qs_status qs_rotate_z(qs_reg r, int target, double theta);
+qs_status qs_t_gate(qs_reg r, int target);
+qs_status qs_sqrt_x(qs_reg r, int target);
+qs_status qs_sqrt_y(qs_reg r, int target);
 
 /* ---- decoherence channels (density matrices only) ---------------------- */
 

@@ -701,6 +701,23 @@ qs_status qs_rotate_z(qs_reg r, int target, double theta)
     return qs_unitary(r, target, u);
 }
 
+qs_status qs_t_gate(qs_reg r, int target)
+{
+    return qs_multi_controlled_phase(r, &target, 1, 0.25 * M_PI);
+}
+
+qs_status qs_sqrt_x(qs_reg r, int target)
+{
+    const qs_cplx u[4] = {{0.5, 0.5}, {0.5, -0.5}, {0.5, -0.5}, {0.5, 0.5}};
+    return qs_unitary(r, target, u);
+}
+
+qs_status qs_sqrt_y(qs_reg r, int target)
+{
+    const qs_cplx u[4] = {{0.5, 0.5}, {-0.5, -0.5}, {0.5, 0.5}, {0.5, 0.5}};
+    return qs_unitary(r, target, u);
+}
+
 static qs_status mix(qs_reg r, int channel, int target, double p)
 {
     QS_CHECK_REG(r);

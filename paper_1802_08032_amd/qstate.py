@@ -78,6 +78,9 @@ SIGNATURES = {
     'qs_rotate_x': (_i, [_vp, _i, _d]),
     'qs_rotate_y': (_i, [_vp, _i, _d]),
     'qs_rotate_z': (_i, [_vp, _i, _d]),
+    'qs_t_gate': (_i, [_vp, _i]),
+    'qs_sqrt_x': (_i, [_vp, _i]),
+    'qs_sqrt_y': (_i, [_vp, _i]),
     'qs_philox_draws': (_i, [_u64, _u64, _u64, _i, _PD]),
     'qs_env_seed': (_i, [_vp, _u64, _u64]),
     'qs_measure_seeded': (_i, [_vp, _i, _PI, _PD]),
@@ -278,6 +281,15 @@ class Register:
 
     def rotate_z(self, target: int, theta: float):
         _check(lib().qs_rotate_z(self.h, target, float(theta)))
+
+    def t_gate(self, target: int):
+        _check(lib().qs_t_gate(self.h, target))
+
+    def sqrt_x(self, target: int):
+        _check(lib().qs_sqrt_x(self.h, target))
+
+    def sqrt_y(self, target: int):
+        _check(lib().qs_sqrt_y(self.h, target))
 
     def mix_dephasing(self, target: int, p: float):
         _check(lib().qs_mix_dephasing(self.h, target, float(p)))

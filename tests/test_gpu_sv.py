@@ -453,13 +453,16 @@ def test_seeded_measurement_takes_the_environment_stream(q):
 
 
 def test_named_gates_match_the_oracle(q, env):
-    """qs_hadamard, qs_cnot, qs_cz and qs_rotate_x/y/z apply the matrices they
-    name: on a state vector from a random state, and on a density matrix
+    """qs_hadamard, qs_cnot, qs_cz, qs_rotate_x/y/z, qs_t_gate and
+    qs_sqrt_x/y apply the matrices they name: on a state vector from a random state, and on a density matrix
     (Eq. 2) from a basis state; argument errors pass through."""
     from workloads import ry, rz
     th = 0.7
     c, s = math.cos(th / 2), math.sin(th / 2)
     rx = np.array([[c, -1j * s], [-1j * s, c]])
+    SX = np.array([[1 + 1j, 1 - 1j], [1 - 1j, 1 + 1j]]) / 2
+    SY = np.array([[1 + 1j, -1 - 1j], [1 + 1j, 1 + 1j]]) / 2
+    assert np.allclose(SX @ SX, [[0, 1], [1, 0]]) and np.allclose(SY @ SY, [[0, -1j], [1j, 0]])
 
     def seq(n):
         return [('hadamard', (3,), Op('u', target=3, u=H)),
@@ -468,6 +471,9 @@ def test_named_gates_match_the_oracle(q, env):
                 ('rotate_x', (0, th), Op('u', target=0, u=rx)),
                 ('rotate_y', (n - 3, th), Op('u', target=n - 3, u=ry(th))),
                 ('rotate_z', (1, th), Op('u', target=1, u=rz(th))),
+                ('t_gate', (4,), Op('phase', qubits=(4,), angle=math.pi / 4)),
+                ('sqrt_x', (2,), Op('u', target=2, u=SX)),
+                ('sqrt_y', (0,), Op('u', target=0, u=SY)),
                 ('hadamard', (n - 1,), Op('u', target=n - 1, u=H))]
 
     n = 9
