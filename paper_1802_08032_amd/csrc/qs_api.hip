@@ -375,14 +375,14 @@ qs_status qs_env_seed(qs_env env, uint64_t seed, uint64_t stream)
 qs_status qs_env_destroy(qs_env env)
 {
     if (!valid_env(env) || !handle_remove(env)) return qs::set_error(QS_E_HANDLE, "invalid environment handle");
-    hipSetDevice(env->device);
+    (void)hipSetDevice(env->device);
     for (auto& rec : env->recs) {
-        hipEventDestroy(rec.a);
-        hipEventDestroy(rec.b);
+        (void)hipEventDestroy(rec.a);
+        (void)hipEventDestroy(rec.b);
     }
     for (auto& sp : env->scratch_pool) {
-        hipFree(sp.first);
-        hipHostFree(sp.second);
+        (void)hipFree(sp.first);
+        (void)hipHostFree(sp.second);
     }
     env->magic = 0;
     delete env;
@@ -414,8 +414,8 @@ static qs_status fold_profile(qs_env env)
         QS_HIP(hipEventElapsedTime(&ms, rec.a, rec.b));
         env->launches[rec.klass] += 1;
         env->ms[rec.klass] += ms;
-        hipEventDestroy(rec.a);
-        hipEventDestroy(rec.b);
+        (void)hipEventDestroy(rec.a);
+        (void)hipEventDestroy(rec.b);
     }
     env->recs.clear();
     return QS_OK;
@@ -474,7 +474,7 @@ static qs_status reg_common(qs_env env, int n, int kind, int prec, void* stream,
     if (!amp) {
         const hipError_t e = dev_alloc(&amp, need);
         if (e != hipSuccess) {
-            hipGetLastError();
+            (void)hipGetLastError();
             return qs::set_error(QS_E_OOM, "cannot allocate " + std::to_string(need) + " bytes");
         }
     }
@@ -493,9 +493,9 @@ static qs_status reg_common(qs_env env, int n, int kind, int prec, void* stream,
         hipError_t e = dev_alloc(&scratch, sbytes);
         if (e == hipSuccess) e = hipHostMalloc(&hres, 2 * sizeof(double), hipHostMallocDefault);
         if (e != hipSuccess) {
-            hipGetLastError();
-            if (scratch) hipFree(scratch);
-            if (!dev_ptr) hipFree(amp);
+            (void)hipGetLastError();
+            if (scratch) (void)hipFree(scratch);
+            if (!dev_ptr) (void)hipFree(amp);
             return qs::set_error(QS_E_OOM, "cannot allocate register scratch");
         }
     }
@@ -532,9 +532,9 @@ qs_status qs_reg_wrap(qs_env env, int n, int kind, int prec, void* dev_ptr, size
 qs_status qs_reg_destroy(qs_reg r)
 {
     if (!valid_reg(r) || !handle_remove(r)) return qs::set_error(QS_E_HANDLE, "invalid register handle");
-    hipSetDevice(r->env->device);
-    hipStreamSynchronize(r->stream);
-    if (r->owned) hipFree(r->amp);
+    (void)hipSetDevice(r->env->device);
+    (void)hipStreamSynchronize(r->stream);
+    if (r->owned) (void)hipFree(r->amp);
     {
         std::lock_guard<std::mutex> g(r->env->mu);
         r->env->scratch_pool.push_back({r->scratch, r->host_res});
@@ -1190,14 +1190,14 @@ qs_status qs_circuit_source(qs_circuit c, int n, int kind, int prec, int tile_qu
 
 static void batch_free(qs_batch b)
 {
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
-    if (b->dbuf) hipFree(b->dbuf);
-    if (b->dprobs) hipFree(b->dprobs);
-    if (b->hprobs) hipHostFree(b->hprobs);
-    if (b->ev_in) hipEventDestroy(b->ev_in);
-    if (b->ev_out) hipEventDestroy(b->ev_out);
-    if (b->stream) hipStreamDestroy(b->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->dbuf) (void)hipFree(b->dbuf);
+    if (b->dprobs) (void)hipFree(b->dprobs);
+    if (b->hprobs) (void)hipHostFree(b->hprobs);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
     b->magic = 0;
     delete b;
 }
@@ -1239,7 +1239,7 @@ qs_status qs_batch_create(const qs_reg* regs, const qs_circuit* circuits, int co
     if (e == hipSuccess) e = dev_alloc((void**)&b->dprobs, 2 * sizeof(double) * count);
     if (e == hipSuccess) e = hipHostMalloc((void**)&b->hprobs, 2 * sizeof(double) * count, hipHostMallocDefault);
     if (e != hipSuccess) {
-        hipGetLastError();
+        (void)hipGetLastError();
         batch_free(b);
         return qs::hip_error(e, "batch resources");
     }
@@ -1256,8 +1256,8 @@ qs_status qs_batch_create(const qs_reg* regs, const qs_circuit* circuits, int co
 qs_status qs_batch_destroy(qs_batch b)
 {
     if (!valid_batch(b) || !handle_remove(b)) return qs::set_error(QS_E_HANDLE, "invalid batch handle");
-    hipSetDevice(b->env->device);
-    hipStreamSynchronize(b->stream);
+    (void)hipSetDevice(b->env->device);
+    (void)hipStreamSynchronize(b->stream);
     batch_free(b);
     return QS_OK;
 }
@@ -1315,11 +1315,11 @@ qs_status qs_batch_capture(qs_batch b, int init_zero)
     QS_HIP(hipSetDevice(b->env->device));
     QS_HIP(hipStreamSynchronize(b->stream));
     if (b->exec) {
-        hipGraphExecDestroy(b->exec);
+        (void)hipGraphExecDestroy(b->exec);
         b->exec = nullptr;
     }
     if (b->graph) {
-        hipGraphDestroy(b->graph);
+        (void)hipGraphDestroy(b->graph);
         b->graph = nullptr;
     }
     QS_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
@@ -1327,7 +1327,7 @@ qs_status qs_batch_capture(qs_batch b, int init_zero)
     hipGraph_t g = nullptr;
     const hipError_t ce = hipStreamEndCapture(b->stream, &g);
     if (le != hipSuccess) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return qs::hip_error(le, "batch launch under capture");
     }
     if (ce != hipSuccess) return qs::hip_error(ce, "hipStreamEndCapture");

@@ -581,7 +581,7 @@ qs_status run_fused_sv(qs_reg r, const std::vector<OpRec>& ops, FusedConfig cfg,
     // from pageable memory the copy has left `host` when the call returns
     e = hipMemcpyAsync(dbuf, host.data(), pbytes + obytes, hipMemcpyHostToDevice, r->stream);
     if (e != hipSuccess) {
-        hipFreeAsync(dbuf, r->stream);
+        (void)hipFreeAsync(dbuf, r->stream);
         return hip_error(e, "plan upload");
     }
     const FPass* dP = (const FPass*)dbuf;

@@ -608,8 +608,8 @@ void jit_plan_free(JitPlan* p)
 {
     if (!p) return;
     if (p->dmats) {
-        hipSetDevice(p->device);
-        hipFree(p->dmats);
+        (void)hipSetDevice(p->device);
+        (void)hipFree(p->dmats);
     }
     delete p;
 }
@@ -628,7 +628,7 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
                        J->nops != c->ops.size();
     if (fresh) {
         if (J) {
-            hipStreamSynchronize(r->stream);  // kernels of the old plan may still read its matrices
+            (void)hipStreamSynchronize(r->stream);  // kernels of the old plan may still read its matrices
             jit_plan_free(J);
             c->jit = nullptr;
         }
@@ -667,7 +667,7 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
             e = hipMemcpy(nj->dmats, mf.data(), bytes, hipMemcpyHostToDevice);
         }
         if (e != hipSuccess) {
-            hipFree(nj->dmats);
+            (void)hipFree(nj->dmats);
             nj->dmats = nullptr;
             return hip_error(e, "matrix upload");
         }
