@@ -232,6 +232,14 @@ qs_status qs_circuit_destroy(qs_circuit c);
 qs_status qs_circuit_add_unitary(qs_circuit c, const int* controls, int n_controls, int target,
                                  const qs_cplx u[4]);
 qs_status qs_circuit_add_not(qs_circuit c, const int* controls, int n_controls, int target);
+/* Change the parameters of recorded op `index` (0-based, in add order),
+ * keeping its kind, target and controls: the matrix of a unitary, or the
+ * angle of a phase.  QS_E_ARG if `index` holds another kind of op (or is out
+ * of range); QS_E_NOT_UNITARY as for qs_circuit_add_unitary.  Later runs
+ * use the new values (compiled passes are rebuilt from them; unchanged
+ * kernel sources are reused); a batch sees them after qs_batch_update. */
+qs_status qs_circuit_set_unitary(qs_circuit c, int index, const qs_cplx u[4]);
+qs_status qs_circuit_set_phase(qs_circuit c, int index, double angle);
 qs_status qs_circuit_add_phase(qs_circuit c, const int* qubits, int n_qubits, double angle);
 qs_status qs_circuit_add_channel(qs_circuit c, int channel, int target, double p);
 /* Number of recorded operations. */
@@ -290,8 +298,9 @@ qs_status qs_circuit_source(qs_circuit c, int n, int kind, int prec, int tile_qu
  * applies pass p of every register that has one, its tiles spread over all
  * workgroups (largest registers first); launch boundaries order a
  * register's passes.  The batch keeps device copies of the
- * plans; registers and circuits must outlive it, and later changes to the
- * circuits are not seen.  Work runs on the batch's own stream, ordered after
+ * plans; registers and circuits must outlive it.  Parameter changes
+ * (qs_circuit_set_*) are seen after qs_batch_update; adding ops to a
+ * batched circuit is not supported.  Work runs on the batch's own stream, ordered after
  * and before the registers' streams. */
 qs_status qs_batch_create(const qs_reg* regs, const qs_circuit* circuits, int count, int tile_qubits,
                           qs_batch* out);
@@ -303,6 +312,12 @@ qs_status qs_batch_run(qs_batch b, int init_zero);
  * one); qs_batch_replay launches it.  Asynchronous. */
 qs_status qs_batch_capture(qs_batch b, int init_zero);
 qs_status qs_batch_replay(qs_batch b);
+/* Take the circuits' current parameters (qs_circuit_set_*) into the batch:
+ * its device op table is rewritten on the batch stream, after earlier runs
+ * and before later ones, so a captured graph replays with the new values
+ * without being captured again.  Asynchronous (the host copy is taken
+ * before the call returns). */
+qs_status qs_batch_update(qs_batch b);
 /* Per register i: p0[i] = P(qubit = 0), total[i] = total probability, in
  * double precision with compensated sums (either output may be NULL).
  * `qubit` must be below every register's size.  Synchronous. */

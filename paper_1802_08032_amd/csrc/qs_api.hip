@@ -1024,6 +1024,32 @@ qs_status qs_circuit_add_unitary(qs_circuit c, const int* controls, int n_contro
     return QS_OK;
 }
 
+qs_status qs_circuit_set_unitary(qs_circuit c, int index, const qs_cplx u[4])
+{
+    if (!valid_circ(c)) return qs::set_error(QS_E_HANDLE, "invalid circuit handle");
+    if (index < 0 || index >= (int)c->ops.size() || c->ops[index].kind != 0)
+        return qs::set_error(QS_E_ARG, "no unitary at that index");
+    qs_status s = check_unitary(u);
+    if (s) return s;
+    for (int k = 0; k < 4; ++k) {
+        c->ops[index].u[2 * k] = u[k].re;
+        c->ops[index].u[2 * k + 1] = u[k].im;
+    }
+    ++c->version;
+    return QS_OK;
+}
+
+qs_status qs_circuit_set_phase(qs_circuit c, int index, double angle)
+{
+    if (!valid_circ(c)) return qs::set_error(QS_E_HANDLE, "invalid circuit handle");
+    if (index < 0 || index >= (int)c->ops.size() || c->ops[index].kind != 2)
+        return qs::set_error(QS_E_ARG, "no phase at that index");
+    if (!isfinite(angle)) return qs::set_error(QS_E_ARG, "non-finite angle");
+    c->ops[index].angle = angle;
+    ++c->version;
+    return QS_OK;
+}
+
 qs_status qs_circuit_add_not(qs_circuit c, const int* controls, int n_controls, int target)
 {
     OpRec op{};
@@ -1346,6 +1372,13 @@ qs_status qs_batch_replay(qs_batch b)
     s = batch_profiled(b, [](qs_batch bb, int) { return hipGraphLaunch(bb->exec, bb->stream); }, 0);
     if (s) return s;
     return batch_leave(b);
+}
+
+qs_status qs_batch_update(qs_batch b)
+{
+    if (!valid_batch(b)) return qs::set_error(QS_E_HANDLE, "invalid batch handle");
+    QS_HIP(hipSetDevice(b->env->device));
+    return qs::batch_update(b);
 }
 
 qs_status qs_batch_probs(qs_batch b, int qubit, double* p0, double* total)

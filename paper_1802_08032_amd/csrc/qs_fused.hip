@@ -452,7 +452,7 @@ FOp encode_op(const OpRec& op, const PassPlan& P, const Layout& L)
 // Device form of a planned pass list, appended to hp / hops (op indices in
 // the phases are positions in hops).
 void serialize(const std::vector<PassPlan>& plan, const std::vector<OpRec>& ops, int TB, int RB,
-               std::vector<FPass>& hp, std::vector<FOp>& hops)
+               std::vector<FPass>& hp, std::vector<FOp>& hops, std::vector<int>* src = nullptr)
 {
     const int K = TB + RB;
     for (size_t p = 0; p < plan.size(); ++p) {
@@ -475,7 +475,10 @@ void serialize(const std::vector<PassPlan>& plan, const std::vector<OpRec>& ops,
             const Layout& prev = ph ? P.phases[ph - 1].lay : P.phases[ph].lay;
             fill_phase(Fp, prev, P.phases[ph].lay, K);
             Fp.op_begin = (int)hops.size();
-            for (int idx : P.phases[ph].ops) hops.push_back(encode_op(ops[idx], P, P.phases[ph].lay));
+            for (int idx : P.phases[ph].ops) {
+                hops.push_back(encode_op(ops[idx], P, P.phases[ph].lay));
+                if (src) src->push_back(idx);
+            }
             Fp.op_end = (int)hops.size();
         }
         const Layout& last = P.phases.back().lay;
@@ -664,6 +667,7 @@ int batch_occupancy_p(int TB, int RB)
 qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
                       const std::vector<const std::vector<OpRec>*>& circs, int tile_qubits)
 {
+    b->op_src.clear();
     int nmin = 64;
     for (qs_reg r : regs) nmin = std::min(nmin, r->n);
     const FusedConfig cfg = default_fused_config(b->prec, tile_qubits, nmin);
@@ -698,10 +702,17 @@ qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
         hr[i].npasses = (int)plan.size();
         hr[i].pad = 0;
         maxpasses = std::max(maxpasses, (int)plan.size());
-        serialize(plan, *ops, cfg.TB, cfg.RB, hp, hops);
+        std::vector<int> src;
+        serialize(plan, *ops, cfg.TB, cfg.RB, hp, hops, &src);
+        for (int idx : src) b->op_src.push_back({(int)i, idx});
     }
     if (hp.empty()) hp.push_back(FPass{});
-    if (hops.empty()) hops.push_back(FOp{});
+    if (hops.empty()) {
+        hops.push_back(FOp{});
+        b->op_src.push_back({-1, -1});
+    }
+    b->circ_ops.assign(circs.begin(), circs.end());
+    b->host_ops.assign((const char*)hops.data(), (const char*)(hops.data() + hops.size()));
     // items level by level; within a level the largest registers first
     std::vector<uint32_t> byn(regs.size());
     for (size_t i = 0; i < byn.size(); ++i) byn[i] = (uint32_t)i;
@@ -739,6 +750,36 @@ qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
                                           : batch_occupancy_p<float>(cfg.TB, cfg.RB);
     b->grid = (int)(256L * per_cu);
     b->passes_total = (int)hp.size();
+    return QS_OK;
+}
+
+qs_status batch_update(qs_batch_s* b)
+{
+    FOp* ops = (FOp*)b->host_ops.data();
+    const size_t n = b->host_ops.size() / sizeof(FOp);
+    for (size_t k = 0; k < n; ++k) {
+        const int ci = b->op_src[k].first, oi = b->op_src[k].second;
+        if (ci < 0) continue;
+        const std::vector<OpRec>& cops = *b->circ_ops[ci];
+        if (oi >= (int)cops.size()) return set_error(QS_E_ARG, "a batched circuit lost operations");
+        const OpRec& op = cops[oi];
+        FOp& f = ops[k];
+        if (op.kind == 2) {
+            f.m[0] = cos(op.angle);
+            f.m[1] = sin(op.angle);
+        } else if (op.kind == 0) {
+            // the dense / diagonal choice follows the new matrix; register
+            // bit and condition variant (the low 5 bits) stay
+            const bool diag = op.u[2] == 0.0 && op.u[3] == 0.0 && op.u[4] == 0.0 && op.u[5] == 0.0;
+            f.kind = (diag ? kDiag : kDense) + (f.kind & 31);
+            for (int q = 0; q < 8; ++q) f.m[q] = op.u[q];
+        }
+    }
+    // from pageable memory the copy has left host_ops when the call returns;
+    // on the batch stream it follows earlier runs and precedes later ones
+    const hipError_t e = hipMemcpyAsync((char*)b->dbuf + b->off_ops, b->host_ops.data(), b->host_ops.size(),
+                                        hipMemcpyHostToDevice, b->stream);
+    if (e != hipSuccess) return hip_error(e, "batch parameter upload");
     return QS_OK;
 }
 

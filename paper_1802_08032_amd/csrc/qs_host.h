@@ -67,6 +67,7 @@ void jit_plan_free(JitPlan* p);
 struct qs_circuit_s {
     uint32_t magic;
     std::vector<OpRec> ops;
+    uint64_t version = 0;  // bumped by every parameter change (qs_circuit_set_*)
     qs::JitPlan* jit = nullptr;  // cached run-time compiled form (qs_jit.hip)
 };
 
@@ -91,6 +92,12 @@ struct qs_batch_s {
     double* hprobs = nullptr;      // pinned copy
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // parameter updates (qs_batch_update): the circuits, the source (circuit,
+    // op index) of every op slot of the device table (-1: padding), and a
+    // host copy of that table
+    std::vector<const std::vector<OpRec>*> circ_ops;
+    std::vector<std::pair<int, int>> op_src;
+    std::vector<char> host_ops;
 };
 
 namespace qs {
@@ -136,6 +143,9 @@ qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
                       const std::vector<const std::vector<OpRec>*>& circs, int K);
 hipError_t batch_launch(qs_batch_s* b, int init);
 hipError_t batch_probs_launch(qs_batch_s* b, int q, double* dev_out);
+// Rewrite the matrices and phase factors of the batch's op table from the
+// circuits' current parameters and upload it on the batch stream.
+qs_status batch_update(qs_batch_s* b);
 // Eq. 2 on the 2N-qubit vector of a density matrix: gates become a gate on
 // q and its conjugate on q+N, channels become 4x4 superoperators on
 // (q, q+N); an uncontrolled gate and the channels that follow it on the same

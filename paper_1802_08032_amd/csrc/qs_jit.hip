@@ -598,6 +598,7 @@ size_t esz_of(int prec) { return prec == QS_C128 ? sizeof(double) : sizeof(float
 struct JitPlan {
     int n = -1, prec = 0, TB = 0, RB = 0, max_phases = 0, contig = 0, device = -1;
     size_t nops = 0;
+    uint64_t version = 0;  // circuit parameter version the plan was built from
     std::vector<hipFunction_t> fns;
     std::vector<size_t> mat_off;  // element offset of each pass's matrices
     std::vector<int> blocks_per_cu;  // resident workgroups per CU for each pass kernel
@@ -625,7 +626,7 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
     JitPlan* J = c->jit;
     const bool fresh = !J || J->n != nbits || J->prec != r->prec || J->TB != cfg.TB || J->RB != cfg.RB ||
                        J->max_phases != cfg.max_phases || J->contig != cfg.contig || J->device != r->env->device ||
-                       J->nops != c->ops.size();
+                       J->nops != c->ops.size() || J->version != c->version;
     if (fresh) {
         if (J) {
             (void)hipStreamSynchronize(r->stream);  // kernels of the old plan may still read its matrices
@@ -679,6 +680,7 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
         nj->contig = cfg.contig;
         nj->device = r->env->device;
         nj->nops = c->ops.size();
+        nj->version = c->version;
         J = c->jit = nj.release();
     }
     unsigned long long ntiles = 1ull << (nbits - (cfg.TB + cfg.RB));

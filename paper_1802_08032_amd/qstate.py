@@ -72,6 +72,9 @@ SIGNATURES = {
     'qs_calc_prob_of_outcome': (_i, [_vp, _i, _i, _PD]),
     'qs_measure': (_i, [_vp, _i, _d, _PI, _PD]),
     'qs_measure_all': (_i, [_vp, _PD, _PI, _PD]),
+    'qs_circuit_set_unitary': (_i, [_vp, _i, _vp]),
+    'qs_circuit_set_phase': (_i, [_vp, _i, _d]),
+    'qs_batch_update': (_i, [_vp]),
     'qs_hadamard': (_i, [_vp, _i]),
     'qs_cnot': (_i, [_vp, _i, _i]),
     'qs_cz': (_i, [_vp, _i, _i]),
@@ -368,6 +371,14 @@ class Circuit:
         for op in ops or []:
             self.add(op)
 
+    def set_unitary(self, index: int, u):
+        """New matrix for recorded unitary op `index` (kind and qubits kept)."""
+        _check(lib().qs_circuit_set_unitary(self.h, index, _mat(u)))
+
+    def set_phase(self, index: int, angle: float):
+        """New angle for recorded phase op `index`."""
+        _check(lib().qs_circuit_set_phase(self.h, index, float(angle)))
+
     def add(self, op):
         L = lib()
         if op.kind == 'u':
@@ -446,6 +457,11 @@ class Batch:
 
     def replay(self):
         _check(lib().qs_batch_replay(self.h))
+
+    def update(self):
+        """Take the circuits' current parameters into the batch (and into a
+        captured graph's next replay)."""
+        _check(lib().qs_batch_update(self.h))
 
     def probs(self, qubit: int = 0):
         """(P(qubit = 0), total probability) per register, as numpy arrays."""

@@ -143,3 +143,77 @@ def test_c3_workload_512_registers(q, env, prec_name):
         c.close()
     for r in regs:
         r.close()
+
+
+def test_batch_parameter_update_replays_new_values(q, env):
+    """A captured batch replays with new gate parameters after
+    qs_batch_update, without being captured again: every register matches
+    the oracle run of its circuit with the new values, including matrices
+    that become diagonal and diagonal ones that become dense; setters reject
+    ops of another kind."""
+    import dataclasses
+    from workloads import H, haar_unitary, rz
+    rng = np.random.default_rng(5)
+    sizes = [10, 12, 9, 11, 13]
+    ops = [param_circuit(n, 3, 300 + i) for i, n in enumerate(sizes)]
+    regs = [q.Register(env, n) for n in sizes]
+    circs = [q.Circuit(o) for o in ops]
+    b = q.Batch(regs, circs, 10)
+    b.capture(init_zero=True)
+    b.replay()
+    for r, n, o in zip(regs, sizes, ops):
+        assert max_abs(r.get_amps(), O.run_sv(n, o)) <= 1e-12
+    new_ops = []
+    for c, o in zip(circs, ops):
+        no = list(o)
+        for k, op in enumerate(no):
+            if op.kind == 'u':
+                u = (haar_unitary(rng), np.eye(2), rz(float(rng.uniform(0, 6))), H)[k % 4]
+                c.set_unitary(k, u)
+                no[k] = dataclasses.replace(op, u=np.asarray(u, dtype=np.complex128))
+            elif op.kind == 'phase':
+                a = float(rng.uniform(0, 6))
+                c.set_phase(k, a)
+                no[k] = dataclasses.replace(op, angle=a)
+        new_ops.append(no)
+    b.update()
+    b.replay()
+    for r, n, o in zip(regs, sizes, new_ops):
+        assert max_abs(r.get_amps(), O.run_sv(n, o)) <= 1e-12
+    # errors: wrong op kind, index out of range, not unitary
+    k_u = next(k for k, op in enumerate(ops[0]) if op.kind == 'u')
+    k_p = next(k for k, op in enumerate(ops[0]) if op.kind == 'phase')
+    for bad in (lambda: circs[0].set_unitary(k_p, H), lambda: circs[0].set_phase(k_u, 0.1),
+                lambda: circs[0].set_unitary(len(ops[0]), H), lambda: circs[0].set_unitary(k_u, 2 * H)):
+        with pytest.raises(q.QStateError):
+            bad()
+    close_all(b, regs, circs)
+
+
+def test_compiled_circuit_sees_parameter_changes(q, env):
+    """Compiled passes are rebuilt after qs_circuit_set_*: the second run
+    uses the new matrices (one turned diagonal) and matches the oracle."""
+    import dataclasses
+    from workloads import haar_unitary, layered_circuit
+    rng = np.random.default_rng(6)
+    n = 14
+    ops = layered_circuit(n, 3, 4, mcphase=True)
+    reg = q.Register(env, n)
+    c = q.Circuit(ops)
+    reg.init_zero()
+    c.run_compiled(reg, 12, 8, 0, 4)
+    assert max_abs(reg.get_amps(), O.run_sv(n, ops)) <= 1e-12
+    no = list(ops)
+    for k, op in enumerate(no):
+        if op.kind == 'u' and k % 2 == 0:
+            u = haar_unitary(rng) if k % 4 == 0 else np.diag([1.0, np.exp(0.4j)])
+            c.set_unitary(k, u)
+            no[k] = dataclasses.replace(op, u=np.asarray(u, dtype=np.complex128))
+        elif op.kind == 'phase':
+            c.set_phase(k, 1.3)
+            no[k] = dataclasses.replace(op, angle=1.3)
+    reg.init_zero()
+    c.run_compiled(reg, 12, 8, 0, 4)
+    assert max_abs(reg.get_amps(), O.run_sv(n, no)) <= 1e-12
+    c.close()
+    reg.close()
