@@ -69,3 +69,25 @@ def test_philox_draws_are_numpy_philox4x64_stream():
     assert q.philox_draws(1, 2, 0, 0).size == 0
     with pytest.raises(q.QStateError):
         q.philox_draws(1, 2, 0, -1)
+
+
+def test_circuit_parameter_setters_validate_on_the_host():
+    """qs_circuit_set_unitary / qs_circuit_set_phase (host only, no device):
+    they accept new values for ops of their own kind and reject another
+    kind, an index out of range, a non-unitary matrix and a non-finite
+    angle, leaving the circuit usable."""
+    import numpy as np
+    import paper_1802_08032_amd as q
+    from workloads import H, Op
+    c = q.Circuit([Op('u', target=0, u=H), Op('x', target=1, controls=(0,)),
+                   Op('phase', qubits=(0, 1), angle=0.5)])
+    c.set_unitary(0, np.eye(2))
+    c.set_phase(2, 1.0)
+    for bad, code in ((lambda: c.set_unitary(1, H), 'QS_E_ARG'), (lambda: c.set_phase(0, 0.1), 'QS_E_ARG'),
+                      (lambda: c.set_unitary(3, H), 'QS_E_ARG'), (lambda: c.set_unitary(-1, H), 'QS_E_ARG'),
+                      (lambda: c.set_unitary(0, 2 * H), 'QS_E_NOT_UNITARY'),
+                      (lambda: c.set_phase(2, float('nan')), 'QS_E_ARG')):
+        with pytest.raises(q.QStateError, match=code):
+            bad()
+    c.set_unitary(0, H)  # still usable
+    c.close()
