@@ -150,7 +150,7 @@ qs_status qs_multi_controlled_phase(qs_reg r, const int* qubits, int n_qubits, d
  *   qs_sqrt_x     [[1+i, 1-i], [1-i, 1+i]] / 2   (its square is X)
  *   qs_sqrt_y     [[1+i, -1-i], [1+i, 1+i]] / 2  (its square is Y)
  * with c = cos(theta / 2), s = sin(theta / 2).  H, T, CZ, sqrt X and sqrt Y
- * are the gate set of the paper's random circuits (Sec. III.A). */
+ * are the gate set of the paper's random circuits (Sec. II.C). */
 qs_status qs_hadamard(qs_reg r, int target);
 qs_status qs_cnot(qs_reg r, int control, int target);
 qs_status qs_cz(qs_reg r, int q1, int q2);

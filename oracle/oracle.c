@@ -170,12 +170,14 @@ void or_dm_kraus(or_cplx* rho, int N, int t, const or_cplx* kraus, int nk)
 {
     const uint64_t dim = (uint64_t)1 << N;
     const uint64_t tb = (uint64_t)1 << t;
+    /* column blocks outermost, so that the inner loop walks rows, which are
+     * contiguous in the vector; every block is computed the same way */
 #pragma omp parallel for schedule(static) if (dim >= 256)
-    for (int64_t jj = 0; jj < (int64_t)dim; ++jj) {
-        const uint64_t j = (uint64_t)jj;
-        if (j & tb) continue;
-        for (uint64_t k = 0; k < dim; ++k) {
-            if (k & tb) continue;
+    for (int64_t kk = 0; kk < (int64_t)dim; ++kk) {
+        const uint64_t k = (uint64_t)kk;
+        if (k & tb) continue;
+        for (uint64_t j = 0; j < dim; ++j) {
+            if (j & tb) continue;
             or_cplx B[2][2], S[2][2] = {{0, 0}, {0, 0}};
             for (int r = 0; r < 2; ++r)
                 for (int c = 0; c < 2; ++c)

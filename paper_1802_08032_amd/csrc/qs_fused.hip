@@ -704,7 +704,8 @@ qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
         maxpasses = std::max(maxpasses, (int)plan.size());
         std::vector<int> src;
         serialize(plan, *ops, cfg.TB, cfg.RB, hp, hops, &src);
-        for (int idx : src) b->op_src.push_back({(int)i, idx});
+        // the placeholder of an empty circuit has no source op: updates skip it
+        for (int idx : src) b->op_src.push_back(ops == &none ? std::make_pair(-1, -1) : std::make_pair((int)i, idx));
     }
     if (hp.empty()) hp.push_back(FPass{});
     if (hops.empty()) {

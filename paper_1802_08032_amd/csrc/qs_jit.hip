@@ -596,7 +596,7 @@ size_t esz_of(int prec) { return prec == QS_C128 ? sizeof(double) : sizeof(float
 
 // Per-circuit cache of the compiled form for one (register shape, tile).
 struct JitPlan {
-    int n = -1, prec = 0, TB = 0, RB = 0, max_phases = 0, contig = 0, device = -1;
+    int n = -1, kind = -1, prec = 0, TB = 0, RB = 0, max_phases = 0, contig = 0, device = -1;
     size_t nops = 0;
     uint64_t version = 0;  // circuit parameter version the plan was built from
     std::vector<hipFunction_t> fns;
@@ -624,7 +624,11 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
     const int nbits = r->nbits;
     if (cfg.max_phases <= 0 || cfg.max_phases > kPhMax) cfg.max_phases = kPhMax;
     JitPlan* J = c->jit;
-    const bool fresh = !J || J->n != nbits || J->prec != r->prec || J->TB != cfg.TB || J->RB != cfg.RB ||
+    // a 2N-qubit state vector and an N-qubit density matrix share nbits but
+    // not their op lists (Eq. 2 adds the conjugate gates): the kind is part
+    // of the key
+    const bool fresh = !J || J->n != nbits || J->kind != r->kind || J->prec != r->prec || J->TB != cfg.TB ||
+                       J->RB != cfg.RB ||
                        J->max_phases != cfg.max_phases || J->contig != cfg.contig || J->device != r->env->device ||
                        J->nops != c->ops.size() || J->version != c->version;
     if (fresh) {
@@ -673,6 +677,7 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
             return hip_error(e, "matrix upload");
         }
         nj->n = nbits;
+        nj->kind = r->kind;
         nj->prec = r->prec;
         nj->TB = cfg.TB;
         nj->RB = cfg.RB;

@@ -154,8 +154,10 @@ def test_batch_parameter_update_replays_new_values(q, env):
     import dataclasses
     from workloads import H, haar_unitary, rz
     rng = np.random.default_rng(5)
-    sizes = [10, 12, 9, 11, 13]
-    ops = [param_circuit(n, 3, 300 + i) for i, n in enumerate(sizes)]
+    sizes = [10, 12, 9, 11, 13, 10]
+    # the last register's circuit is empty (the batch runs a placeholder
+    # pass for it, which an update must leave alone)
+    ops = [param_circuit(n, 3, 300 + i) for i, n in enumerate(sizes[:-1])] + [[]]
     regs = [q.Register(env, n) for n in sizes]
     circs = [q.Circuit(o) for o in ops]
     b = q.Batch(regs, circs, 10)
@@ -180,6 +182,7 @@ def test_batch_parameter_update_replays_new_values(q, env):
     b.replay()
     for r, n, o in zip(regs, sizes, new_ops):
         assert max_abs(r.get_amps(), O.run_sv(n, o)) <= 1e-12
+    assert max_abs(regs[-1].get_amps(), O.zero_state(sizes[-1])) == 0.0
     # errors: wrong op kind, index out of range, not unitary
     k_u = next(k for k, op in enumerate(ops[0]) if op.kind == 'u')
     k_p = next(k for k, op in enumerate(ops[0]) if op.kind == 'phase')
