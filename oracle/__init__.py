@@ -68,6 +68,13 @@ def lib():
             'or_dm_measure': (i, [vp, i, i, d, C.POINTER(d)]),
             'or_neumaier_sum': (d, [vp, u64]),
             'or_set_threads': (i, [i]),
+            'or_sv_multi_unitary': (None, [vp, i, vp, i, vp, i, vp]),
+            'or_dm_multi_unitary': (None, [vp, i, vp, i, vp, i, vp]),
+            'or_dm_kraus_multi': (None, [vp, i, vp, i, vp, i]),
+            'or_init_uniform': (None, [vp, u64, d]),
+            'or_dm_init_pure': (None, [vp, i, vp]),
+            'or_dm_purity': (d, [vp, i]),
+            'or_dm_fidelity_pure': (d, [vp, i, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -76,6 +83,8 @@ def lib():
         # returns double complex: read back through a 2-double struct
         class _C2(C.Structure):
             _fields_ = [('re', C.c_double), ('im', C.c_double)]
+        L.or_sv_inner_product.restype = _C2
+        L.or_sv_inner_product.argtypes = [vp, vp, i]
         L.or_sv_amp_after.restype = _C2
         L.or_sv_amp_after.argtypes = [i, vp, vp, i, u64]
         _lib = L
@@ -175,6 +184,58 @@ def dm_damping(rho, N, t, g):
     lib().or_dm_damping(_p(rho), N, t, float(g))
 
 
+def _matk(u, k) -> np.ndarray:
+    d = 1 << k
+    m = np.ascontiguousarray(np.asarray(u, dtype=np.complex128).reshape(d * d))
+    return m
+
+
+def sv_multi_unitary(amp, n, controls, targets, u):
+    c, t = _ints(controls), _ints(targets)
+    m = _matk(u, len(t))
+    lib().or_sv_multi_unitary(_p(amp), n, _p(c), len(c), _p(t), len(t), _p(m))
+
+
+def dm_multi_unitary(rho, N, controls, targets, u):
+    c, t = _ints(controls), _ints(targets)
+    m = _matk(u, len(t))
+    lib().or_dm_multi_unitary(_p(rho), N, _p(c), len(c), _p(t), len(t), _p(m))
+
+
+def dm_kraus_multi(rho, N, targets, kraus_ops):
+    t = _ints(targets)
+    d = 1 << len(t)
+    k = np.ascontiguousarray(np.asarray(kraus_ops, dtype=np.complex128).reshape(-1))
+    lib().or_dm_kraus_multi(_p(rho), N, _p(t), len(t), _p(k), k.size // (d * d))
+
+
+def uniform_state(nbits: int, value: float) -> np.ndarray:
+    a = np.empty(1 << nbits, dtype=np.complex128)
+    lib().or_init_uniform(_p(a), a.size, float(value))
+    return a
+
+
+def dm_pure(N, psi) -> np.ndarray:
+    psi = np.ascontiguousarray(np.asarray(psi, dtype=np.complex128))
+    rho = np.empty(1 << (2 * N), dtype=np.complex128)
+    lib().or_dm_init_pure(_p(rho), N, _p(psi))
+    return rho
+
+
+def sv_inner_product(bra, ket, n) -> complex:
+    z = lib().or_sv_inner_product(_p(bra), _p(ket), n)
+    return complex(z.re, z.im)
+
+
+def dm_purity(rho, N) -> float:
+    return lib().or_dm_purity(_p(rho), N)
+
+
+def dm_fidelity_pure(rho, N, psi) -> float:
+    psi = np.ascontiguousarray(np.asarray(psi, dtype=np.complex128))
+    return lib().or_dm_fidelity_pure(_p(rho), N, _p(psi))
+
+
 def dm_total_prob(rho, N) -> float:
     return lib().or_dm_total_prob(_p(rho), N)
 
@@ -204,6 +265,8 @@ def apply_sv(amp, n, op):
         sv_x(amp, n, op.controls, op.target)
     elif op.kind == 'phase':
         sv_phase(amp, n, op.qubits, op.angle)
+    elif op.kind == 'unitary':
+        sv_multi_unitary(amp, n, op.controls, op.targets, op.u)
     else:
         raise ValueError(f'{op.kind} is not defined on a state vector')
 
@@ -221,6 +284,10 @@ def apply_dm(rho, N, op):
         dm_depolarising(rho, N, op.target, op.p)
     elif op.kind == 'damping':
         dm_damping(rho, N, op.target, op.p)
+    elif op.kind == 'unitary':
+        dm_multi_unitary(rho, N, op.controls, op.targets, op.u)
+    elif op.kind == 'kraus':
+        dm_kraus_multi(rho, N, op.targets, op.kraus)
     else:
         raise ValueError(op.kind)
 

@@ -266,6 +266,157 @@ int or_dm_measure(or_cplx* rho, int N, int q, double r, double* prob)
     return outcome;
 }
 
+/* ---- multi-qubit gates and maps ----------------------------------------- */
+
+/* Offset of matrix index a on the target qubits: bit j of a sits at bit
+ * targets[j] of the amplitude index. */
+static uint64_t spread(uint64_t a, const int* targets, int nt)
+{
+    uint64_t o = 0;
+    for (int j = 0; j < nt; ++j)
+        if ((a >> j) & 1) o |= (uint64_t)1 << targets[j];
+    return o;
+}
+
+/* A k-qubit gate (Sec. II.B.1: the pair update of Eq. 1 holds for
+ * multi-qubit gates with groups of 2^k amplitudes in place of pairs): for
+ * every index b whose target bits are all 0 and whose control bits are all
+ * 1, the 2^k amplitudes x_a = alpha_{b + spread(a)} are replaced by U x.
+ * u is 2^k x 2^k row-major, u[r * 2^k + c]. */
+void or_sv_multi_unitary(or_cplx* amp, int n, const int* ctrls, int nctrl, const int* targets, int nt,
+                         const or_cplx* u)
+{
+    const uint64_t len = (uint64_t)1 << n;
+    const uint64_t tmask = mask_of(targets, nt), cmask = mask_of(ctrls, nctrl);
+    const int d = 1 << nt;
+#pragma omp parallel for schedule(static) if (len >= 65536)
+    for (int64_t bb = 0; bb < (int64_t)len; ++bb) {
+        const uint64_t b = (uint64_t)bb;
+        if ((b & tmask) != 0 || (b & cmask) != cmask) continue;
+        or_cplx x[32], y[32];
+        for (int a = 0; a < d; ++a) x[a] = amp[b + spread((uint64_t)a, targets, nt)];
+        for (int r = 0; r < d; ++r) {
+            or_cplx acc = 0;
+            for (int c = 0; c < d; ++c) acc += u[r * d + c] * x[c];
+            y[r] = acc;
+        }
+        for (int a = 0; a < d; ++a) amp[b + spread((uint64_t)a, targets, nt)] = y[a];
+    }
+}
+
+/* Eq. 2 for a k-qubit gate: U on the row qubits, then conj(U) on the column
+ * qubits (targets + N, controls + N). */
+void or_dm_multi_unitary(or_cplx* rho, int N, const int* ctrls, int nctrl, const int* targets, int nt,
+                         const or_cplx* u)
+{
+    const int d = 1 << nt;
+    int cs[64], ts[8];
+    for (int k = 0; k < nctrl; ++k) cs[k] = ctrls[k] + N;
+    for (int k = 0; k < nt; ++k) ts[k] = targets[k] + N;
+    or_cplx* uc = (or_cplx*)malloc(sizeof(or_cplx) * (size_t)d * (size_t)d);
+    for (int k = 0; k < d * d; ++k) uc[k] = conj(u[k]);
+    or_sv_multi_unitary(rho, 2 * N, ctrls, nctrl, targets, nt, u);
+    or_sv_multi_unitary(rho, 2 * N, cs, nctrl, ts, nt, uc);
+    free(uc);
+}
+
+/* Kraus map on the qubits `targets` (k of them, k <= 2): every 2^k x 2^k
+ * block B of rho whose row and column indices vary only in the target bits
+ * is replaced by sum_m K_m B K_m^dagger, by plain matrix products.  kraus
+ * holds nk row-major 2^k x 2^k matrices one after the other. */
+void or_dm_kraus_multi(or_cplx* rho, int N, const int* targets, int nt, const or_cplx* kraus, int nk)
+{
+    const uint64_t dim = (uint64_t)1 << N;
+    const uint64_t tmask = mask_of(targets, nt);
+    const int d = 1 << nt;
+#pragma omp parallel for schedule(static) if (dim >= 256)
+    for (int64_t kk = 0; kk < (int64_t)dim; ++kk) {
+        const uint64_t k = (uint64_t)kk;
+        if (k & tmask) continue;
+        for (uint64_t j = 0; j < dim; ++j) {
+            if (j & tmask) continue;
+            or_cplx B[4][4], S[4][4];
+            for (int r = 0; r < d; ++r)
+                for (int c = 0; c < d; ++c) {
+                    B[r][c] = rho[(j | spread((uint64_t)r, targets, nt)) + dim * (k | spread((uint64_t)c, targets, nt))];
+                    S[r][c] = 0;
+                }
+            for (int m = 0; m < nk; ++m) {
+                const or_cplx* K = kraus + (size_t)m * d * d;
+                or_cplx KB[4][4];
+                for (int r = 0; r < d; ++r)
+                    for (int c = 0; c < d; ++c) {
+                        or_cplx acc = 0;
+                        for (int s = 0; s < d; ++s) acc += K[r * d + s] * B[s][c];
+                        KB[r][c] = acc;
+                    }
+                for (int r = 0; r < d; ++r)
+                    for (int c = 0; c < d; ++c) {
+                        or_cplx acc = 0;
+                        for (int s = 0; s < d; ++s) acc += KB[r][s] * conj(K[c * d + s]);
+                        S[r][c] += acc;
+                    }
+            }
+            for (int r = 0; r < d; ++r)
+                for (int c = 0; c < d; ++c)
+                    rho[(j | spread((uint64_t)r, targets, nt)) + dim * (k | spread((uint64_t)c, targets, nt))] = S[r][c];
+        }
+    }
+}
+
+/* ---- state initialisation and overlaps ---------------------------------- */
+
+/* |+>^n = H^(x)n |0..0>: every amplitude 2^(-n/2).  For a density matrix
+ * (len = 4^N) the same routine with value 2^(-N) gives |+><+|. */
+void or_init_uniform(or_cplx* amp, uint64_t len, double value)
+{
+    for (uint64_t i = 0; i < len; ++i) amp[i] = value;
+}
+
+/* rho = |psi><psi|: rho[j][k] = psi_j conj(psi_k), stored at j + 2^N k. */
+void or_dm_init_pure(or_cplx* rho, int N, const or_cplx* psi)
+{
+    const uint64_t dim = (uint64_t)1 << N;
+    for (uint64_t k = 0; k < dim; ++k)
+        for (uint64_t j = 0; j < dim; ++j) rho[j + dim * k] = psi[j] * conj(psi[k]);
+}
+
+/* <bra|ket> = sum_i conj(bra_i) ket_i, real and imaginary parts summed
+ * with Neumaier compensation. */
+or_cplx or_sv_inner_product(const or_cplx* bra, const or_cplx* ket, int n)
+{
+    const uint64_t len = (uint64_t)1 << n;
+    nsum re = {0.0, 0.0}, im = {0.0, 0.0};
+    for (uint64_t i = 0; i < len; ++i) {
+        const or_cplx z = conj(bra[i]) * ket[i];
+        nsum_add(&re, creal(z));
+        nsum_add(&im, cimag(z));
+    }
+    return (re.s + re.c) + I * (im.s + im.c);
+}
+
+/* Purity Tr(rho^2) = sum_jk rho_jk rho_kj = sum_jk |rho_jk|^2 for Hermitian
+ * rho (Neumaier sum over every entry). */
+double or_dm_purity(const or_cplx* rho, int N)
+{
+    const uint64_t len = (uint64_t)1 << (2 * N);
+    nsum acc = {0.0, 0.0};
+    for (uint64_t i = 0; i < len; ++i) nsum_add(&acc, abs2(rho[i]));
+    return acc.s + acc.c;
+}
+
+/* Fidelity of rho with the pure state psi: <psi|rho|psi> =
+ * sum_jk conj(psi_j) rho_jk psi_k (its real part; the imaginary part
+ * vanishes for Hermitian rho). */
+double or_dm_fidelity_pure(const or_cplx* rho, int N, const or_cplx* psi)
+{
+    const uint64_t dim = (uint64_t)1 << N;
+    nsum acc = {0.0, 0.0};
+    for (uint64_t k = 0; k < dim; ++k)
+        for (uint64_t j = 0; j < dim; ++j) nsum_add(&acc, creal(conj(psi[j]) * rho[j + dim * k] * psi[k]));
+    return acc.s + acc.c;
+}
+
 /* ---- single output amplitude ------------------------------------------ */
 
 static or_cplx amp_rec(int n, const or_cplx* v, const or_gate* g, int ng, uint64_t i)

@@ -68,6 +68,24 @@ double or_dm_total_prob(const or_cplx* rho, int N);
 double or_dm_prob_outcome(const or_cplx* rho, int N, int q, int outcome);
 int or_dm_measure(or_cplx* rho, int N, int q, double r, double* prob);
 
+/* k-qubit gates (k = n_targets <= 5): U is 2^k x 2^k row-major, matrix
+ * index bit j <-> qubit targets[j]; applied to every group of 2^k amplitudes
+ * whose control bits are all 1.  On rho: U on the targets, then conj(U) on
+ * targets + N (controls + N). */
+void or_sv_multi_unitary(or_cplx* amp, int n, const int* ctrls, int nctrl, const int* targets, int nt,
+                         const or_cplx* u);
+void or_dm_multi_unitary(or_cplx* rho, int N, const int* ctrls, int nctrl, const int* targets, int nt,
+                         const or_cplx* u);
+/* Kraus map on k <= 2 qubits: nk row-major 2^k x 2^k operators. */
+void or_dm_kraus_multi(or_cplx* rho, int N, const int* targets, int nt, const or_cplx* kraus, int nk);
+
+/* Initialisation and overlaps. */
+void or_init_uniform(or_cplx* amp, uint64_t len, double value);
+void or_dm_init_pure(or_cplx* rho, int N, const or_cplx* psi);
+or_cplx or_sv_inner_product(const or_cplx* bra, const or_cplx* ket, int n);
+double or_dm_purity(const or_cplx* rho, int N);
+double or_dm_fidelity_pure(const or_cplx* rho, int N, const or_cplx* psi);
+
 /* One output amplitude of: product state (x)_q v_q, then gates[0..ng).
  * v holds n two-vectors, v[2q + b] = <b|v_q>.  Each gate is read as Eq. 1
  * for the single output element requested; cost 2^(#dense gates). */

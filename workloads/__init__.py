@@ -8,5 +8,5 @@ that arithmetic on their own.
 from .circuits import (  # noqa: F401
     Op, haar_unitary, layered_circuit, noisy_circuit, param_circuit,
     measurement_draws, gate_counts, product_layer, inverse, random_state,
-    random_gate_ops, serving_requests, X, H, ry, rz,
+    random_gate_ops, serving_requests, X, H, ry, rz, haar_unitary_k, random_kraus, random_multi_ops,
 )

@@ -55,6 +55,10 @@ class Op:
                      ``qubits`` are all 1 (CZ is angle = pi on two qubits)
       'dephasing' / 'depolarising' / 'damping'
                      single-qubit channel of strength ``p`` on ``target``
+      'unitary'      dense 2^k x 2^k ``u`` on ``targets`` (matrix index bit j
+                     is qubit targets[j]) where every control is 1
+      'kraus'        Kraus map with operators ``kraus`` (each 2^k x 2^k) on
+                     ``targets`` (density matrices only)
     """
     kind: str
     target: int = -1
@@ -63,10 +67,14 @@ class Op:
     qubits: tuple = ()
     angle: float = 0.0
     p: float = 0.0
+    targets: tuple = ()
+    kraus: tuple = ()
 
     def touched(self) -> tuple:
         if self.kind == 'phase':
             return tuple(sorted(self.qubits))
+        if self.kind in ('unitary', 'kraus'):
+            return tuple(sorted(set(self.controls) | set(self.targets)))
         return tuple(sorted(set(self.controls) | {self.target}))
 
 
@@ -166,6 +174,48 @@ def inverse(ops: list[Op]) -> list[Op]:
         else:
             raise ValueError(f'{o.kind} has no inverse')
     return out
+
+
+def haar_unitary_dim(rng: np.random.Generator, d: int) -> np.ndarray:
+    """Haar-random U(d), by the same QR recipe as haar_unitary."""
+    z = (rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))) / math.sqrt(2.0)
+    q, r = np.linalg.qr(z)
+    dg = np.diagonal(r)
+    return np.ascontiguousarray(q * (dg / np.abs(dg))[None, :], dtype=np.complex128)
+
+
+def haar_unitary_k(rng: np.random.Generator, k: int) -> np.ndarray:
+    """Haar-random unitary on k qubits (2^k x 2^k)."""
+    return haar_unitary_dim(rng, 1 << k)
+
+
+def random_kraus(rng: np.random.Generator, k: int, count: int) -> tuple:
+    """`count` Kraus operators on k qubits with sum K^dagger K = I: the
+    blocks of the first 2^k columns of a Haar unitary of size count * 2^k
+    (a Stinespring isometry)."""
+    d = 1 << k
+    w = haar_unitary_dim(rng, count * d)[:, :d]
+    return tuple(np.ascontiguousarray(w[m * d:(m + 1) * d, :]) for m in range(count))
+
+
+def random_multi_ops(n: int, count: int, seed: int, max_targets: int = 3, max_controls: int = 2,
+                     kraus: bool = False) -> list[Op]:
+    """Dense k-qubit unitaries (k = 1..max_targets, Haar) on random distinct
+    targets with 0..max_controls random controls; with `kraus`, every third op
+    is instead a random 1- or 2-qubit Kraus map of 1..4 operators."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ops: list[Op] = []
+    for i in range(count):
+        if kraus and i % 3 == 2:
+            k = int(rng.integers(1, min(2, n) + 1))
+            ts = tuple(int(v) for v in rng.choice(n, size=k, replace=False))
+            ops.append(Op('kraus', targets=ts, kraus=random_kraus(rng, k, int(rng.integers(1, 5)))))
+            continue
+        k = int(rng.integers(1, min(max_targets, n) + 1))
+        c = int(rng.integers(0, min(max_controls, n - k) + 1))
+        qs = [int(v) for v in rng.choice(n, size=k + c, replace=False)]
+        ops.append(Op('unitary', targets=tuple(qs[:k]), controls=tuple(qs[k:]), u=haar_unitary_k(rng, k)))
+    return ops
 
 
 def random_state(nbits: int, seed: int) -> np.ndarray:
