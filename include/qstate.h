@@ -58,7 +58,8 @@ typedef enum {
     QS_E_OOM = -3,         /* device allocation failed                                   */
     QS_E_DEVICE = -4,      /* a HIP call failed; qs_last_error() has hipGetErrorString   */
     QS_E_HANDLE = -5,      /* null, destroyed or foreign handle                          */
-    QS_E_NOT_UNITARY = -6  /* max |U U^dagger - I| > 1e-10                               */
+    QS_E_NOT_UNITARY = -6, /* max |U U^dagger - I| > 1e-10                               */
+    QS_E_NOT_CPTP = -7     /* Kraus operators with max |sum K^dagger K - I| > 1e-10      */
 } qs_status;
 
 /* Channel kinds for qs_circuit_add_channel. */
@@ -169,6 +170,77 @@ qs_status qs_mix_dephasing(qs_reg r, int target, double p);
 qs_status qs_mix_depolarising(qs_reg r, int target, double p);
 /* Kraus {[[1,0],[0,sqrt(1-g)]], [[0,sqrt(g)],[0,0]]},   0 <= g <= 1 */
 qs_status qs_mix_damping(qs_reg r, int target, double gamma);
+
+/* ---- gates on several qubits and general Kraus maps --------------------- */
+/* Sec. II.B.1: the pair update of Eq. 1 generalises to the group of 2^k
+ * amplitudes that agree outside the k target bits, and the Eq. 2 identity
+ * holds for multi-qubit gates.  Matrices are row-major 2^k x 2^k qs_cplx in
+ * double precision; matrix index bit j corresponds to qubit targets[j]
+ * (entry [r][c] maps the amplitude whose target bits spell c into the one
+ * whose target bits spell r).  For QS_C64 registers they are rounded to
+ * float once per call.  Each call copies its matrix to the register's
+ * scratch memory on the register's stream and returns without waiting. */
+
+/* Dense k-qubit unitary u on targets[0..k), k = 1..5, applied to the groups
+ * whose `n_controls` control bits are all 1 (controls distinct and not
+ * targets).  On a density matrix: u on the targets (controls as given), then
+ * conj(u) on targets + N (controls + N), Eq. 2.  QS_E_ARG for a bad qubit
+ * list or a non-finite entry, QS_E_NOT_UNITARY for max |u u^dagger - I| >
+ * 1e-10. */
+qs_status qs_multi_qubit_unitary(qs_reg r, const int* controls, int n_controls, const int* targets,
+                                 int n_targets, const qs_cplx* u);
+/* qs_multi_qubit_unitary on (target1, target2) with no controls: u is 4x4,
+ * index = bit(target1) + 2 bit(target2). */
+qs_status qs_two_qubit_unitary(qs_reg r, int target1, int target2, const qs_cplx u[16]);
+
+/* General Kraus map rho -> sum_m K_m rho K_m^dagger on k = 1 or 2 target
+ * qubits of a density matrix (the decoherence of Sec. II.B.1 in its general
+ * form): `ops` holds n_ops operators of 2^k x 2^k, one after the other,
+ * 1 <= n_ops <= 4^k.  Applied in one pass as the superoperator
+ * S = sum_m conj(K_m) (x) K_m on (targets, targets + N), which the host forms
+ * in double precision.  QS_E_KIND on a state vector; QS_E_NOT_CPTP when
+ * max |sum_m K_m^dagger K_m - I| > 1e-10. */
+qs_status qs_mix_multi_kraus(qs_reg r, const int* targets, int n_targets, const qs_cplx* ops, int n_ops);
+qs_status qs_mix_kraus(qs_reg r, int target, const qs_cplx* ops, int n_ops);
+qs_status qs_mix_two_qubit_kraus(qs_reg r, int target1, int target2, const qs_cplx* ops, int n_ops);
+
+/* ---- initialisation variants, copies, overlaps, checkpoints -------------- */
+/* Sec. II.B.1 allows direct reading and writing of the state; these build
+ * common states on the device and read overlaps without copying the state
+ * to the host.  Calls that take two registers need the same device,
+ * precision and qubit count; they order the two registers' streams with
+ * events (the reading call runs after earlier work on the other register,
+ * and later work on that register runs after the read). */
+
+/* |+>^n: every amplitude 2^(-n/2); on a density matrix |+><+|, every entry
+ * 2^-N.  Write-only, asynchronous. */
+qs_status qs_init_plus(qs_reg r);
+/* r = |psi><psi| (density matrix r, entry j + 2^N k = psi_j conj(psi_k)) or
+ * a copy of psi (state vector r), psi = the state vector `pure`.
+ * Asynchronous. */
+qs_status qs_init_pure_state(qs_reg r, qs_reg pure);
+/* Copy the whole state of `src` into `dst` (same kind too).  Asynchronous. */
+qs_status qs_clone(qs_reg dst, qs_reg src);
+/* <bra|ket> = sum_i conj(bra_i) ket_i of two state vectors, accumulated in
+ * double precision with compensated sums.  Synchronous. */
+qs_status qs_calc_inner_product(qs_reg bra, qs_reg ket, qs_cplx* out);
+/* Tr(rho^2) of a density matrix (the squared norm of its Eq. 2 vector, equal
+ * to the purity for Hermitian rho), compensated, in double.  Synchronous. */
+qs_status qs_calc_purity(qs_reg r, double* out);
+/* Fidelity with the pure state `pure`: |<pure|r>|^2 for a state vector r,
+ * <pure|rho|pure> (real part) for a density matrix r.  Synchronous. */
+qs_status qs_calc_fidelity(qs_reg r, qs_reg pure, double* out);
+/* Checkpoint: write the register to `path` (64-byte header: "QSTATE01",
+ * int32 n, kind, prec, 0, uint64 amplitude count, 32 zero bytes; then the
+ * raw amplitudes in the register's precision), streamed through two pinned
+ * 64 MiB buffers so that device copies overlap file writes.  Synchronous;
+ * QS_E_ARG on an I/O failure. */
+qs_status qs_save_state(qs_reg r, const char* path);
+/* Read a checkpoint written by qs_save_state into a register of the same
+ * n, kind and precision.  The header and file size are checked before any
+ * amplitude is written (QS_E_ARG, register unchanged); an I/O error later
+ * leaves the register partly overwritten.  Synchronous. */
+qs_status qs_load_state(qs_reg r, const char* path);
 
 /* ---- probabilities and measurement -------------------------------------- */
 /* The paper states no probability or measurement routine; these read the

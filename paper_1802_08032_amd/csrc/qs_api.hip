@@ -489,7 +489,7 @@ static qs_status reg_common(qs_env env, int n, int kind, int prec, void* stream,
         }
     }
     if (!scratch) {
-        const size_t sbytes = (4 * qs::kReduceBlocks + 2) * sizeof(double);
+        const size_t sbytes = qs::kScratchDoubles * sizeof(double);
         hipError_t e = dev_alloc(&scratch, sbytes);
         if (e == hipSuccess) e = hipHostMalloc(&hres, 2 * sizeof(double), hipHostMallocDefault);
         if (e != hipSuccess) {
@@ -1407,6 +1407,484 @@ qs_status qs_batch_info(qs_batch b, int* n_regs, int* tile_qubits, int* n_passes
     if (tile_qubits) *tile_qubits = b->TB + b->RB;
     if (n_passes) *n_passes = b->passes_total;
     return QS_OK;
+}
+
+
+// ---- k-qubit gates and Kraus maps -------------------------------------------
+// Sec. II.B.1: the pair update of Eq. 1 generalises to a group of 2^k
+// amplitudes for a gate on k qubits, and the Eq. 2 identity holds for
+// multi-qubit gates (G on the row qubits, conj(G) on the column qubits); a
+// Kraus map is applied through the same identity as its superoperator
+// sum_m conj(K_m) (x) K_m on the row and column qubits of its targets.
+
+namespace {
+
+// max |(A A^dagger - I)[r][c]| (d x d, row-major) or, with `kraus`,
+// max |(sum_m K_m^dagger K_m - I)[r][c]| over `count` matrices.
+double identity_error(const qs_cplx* a, int d, int count, bool kraus)
+{
+    double worst = 0.0;
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) {
+            double re = 0.0, im = 0.0;
+            for (int m = 0; m < count; ++m) {
+                const qs_cplx* A = a + (size_t)m * d * d;
+                for (int s = 0; s < d; ++s) {
+                    // unitary: A[r][s] conj(A[c][s]); Kraus: conj(A[s][r]) A[s][c]
+                    const qs_cplx x = kraus ? A[s * d + r] : A[r * d + s];
+                    const qs_cplx y = kraus ? A[s * d + c] : A[c * d + s];
+                    if (kraus) {
+                        re += x.re * y.re + x.im * y.im;
+                        im += x.re * y.im - x.im * y.re;
+                    } else {
+                        re += x.re * y.re + x.im * y.im;
+                        im += x.im * y.re - x.re * y.im;
+                    }
+                }
+            }
+            if (r == c) re -= 1.0;
+            worst = std::max(worst, std::max(fabs(re), fabs(im)));
+        }
+    return worst;
+}
+
+qs_status check_finite(const qs_cplx* a, size_t count)
+{
+    for (size_t k = 0; k < count; ++k)
+        if (!isfinite(a[k].re) || !isfinite(a[k].im)) return qs::set_error(QS_E_ARG, "non-finite matrix entry");
+    return QS_OK;
+}
+
+// Copy a d x d complex matrix (interleaved doubles) into matrix slot `slot`
+// (0 or 1) of the register's scratch, in the register's precision, ordered
+// on its stream after earlier work; returns the device address.
+qs_status upload_matrix(qs_reg r, int slot, const std::vector<double>& m, const void** dev)
+{
+    char* dst = (char*)(r->scratch + qs::kScratchMatOff) + (size_t)slot * (32 * 32 * 2 * sizeof(double));
+    if (r->prec == QS_C128) {
+        QS_HIP(hipMemcpyAsync(dst, m.data(), m.size() * sizeof(double), hipMemcpyHostToDevice, r->stream));
+    } else {
+        std::vector<float> f(m.begin(), m.end());
+        QS_HIP(hipMemcpyAsync(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, r->stream));
+    }
+    *dev = dst;
+    return QS_OK;
+}
+
+qs_status group_launch(qs_reg r, const int* targets, int k, const int* ctrls, int nc, const void* dev_m, int klass)
+{
+    const qs::Launch L = launch_of(r);
+    return qs::profiled(r, klass, [&](int*) {
+        return r->prec == QS_C128
+                   ? qs::launch_group_gate<double>(L, r->amp, r->nbits, targets, k, ctrls, nc, (const double*)dev_m)
+                   : qs::launch_group_gate<float>(L, r->amp, r->nbits, targets, k, ctrls, nc, (const float*)dev_m);
+    });
+}
+
+}  // namespace
+
+qs_status qs_multi_qubit_unitary(qs_reg r, const int* controls, int n_controls, const int* targets,
+                                 int n_targets, const qs_cplx* u)
+{
+    QS_CHECK_REG(r);
+    if (n_targets < 1 || n_targets > 5) return qs::set_error(QS_E_ARG, "1 to 5 target qubits");
+    qs_status s = check_qubits(targets, n_targets, r->n, -1, "targets");
+    if (s) return s;
+    if ((s = check_qubits(controls, n_controls, r->n, -1, "controls"))) return s;
+    for (int i = 0; i < n_controls; ++i)
+        for (int j = 0; j < n_targets; ++j)
+            if (controls[i] == targets[j]) return qs::set_error(QS_E_ARG, "controls: control equals a target");
+    if (!u) return qs::set_error(QS_E_ARG, "NULL matrix");
+    const int d = 1 << n_targets;
+    if ((s = check_finite(u, (size_t)d * d))) return s;
+    if (identity_error(u, d, 1, false) > 1e-10) return qs::set_error(QS_E_NOT_UNITARY, "matrix is not unitary");
+    std::vector<double> m(2 * d * d);
+    for (int i = 0; i < d * d; ++i) {
+        m[2 * i] = u[i].re;
+        m[2 * i + 1] = u[i].im;
+    }
+    const void* dm = nullptr;
+    if ((s = upload_matrix(r, 0, m, &dm))) return s;
+    if ((s = group_launch(r, targets, n_targets, controls, n_controls, dm, QS_K_GATE))) return s;
+    if (r->kind != QS_DENSITY) return QS_OK;
+    // Eq. 2: conj(U) on the column qubits, controls shifted likewise
+    for (int i = 0; i < d * d; ++i) m[2 * i + 1] = -m[2 * i + 1];
+    int ct[5], cc[64];
+    for (int j = 0; j < n_targets; ++j) ct[j] = targets[j] + r->n;
+    for (int j = 0; j < n_controls; ++j) cc[j] = controls[j] + r->n;
+    if ((s = upload_matrix(r, 1, m, &dm))) return s;
+    return group_launch(r, ct, n_targets, cc, n_controls, dm, QS_K_GATE);
+}
+
+qs_status qs_two_qubit_unitary(qs_reg r, int target1, int target2, const qs_cplx u[16])
+{
+    const int t[2] = {target1, target2};
+    return qs_multi_qubit_unitary(r, nullptr, 0, t, 2, u);
+}
+
+qs_status qs_mix_multi_kraus(qs_reg r, const int* targets, int n_targets, const qs_cplx* ops, int n_ops)
+{
+    QS_CHECK_REG(r);
+    if (r->kind != QS_DENSITY) return qs::set_error(QS_E_KIND, "Kraus maps need a density matrix");
+    if (n_targets < 1 || n_targets > 2) return qs::set_error(QS_E_ARG, "1 or 2 target qubits");
+    qs_status s = check_qubits(targets, n_targets, r->n, -1, "targets");
+    if (s) return s;
+    const int d = 1 << n_targets;
+    if (n_ops < 1 || n_ops > d * d) return qs::set_error(QS_E_ARG, "1 to 4^k Kraus operators");
+    if (!ops) return qs::set_error(QS_E_ARG, "NULL Kraus operators");
+    if ((s = check_finite(ops, (size_t)n_ops * d * d))) return s;
+    if (identity_error(ops, d, n_ops, true) > 1e-10)
+        return qs::set_error(QS_E_NOT_CPTP, "Kraus operators are not trace preserving");
+    // S[(a + d b)][(a' + d b')] = sum_m K_m[a][a'] conj(K_m[b][b']): row
+    // index a on the targets, column index b on the targets + N
+    const int D = d * d;
+    std::vector<double> S(2 * D * D, 0.0);
+    for (int m = 0; m < n_ops; ++m) {
+        const qs_cplx* K = ops + (size_t)m * d * d;
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b)
+                for (int a2 = 0; a2 < d; ++a2)
+                    for (int b2 = 0; b2 < d; ++b2) {
+                        const qs_cplx x = K[a * d + a2], y = K[b * d + b2];
+                        const size_t e = (size_t)(a + d * b) * D + (a2 + d * b2);
+                        S[2 * e] += x.re * y.re + x.im * y.im;
+                        S[2 * e + 1] += x.im * y.re - x.re * y.im;
+                    }
+    }
+    int vt[4];
+    for (int j = 0; j < n_targets; ++j) {
+        vt[j] = targets[j];
+        vt[n_targets + j] = targets[j] + r->n;
+    }
+    const void* dm = nullptr;
+    if ((s = upload_matrix(r, 0, S, &dm))) return s;
+    return group_launch(r, vt, 2 * n_targets, nullptr, 0, dm, QS_K_DM_CHANNEL);
+}
+
+qs_status qs_mix_kraus(qs_reg r, int target, const qs_cplx* ops, int n_ops)
+{
+    return qs_mix_multi_kraus(r, &target, 1, ops, n_ops);
+}
+
+qs_status qs_mix_two_qubit_kraus(qs_reg r, int target1, int target2, const qs_cplx* ops, int n_ops)
+{
+    const int t[2] = {target1, target2};
+    return qs_mix_multi_kraus(r, t, 2, ops, n_ops);
+}
+
+// ---- initialisation variants, copies, overlaps, checkpoints -----------------
+// Sec. II.B.1: the state is directly readable and writable; these calls
+// build common states and read overlaps without copying the state out.
+
+namespace {
+
+// Order `waiter`'s later work after everything already queued on `producer`.
+qs_status order_after(hipStream_t waiter, hipStream_t producer)
+{
+    if (waiter == producer) return QS_OK;
+    hipEvent_t ev;
+    QS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(ev, producer);
+    if (e == hipSuccess) e = hipStreamWaitEvent(waiter, ev, 0);
+    (void)hipEventDestroy(ev);
+    if (e != hipSuccess) return qs::hip_error(e, "stream ordering");
+    return QS_OK;
+}
+
+qs_status read_pair(qs_reg r, double out[2])
+{
+    const double* dev_out = r->scratch + 4 * qs::kReduceBlocks;
+    QS_HIP(hipMemcpyAsync(r->host_res, dev_out, 2 * sizeof(double), hipMemcpyDeviceToHost, r->stream));
+    qs_status s = sync_stream(r);
+    if (s) return s;
+    out[0] = r->host_res[0];
+    out[1] = r->host_res[1];
+    return QS_OK;
+}
+
+}  // namespace
+
+qs_status qs_init_plus(qs_reg r)
+{
+    QS_CHECK_REG(r);
+    // state vector: every amplitude 2^(-n/2); density matrix |+><+|: every entry 2^-N
+    const double v = r->kind == QS_DENSITY ? ldexp(1.0, -r->n) : 1.0 / sqrt(ldexp(1.0, r->n));
+    const qs::Launch L = launch_of(r);
+    const uint64_t len = 1ull << r->nbits;
+    return qs::profiled(r, QS_K_INIT, [&](int*) {
+        return r->prec == QS_C128 ? qs::launch_init_fill<double>(L, r->amp, len, v, 0.0)
+                                  : qs::launch_init_fill<float>(L, r->amp, len, v, 0.0);
+    });
+}
+
+qs_status qs_init_pure_state(qs_reg r, qs_reg pure)
+{
+    QS_CHECK_REG(r);
+    if (!valid_reg(pure)) return qs::set_error(QS_E_HANDLE, "invalid register handle (pure state)");
+    if (pure->kind != QS_STATEVEC) return qs::set_error(QS_E_KIND, "the pure state must be a state vector");
+    if (pure->n != r->n || pure->prec != r->prec || pure->env->device != r->env->device)
+        return qs::set_error(QS_E_ARG, "registers differ in qubits, precision or device");
+    if (pure == r) return QS_OK;
+    QS_HIP(hipSetDevice(r->env->device));
+    qs_status s = order_after(r->stream, pure->stream);
+    if (s) return s;
+    const qs::Launch L = launch_of(r);
+    if (r->kind == QS_STATEVEC) {
+        s = qs::profiled(r, QS_K_INIT, [&](int*) {
+            return hipMemcpyAsync(r->amp, pure->amp, r->bytes, hipMemcpyDeviceToDevice, r->stream);
+        });
+    } else {
+        s = qs::profiled(r, QS_K_INIT, [&](int*) {
+            return r->prec == QS_C128 ? qs::launch_dm_from_pure<double>(L, r->amp, r->n, pure->amp)
+                                      : qs::launch_dm_from_pure<float>(L, r->amp, r->n, pure->amp);
+        });
+    }
+    if (s) return s;
+    // later work on `pure` waits for this read
+    return order_after(pure->stream, r->stream);
+}
+
+qs_status qs_clone(qs_reg dst, qs_reg src)
+{
+    QS_CHECK_REG(dst);
+    if (!valid_reg(src)) return qs::set_error(QS_E_HANDLE, "invalid register handle (source)");
+    if (src->n != dst->n || src->kind != dst->kind || src->prec != dst->prec ||
+        src->env->device != dst->env->device)
+        return qs::set_error(QS_E_ARG, "registers differ in shape, precision or device");
+    if (src == dst) return QS_OK;
+    QS_HIP(hipSetDevice(dst->env->device));
+    qs_status s = order_after(dst->stream, src->stream);
+    if (s) return s;
+    s = qs::profiled(dst, QS_K_INIT, [&](int*) {
+        return hipMemcpyAsync(dst->amp, src->amp, dst->bytes, hipMemcpyDeviceToDevice, dst->stream);
+    });
+    if (s) return s;
+    return order_after(src->stream, dst->stream);
+}
+
+qs_status qs_calc_inner_product(qs_reg bra, qs_reg ket, qs_cplx* out)
+{
+    QS_CHECK_REG(bra);
+    if (!valid_reg(ket)) return qs::set_error(QS_E_HANDLE, "invalid register handle (ket)");
+    if (!out) return qs::set_error(QS_E_ARG, "NULL output");
+    if (bra->kind != QS_STATEVEC || ket->kind != QS_STATEVEC)
+        return qs::set_error(QS_E_KIND, "inner products need state vectors");
+    if (bra->n != ket->n || bra->prec != ket->prec || bra->env->device != ket->env->device)
+        return qs::set_error(QS_E_ARG, "registers differ in qubits, precision or device");
+    QS_HIP(hipSetDevice(bra->env->device));
+    qs_status s = order_after(bra->stream, ket->stream);
+    if (s) return s;
+    const qs::Launch L = launch_of(bra);
+    double* partials = bra->scratch;
+    double* dev_out = bra->scratch + 4 * qs::kReduceBlocks;
+    s = qs::profiled(bra, QS_K_REDUCE, [&](int*) {
+        return bra->prec == QS_C128
+                   ? qs::launch_inner_sv<double>(L, bra->amp, ket->amp, bra->nbits, partials, dev_out)
+                   : qs::launch_inner_sv<float>(L, bra->amp, ket->amp, bra->nbits, partials, dev_out);
+    });
+    if (s) return s;
+    double v[2];
+    if ((s = read_pair(bra, v))) return s;
+    out->re = v[0];
+    out->im = v[1];
+    return QS_OK;
+}
+
+qs_status qs_calc_purity(qs_reg r, double* out)
+{
+    QS_CHECK_REG(r);
+    if (!out) return qs::set_error(QS_E_ARG, "NULL output");
+    if (r->kind != QS_DENSITY) return qs::set_error(QS_E_KIND, "purity needs a density matrix");
+    // Tr(rho^2) = sum_{jk} rho_jk rho_kj = sum_{jk} |rho_jk|^2 for Hermitian
+    // rho: the squared norm of the Eq. 2 vector
+    const qs::Launch L = launch_of(r);
+    double* partials = r->scratch;
+    double* dev_out = r->scratch + 4 * qs::kReduceBlocks;
+    qs_status s = qs::profiled(r, QS_K_REDUCE, [&](int*) {
+        return r->prec == QS_C128 ? qs::launch_prob_sv<double>(L, r->amp, r->nbits, -1, partials, dev_out)
+                                  : qs::launch_prob_sv<float>(L, r->amp, r->nbits, -1, partials, dev_out);
+    });
+    if (s) return s;
+    double v[2];
+    if ((s = read_pair(r, v))) return s;
+    *out = v[0] + v[1];
+    return QS_OK;
+}
+
+qs_status qs_calc_fidelity(qs_reg r, qs_reg pure, double* out)
+{
+    QS_CHECK_REG(r);
+    if (!valid_reg(pure)) return qs::set_error(QS_E_HANDLE, "invalid register handle (pure state)");
+    if (!out) return qs::set_error(QS_E_ARG, "NULL output");
+    if (pure->kind != QS_STATEVEC) return qs::set_error(QS_E_KIND, "the pure state must be a state vector");
+    if (pure->n != r->n || pure->prec != r->prec || pure->env->device != r->env->device)
+        return qs::set_error(QS_E_ARG, "registers differ in qubits, precision or device");
+    if (r->kind == QS_STATEVEC) {
+        // |<pure|r>|^2
+        qs_cplx ip;
+        qs_status s = qs_calc_inner_product(pure, r, &ip);
+        if (s) return s;
+        *out = ip.re * ip.re + ip.im * ip.im;
+        return QS_OK;
+    }
+    QS_HIP(hipSetDevice(r->env->device));
+    qs_status s = order_after(r->stream, pure->stream);
+    if (s) return s;
+    const qs::Launch L = launch_of(r);
+    double* partials = r->scratch;
+    double* dev_out = r->scratch + 4 * qs::kReduceBlocks;
+    s = qs::profiled(r, QS_K_REDUCE, [&](int*) {
+        return r->prec == QS_C128 ? qs::launch_fid_dm<double>(L, r->amp, r->n, pure->amp, partials, dev_out)
+                                  : qs::launch_fid_dm<float>(L, r->amp, r->n, pure->amp, partials, dev_out);
+    });
+    if (s) return s;
+    double v[2];
+    if ((s = read_pair(r, v))) return s;
+    *out = v[0];
+    return QS_OK;
+}
+
+// Checkpoint file: a 64-byte header (magic "QSTATE01", then int32 n, kind,
+// prec, 0, uint64 amplitude count, 32 zero bytes) followed by the raw
+// amplitudes in the register's precision, little endian.
+namespace {
+
+constexpr char kCkptMagic[8] = {'Q', 'S', 'T', 'A', 'T', 'E', '0', '1'};
+constexpr size_t kCkptChunk = 64ull << 20;
+
+struct CkptHeader {
+    char magic[8];
+    int32_t n, kind, prec, zero;
+    uint64_t count;
+    uint8_t pad[32];
+};
+static_assert(sizeof(CkptHeader) == 64, "checkpoint header is 64 bytes");
+
+// Two pinned staging buffers: the copy of one chunk overlaps the file
+// transfer of the other.
+struct Staging {
+    void* buf[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    ~Staging()
+    {
+        for (int k = 0; k < 2; ++k) {
+            if (ev[k]) (void)hipEventDestroy(ev[k]);
+            if (buf[k]) (void)hipHostFree(buf[k]);
+        }
+    }
+    qs_status init(size_t bytes)
+    {
+        for (int k = 0; k < 2; ++k) {
+            if (hipHostMalloc(&buf[k], bytes, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                buf[k] = nullptr;
+                return qs::set_error(QS_E_OOM, "cannot allocate pinned staging");
+            }
+            QS_HIP(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming));
+        }
+        return QS_OK;
+    }
+};
+
+}  // namespace
+
+qs_status qs_save_state(qs_reg r, const char* path)
+{
+    QS_CHECK_REG(r);
+    if (!path) return qs::set_error(QS_E_ARG, "NULL path");
+    QS_HIP(hipSetDevice(r->env->device));
+    FILE* f = fopen(path, "wb");
+    if (!f) return qs::set_error(QS_E_ARG, std::string("cannot open ") + path + " for writing");
+    CkptHeader h;
+    memset(&h, 0, sizeof h);
+    memcpy(h.magic, kCkptMagic, 8);
+    h.n = r->n;
+    h.kind = r->kind;
+    h.prec = r->prec;
+    h.count = 1ull << r->nbits;
+    bool ok = fwrite(&h, sizeof h, 1, f) == 1;
+    Staging st;
+    const size_t chunk = std::min(kCkptChunk, r->bytes);
+    qs_status s = ok ? st.init(chunk) : qs::set_error(QS_E_ARG, "checkpoint write failed");
+    size_t pending = 0, pend_bytes = 0;
+    int k = 0;
+    for (size_t off = 0; !s && off < r->bytes; off += chunk, k ^= 1) {
+        const size_t nb = std::min(chunk, r->bytes - off);
+        hipError_t e = hipMemcpyAsync(st.buf[k], (const char*)r->amp + off, nb, hipMemcpyDeviceToHost, r->stream);
+        if (e == hipSuccess) e = hipEventRecord(st.ev[k], r->stream);
+        if (e != hipSuccess) {
+            s = qs::hip_error(e, "checkpoint copy");
+            break;
+        }
+        if (off > 0) {  // write the previous chunk while this one is copied
+            const int j = k ^ 1;
+            e = hipEventSynchronize(st.ev[j]);
+            if (e != hipSuccess) s = qs::hip_error(e, "checkpoint copy");
+            else if (fwrite(st.buf[j], 1, pend_bytes, f) != pend_bytes) s = qs::set_error(QS_E_ARG, "checkpoint write failed");
+        }
+        pending = 1;
+        pend_bytes = nb;
+    }
+    if (!s && pending) {
+        const int j = k ^ 1;
+        hipError_t e = hipEventSynchronize(st.ev[j]);
+        if (e != hipSuccess) s = qs::hip_error(e, "checkpoint copy");
+        else if (fwrite(st.buf[j], 1, pend_bytes, f) != pend_bytes) s = qs::set_error(QS_E_ARG, "checkpoint write failed");
+    }
+    if (fclose(f) != 0 && !s) s = qs::set_error(QS_E_ARG, "checkpoint close failed");
+    return s;
+}
+
+qs_status qs_load_state(qs_reg r, const char* path)
+{
+    QS_CHECK_REG(r);
+    if (!path) return qs::set_error(QS_E_ARG, "NULL path");
+    FILE* f = fopen(path, "rb");
+    if (!f) return qs::set_error(QS_E_ARG, std::string("cannot open ") + path);
+    CkptHeader h;
+    if (fread(&h, sizeof h, 1, f) != 1 || memcmp(h.magic, kCkptMagic, 8) != 0) {
+        fclose(f);
+        return qs::set_error(QS_E_ARG, "not a qstate checkpoint");
+    }
+    if (h.n != r->n || h.kind != r->kind || h.prec != r->prec || h.count != (1ull << r->nbits)) {
+        fclose(f);
+        return qs::set_error(QS_E_ARG, "checkpoint shape differs from the register");
+    }
+    fseek(f, 0, SEEK_END);
+    const long size = ftell(f);
+    if (size < 0 || (uint64_t)size != sizeof h + r->bytes) {
+        fclose(f);
+        return qs::set_error(QS_E_ARG, "checkpoint is truncated");
+    }
+    fseek(f, (long)sizeof h, SEEK_SET);
+    QS_HIP(hipSetDevice(r->env->device));
+    Staging st;
+    const size_t chunk = std::min(kCkptChunk, r->bytes);
+    qs_status s = st.init(chunk);
+    int k = 0;
+    bool used[2] = {false, false};
+    for (size_t off = 0; !s && off < r->bytes; off += chunk, k ^= 1) {
+        const size_t nb = std::min(chunk, r->bytes - off);
+        if (used[k]) {  // the copy out of this buffer must have finished
+            const hipError_t e = hipEventSynchronize(st.ev[k]);
+            if (e != hipSuccess) {
+                s = qs::hip_error(e, "checkpoint copy");
+                break;
+            }
+        }
+        if (fread(st.buf[k], 1, nb, f) != nb) {
+            s = qs::set_error(QS_E_ARG, "checkpoint read failed");
+            break;
+        }
+        hipError_t e = hipMemcpyAsync((char*)r->amp + off, st.buf[k], nb, hipMemcpyHostToDevice, r->stream);
+        if (e == hipSuccess) e = hipEventRecord(st.ev[k], r->stream);
+        if (e != hipSuccess) s = qs::hip_error(e, "checkpoint copy");
+        used[k] = true;
+    }
+    fclose(f);
+    // the staging buffers are freed on return: wait for the copies
+    const qs_status s2 = sync_stream(r);
+    return s ? s : s2;
 }
 
 }  // extern "C"

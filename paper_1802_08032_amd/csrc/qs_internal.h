@@ -68,6 +68,30 @@ template <typename T> hipError_t launch_collapse_sv(const Launch& L, void* amp, 
 template <typename T> hipError_t launch_collapse_dm(const Launch& L, void* rho, int N, int q,
                                                     int outcome, double scale);
 
+// Register scratch (device doubles): reduction partials, two results, then
+// two k-qubit matrices of up to 32 x 32 complex entries (a gate and its
+// conjugate, or a superoperator).
+constexpr int kScratchMatOff = 4 * kReduceBlocks + 8;
+constexpr int kScratchMatDoubles = 2 * 32 * 32 * 2;
+constexpr int kScratchDoubles = kScratchMatOff + kScratchMatDoubles;
+
+// --- k-qubit groups, initialisation variants, overlaps ---------------------
+// Replace every group of 2^k amplitudes (k = 1..5 targets; matrix index bit j
+// <-> targets[j]) whose control bits are all 1 by dev_m times it; dev_m is a
+// device array of 2^k x 2^k complex T pairs, row-major.
+template <typename T> hipError_t launch_group_gate(const Launch& L, void* amp, int nbits, const int* targets,
+                                                   int k, const int* ctrls, int nc, const T* dev_m);
+// Every amplitude set to (re, im).  Write-only.
+template <typename T> hipError_t launch_init_fill(const Launch& L, void* amp, uint64_t len, double re, double im);
+// rho = |psi><psi| in the Eq. 2 layout; psi holds 2^N amplitudes.
+template <typename T> hipError_t launch_dm_from_pure(const Launch& L, void* rho, int N, const void* psi);
+// dev_out = {Re, Im} of sum_i conj(a_i) b_i (compensated, in double).
+template <typename T> hipError_t launch_inner_sv(const Launch& L, const void* a, const void* b, int nbits,
+                                                 double* partials, double* dev_out);
+// dev_out = {Re, Im} of <psi| rho |psi> (compensated, in double).
+template <typename T> hipError_t launch_fid_dm(const Launch& L, const void* rho, int N, const void* psi,
+                                               double* partials, double* dev_out);
+
 // --- measure-all ----------------------------------------------------------
 // |alpha|^2 of the items j < 2^(nbits - shift) at index fixed + (j << shift),
 // summed per bin j mod 2^mbits (mbits <= 10) with compensated sums: dev_out

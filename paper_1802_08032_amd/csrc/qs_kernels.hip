@@ -674,6 +674,183 @@ __global__ __launch_bounds__(kBlock) void k_diag_dm(const typename C2<T>::type* 
         out[j] = (double)rho[j * (dim + 1)].x;
 }
 
+// ---------------------------------------------------------------------------
+// k-qubit groups.  Eq. 1 and the Eq. 2 identity hold for gates on several
+// qubits (Sec. II.B.1): a group is the D = 2^k amplitudes that agree on
+// every bit outside the target set, member r at base + the sum of
+// tbit[j] = 2^targets[j] over the set bits j of r; the group is replaced by
+// m times it (m: D x D complex, row-major, interleaved, read with uniform
+// loads).  `ins` inserts a 0 at every target and a 1 at every control.  One
+// thread holds one group and writes each output row as soon as it is formed
+// (all D inputs are already in registers).
+template <int K>
+struct GroupBits {
+    uint64_t tbit[K];
+};
+
+template <int K>
+__device__ __forceinline__ uint64_t group_off(const GroupBits<K>& gb, int r)
+{
+    uint64_t o = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if ((r >> j) & 1) o += gb.tbit[j];
+    return o;
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(kBlock) void k_group_gate(typename C2<T>::type* __restrict__ amp,
+                                                       uint64_t ngroups, BitInsert ins, GroupBits<K> gb,
+                                                       const T* __restrict__ m)
+{
+    using V = typename C2<T>::type;
+    constexpr int D = 1 << K;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x; g < ngroups; g += stride) {
+        const uint64_t b = expand(g, ins);
+        V x[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) x[j] = ldnt(amp + b + group_off<K>(gb, j));
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const T* row = m + 2 * D * i;
+            // one product or multiply-add per statement: every term is a
+            // fused multiply-add
+            T re = row[0] * x[0].x;
+            T im = row[0] * x[0].y;
+            re = -row[1] * x[0].y + re;
+            im = row[1] * x[0].x + im;
+#pragma unroll
+            for (int j = 1; j < D; ++j) {
+                re = row[2 * j] * x[j].x + re;
+                re = -row[2 * j + 1] * x[j].y + re;
+                im = row[2 * j] * x[j].y + im;
+                im = row[2 * j + 1] * x[j].x + im;
+            }
+            V y;
+            y.x = re;
+            y.y = im;
+            stnt(amp + b + group_off<K>(gb, i), y);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Every amplitude set to (re, im).  Write-only.
+template <typename T, int U>
+__global__ __launch_bounds__(kBlock) void k_init_fill(typename C2<T>::type* __restrict__ amp, uint64_t len,
+                                                      T re, T im)
+{
+    using V = typename C2<T>::type;
+    static_assert(U % 2 == 0, "the step order alternates two half-runs");
+    const uint64_t ps = (uint64_t)kBlock * U;
+    V v;
+    v.x = re;
+    v.y = im;
+    for (uint64_t s = blockIdx.x; step_base(s, ps) < len; s += gridDim.x) {
+        const uint64_t c = step_base(s, ps);
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t i = step_item(c, j, ps);
+            if (i < len) amp[i] = v;
+        }
+    }
+}
+
+// rho[j][k] = psi_j conj(psi_k) at vector index j + 2^N k (Eq. 2 layout).
+// Write-only on rho; psi (2^N amplitudes) is read through the caches.
+template <typename T, int U>
+__global__ __launch_bounds__(kBlock) void k_dm_from_pure(typename C2<T>::type* __restrict__ rho,
+                                                         const typename C2<T>::type* __restrict__ psi, int N)
+{
+    using V = typename C2<T>::type;
+    static_assert(U % 2 == 0, "the step order alternates two half-runs");
+    const uint64_t len = 1ull << (2 * N), low = (1ull << N) - 1;
+    const uint64_t ps = (uint64_t)kBlock * U;
+    for (uint64_t s = blockIdx.x; step_base(s, ps) < len; s += gridDim.x) {
+        const uint64_t c = step_base(s, ps);
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t i = step_item(c, j, ps);
+            if (i >= len) continue;
+            const V a = psi[i & low], b = psi[i >> N];
+            V v;  // a conj(b)
+            v.x = a.x * b.x + a.y * b.y;
+            v.y = a.y * b.x - a.x * b.y;
+            stnt(rho + i, v);
+        }
+    }
+}
+
+// sum_i conj(a_i) b_i: real part in the first compensated sum, imaginary
+// part in the second (products formed in double).
+template <typename T, int U>
+__global__ __launch_bounds__(kBlock) void k_inner_sv(const typename C2<T>::type* __restrict__ a,
+                                                     const typename C2<T>::type* __restrict__ b, uint64_t len,
+                                                     double* partials)
+{
+    static_assert(U % 2 == 0, "the step order alternates two half-runs");
+    using V = typename C2<T>::type;
+    NSum s0 = {0.0, 0.0}, s1 = {0.0, 0.0};
+    const uint64_t ps = (uint64_t)kBlock * U;
+    for (uint64_t s = blockIdx.x; step_base(s, ps) < len; s += gridDim.x) {
+        const uint64_t c = step_base(s, ps);
+        V x[U], y[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t i0 = step_item(c, j, ps);
+            const uint64_t i = i0 < len ? i0 : len - 1;
+            x[j] = ldnt(a + i);
+            y[j] = ldnt(b + i);
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const bool in = step_item(c, j, ps) < len;
+            const double xr = x[j].x, xi = x[j].y, yr = y[j].x, yi = y[j].y;
+            nadd(s0, in ? xr * yr + xi * yi : 0.0);
+            nadd(s1, in ? xr * yi - xi * yr : 0.0);
+        }
+    }
+    block_store2(s0, s1, partials);
+}
+
+// <psi| rho |psi> = sum_{j,k} conj(psi_j) rho[j][k] psi_k over the Eq. 2
+// vector (entry j + 2^N k): real part in the first sum, imaginary part (zero
+// for a Hermitian rho, up to rounding) in the second.
+template <typename T, int U>
+__global__ __launch_bounds__(kBlock) void k_fid_dm(const typename C2<T>::type* __restrict__ rho,
+                                                   const typename C2<T>::type* __restrict__ psi, int N,
+                                                   double* partials)
+{
+    static_assert(U % 2 == 0, "the step order alternates two half-runs");
+    using V = typename C2<T>::type;
+    NSum s0 = {0.0, 0.0}, s1 = {0.0, 0.0};
+    const uint64_t len = 1ull << (2 * N), low = (1ull << N) - 1;
+    const uint64_t ps = (uint64_t)kBlock * U;
+    for (uint64_t s = blockIdx.x; step_base(s, ps) < len; s += gridDim.x) {
+        const uint64_t c = step_base(s, ps);
+        V r[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t i0 = step_item(c, j, ps);
+            r[j] = ldnt(rho + (i0 < len ? i0 : len - 1));
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t i0 = step_item(c, j, ps);
+            const uint64_t i = i0 < len ? i0 : len - 1;
+            const V pj = psi[i & low], pk = psi[i >> N];
+            // t = conj(psi_j) rho psi_k, in double
+            const double ar = pj.x, ai = -(double)pj.y, rr = r[j].x, ri = r[j].y, br = pk.x, bi = pk.y;
+            const double ur = ar * rr - ai * ri, ui = ar * ri + ai * rr;
+            const bool in = i0 < len;
+            nadd(s0, in ? ur * br - ui * bi : 0.0);
+            nadd(s1, in ? ur * bi + ui * br : 0.0);
+        }
+    }
+    block_store2(s0, s1, partials);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -990,6 +1167,106 @@ hipError_t launch_collapse_dm(const Launch& L, void* rho, int N, int q, int outc
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_group_gate(const Launch& L, void* amp, int nbits, const int* targets, int k, const int* ctrls,
+                             int nc, const T* dev_m)
+{
+    using V = typename C2<T>::type;
+    int pos[64];
+    int np = 0;
+    uint64_t ones = 0;
+    for (int j = 0; j < k; ++j) pos[np++] = targets[j];
+    for (int j = 0; j < nc; ++j) {
+        pos[np++] = ctrls[j];
+        ones |= 1ull << ctrls[j];
+    }
+    const BitInsert ins = make_insert(pos, np, ones);
+    const uint64_t ngroups = 1ull << (nbits - np);
+    const int grid = grid_for(ngroups, 1);
+    switch (k) {
+#define QS_GROUP(KK) case KK: {                                                                        \
+        GroupBits<KK> gb;                                                                              \
+        for (int j = 0; j < KK; ++j) gb.tbit[j] = 1ull << targets[j];                                  \
+        hipLaunchKernelGGL((k_group_gate<T, KK>), dim3(grid), dim3(kBlock), 0, L.stream, (V*)amp, ngroups, \
+                           ins, gb, dev_m);                                                            \
+        break;                                                                                         \
+    }
+        QS_GROUP(1) QS_GROUP(2) QS_GROUP(3) QS_GROUP(4) QS_GROUP(5)
+#undef QS_GROUP
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_init_fill(const Launch& L, void* amp, uint64_t len, double re, double im)
+{
+    using V = typename C2<T>::type;
+    if (wide(len, kPer<T>))
+        hipLaunchKernelGGL((k_init_fill<T, kPer<T>>), dim3(grid_for(len, kPer<T>)), dim3(kBlock), 0, L.stream,
+                           (V*)amp, len, (T)re, (T)im);
+    else
+        hipLaunchKernelGGL((k_init_fill<T, kSmallPer>), dim3(grid_for(len, kSmallPer)), dim3(kBlock), 0,
+                           L.stream, (V*)amp, len, (T)re, (T)im);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dm_from_pure(const Launch& L, void* rho, int N, const void* psi)
+{
+    using V = typename C2<T>::type;
+    const uint64_t len = 1ull << (2 * N);
+    if (wide(len, kPer<T>))
+        hipLaunchKernelGGL((k_dm_from_pure<T, kPer<T>>), dim3(grid_for(len, kPer<T>)), dim3(kBlock), 0,
+                           L.stream, (V*)rho, (const V*)psi, N);
+    else
+        hipLaunchKernelGGL((k_dm_from_pure<T, kSmallPer>), dim3(grid_for(len, kSmallPer)), dim3(kBlock), 0,
+                           L.stream, (V*)rho, (const V*)psi, N);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_inner_sv(const Launch& L, const void* a, const void* b, int nbits, double* partials,
+                           double* dev_out)
+{
+    using V = typename C2<T>::type;
+    const uint64_t len = 1ull << nbits;
+    constexpr int U = kPer<T> / 2;  // two streams per step
+    int grid;
+    if (wide(len, U)) {
+        grid = std::min(grid_for(len, U), kReduceBlocks);
+        hipLaunchKernelGGL((k_inner_sv<T, U>), dim3(grid), dim3(kBlock), 0, L.stream, (const V*)a, (const V*)b,
+                           len, partials);
+    } else {
+        grid = std::min(grid_for(len, kSmallPer), kReduceBlocks);
+        hipLaunchKernelGGL((k_inner_sv<T, kSmallPer>), dim3(grid), dim3(kBlock), 0, L.stream, (const V*)a,
+                           (const V*)b, len, partials);
+    }
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, L.stream, partials, grid, dev_out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fid_dm(const Launch& L, const void* rho, int N, const void* psi, double* partials,
+                         double* dev_out)
+{
+    using V = typename C2<T>::type;
+    const uint64_t len = 1ull << (2 * N);
+    int grid;
+    if (wide(len, kPer<T>)) {
+        grid = std::min(grid_for(len, kPer<T>), kReduceBlocks);
+        hipLaunchKernelGGL((k_fid_dm<T, kPer<T>>), dim3(grid), dim3(kBlock), 0, L.stream, (const V*)rho,
+                           (const V*)psi, N, partials);
+    } else {
+        grid = std::min(grid_for(len, kSmallPer), kReduceBlocks);
+        hipLaunchKernelGGL((k_fid_dm<T, kSmallPer>), dim3(grid), dim3(kBlock), 0, L.stream, (const V*)rho,
+                           (const V*)psi, N, partials);
+    }
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, L.stream, partials, grid, dev_out);
+    return hipGetLastError();
+}
+
 #define QS_INSTANTIATE(T)                                                                              \
     template hipError_t launch_init_basis<T>(const Launch&, void*, uint64_t, uint64_t, double, double); \
     template hipError_t launch_hist_sv<T>(const Launch&, const void*, int, int, uint64_t, int, double*, int, \
@@ -1006,7 +1283,13 @@ hipError_t launch_collapse_dm(const Launch& L, void* rho, int N, int q, int outc
     template hipError_t launch_prob_half_sv<T>(const Launch&, const void*, int, int, int, double*, double*); \
     template hipError_t launch_prob_dm<T>(const Launch&, const void*, int, int, double*, double*);     \
     template hipError_t launch_collapse_sv<T>(const Launch&, void*, int, int, int, double);            \
-    template hipError_t launch_collapse_dm<T>(const Launch&, void*, int, int, int, double);
+    template hipError_t launch_collapse_dm<T>(const Launch&, void*, int, int, int, double); \
+    template hipError_t launch_group_gate<T>(const Launch&, void*, int, const int*, int, const int*, int, \
+                                             const T*);                                                \
+    template hipError_t launch_init_fill<T>(const Launch&, void*, uint64_t, double, double);           \
+    template hipError_t launch_dm_from_pure<T>(const Launch&, void*, int, const void*);                \
+    template hipError_t launch_inner_sv<T>(const Launch&, const void*, const void*, int, double*, double*); \
+    template hipError_t launch_fid_dm<T>(const Launch&, const void*, int, const void*, double*, double*);
 
 QS_INSTANTIATE(double)
 QS_INSTANTIATE(float)

@@ -24,7 +24,7 @@ KERNEL_CLASSES = ['init', 'gate', 'gate_low', 'not', 'phase', 'dm_gate', 'dm_cha
                   'collapse', 'fused']
 
 _STATUS = {0: 'QS_OK', -1: 'QS_E_ARG', -2: 'QS_E_KIND', -3: 'QS_E_OOM', -4: 'QS_E_DEVICE',
-           -5: 'QS_E_HANDLE', -6: 'QS_E_NOT_UNITARY'}
+           -5: 'QS_E_HANDLE', -6: 'QS_E_NOT_UNITARY', -7: 'QS_E_NOT_CPTP'}
 
 
 class QStateError(RuntimeError):
@@ -106,6 +106,19 @@ SIGNATURES = {
     'qs_batch_replay': (_i, [_vp]),
     'qs_batch_probs': (_i, [_vp, _i, _vp, _vp]),
     'qs_batch_info': (_i, [_vp, _PI, _PI, _PI]),
+    'qs_multi_qubit_unitary': (_i, [_vp, _vp, _i, _vp, _i, _vp]),
+    'qs_two_qubit_unitary': (_i, [_vp, _i, _i, _vp]),
+    'qs_mix_multi_kraus': (_i, [_vp, _vp, _i, _vp, _i]),
+    'qs_mix_kraus': (_i, [_vp, _i, _vp, _i]),
+    'qs_mix_two_qubit_kraus': (_i, [_vp, _i, _i, _vp, _i]),
+    'qs_init_plus': (_i, [_vp]),
+    'qs_init_pure_state': (_i, [_vp, _vp]),
+    'qs_clone': (_i, [_vp, _vp]),
+    'qs_calc_inner_product': (_i, [_vp, _vp, _vp]),
+    'qs_calc_purity': (_i, [_vp, _PD]),
+    'qs_calc_fidelity': (_i, [_vp, _vp, _PD]),
+    'qs_save_state': (_i, [_vp, C.c_char_p]),
+    'qs_load_state': (_i, [_vp, C.c_char_p]),
 }
 
 
@@ -139,6 +152,12 @@ def _ints(xs):
 def _mat(u):
     m = np.asarray(u, dtype=np.complex128).reshape(4)
     return (Cplx * 4)(*[Cplx(float(z.real), float(z.imag)) for z in m])
+
+
+def _cplx_array(a):
+    """Contiguous complex128 copy of `a` (passed as qs_cplx[]) and its size."""
+    m = np.ascontiguousarray(np.asarray(a, dtype=np.complex128).reshape(-1))
+    return m, m.size
 
 
 def philox_draws(seed: int, stream: int, first: int, count: int) -> np.ndarray:
@@ -303,6 +322,64 @@ class Register:
     def mix_damping(self, target: int, gamma: float):
         _check(lib().qs_mix_damping(self.h, target, float(gamma)))
 
+    def multi_qubit_unitary(self, targets, u, controls=()):
+        """Dense 2^k x 2^k unitary on targets (matrix index bit j <->
+        targets[j]), where every control is 1."""
+        t, k = _ints(targets)
+        c, nc = _ints(controls)
+        m, _ = _cplx_array(u)
+        _check(lib().qs_multi_qubit_unitary(self.h, c, nc, t, k, m.ctypes.data_as(C.c_void_p)))
+
+    def two_qubit_unitary(self, target1: int, target2: int, u):
+        m, _ = _cplx_array(u)
+        _check(lib().qs_two_qubit_unitary(self.h, target1, target2, m.ctypes.data_as(C.c_void_p)))
+
+    def mix_multi_kraus(self, targets, ops):
+        """Kraus map sum_m K rho K^dagger on 1 or 2 targets; ops: (m, d, d)."""
+        t, k = _ints(targets)
+        m, size = _cplx_array(ops)
+        d = 1 << k
+        _check(lib().qs_mix_multi_kraus(self.h, t, k, m.ctypes.data_as(C.c_void_p), size // (d * d)))
+
+    def mix_kraus(self, target: int, ops):
+        m, size = _cplx_array(ops)
+        _check(lib().qs_mix_kraus(self.h, target, m.ctypes.data_as(C.c_void_p), size // 4))
+
+    def mix_two_qubit_kraus(self, target1: int, target2: int, ops):
+        m, size = _cplx_array(ops)
+        _check(lib().qs_mix_two_qubit_kraus(self.h, target1, target2, m.ctypes.data_as(C.c_void_p), size // 16))
+
+    def init_plus(self):
+        _check(lib().qs_init_plus(self.h))
+
+    def init_pure_state(self, pure: 'Register'):
+        _check(lib().qs_init_pure_state(self.h, pure.h))
+
+    def clone_from(self, src: 'Register'):
+        _check(lib().qs_clone(self.h, src.h))
+
+    def calc_inner_product(self, ket: 'Register') -> complex:
+        """<self|ket>."""
+        out = (Cplx * 1)()
+        _check(lib().qs_calc_inner_product(self.h, ket.h, out))
+        return complex(out[0].re, out[0].im)
+
+    def calc_purity(self) -> float:
+        v = C.c_double()
+        _check(lib().qs_calc_purity(self.h, C.byref(v)))
+        return v.value
+
+    def calc_fidelity(self, pure: 'Register') -> float:
+        v = C.c_double()
+        _check(lib().qs_calc_fidelity(self.h, pure.h, C.byref(v)))
+        return v.value
+
+    def save_state(self, path: str):
+        _check(lib().qs_save_state(self.h, os.fsencode(path)))
+
+    def load_state(self, path: str):
+        _check(lib().qs_load_state(self.h, os.fsencode(path)))
+
     def apply(self, op):
         """Apply one workloads.Op."""
         if op.kind == 'u':
@@ -317,6 +394,10 @@ class Register:
             self.mix_depolarising(op.target, op.p)
         elif op.kind == 'damping':
             self.mix_damping(op.target, op.p)
+        elif op.kind == 'unitary':
+            self.multi_qubit_unitary(op.targets, op.u, op.controls)
+        elif op.kind == 'kraus':
+            self.mix_multi_kraus(op.targets, np.stack(op.kraus))
         else:
             raise ValueError(op.kind)
 
