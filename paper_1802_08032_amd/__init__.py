@@ -6,5 +6,5 @@ package is its thin Python binding.
 """
 from .qstate import (  # noqa: F401
     C64, C128, DAMPING, DENSITY, DEPHASING, DEPOLARISING, STATEVEC, Batch, Circuit, Env,
-    QStateError, Register, lib, philox_draws, reg_bytes,
+    QStateError, Register, lib, philox_draws, prob_noalloc, reg_bytes,
 )

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, 'csrc')
 OBJ = os.path.join(HERE, '_build')
 LIB = os.path.join(HERE, 'libqstate.so')
-SOURCES = ['qs_api.hip', 'qs_kernels.hip', 'qs_fused.hip', 'qs_plan.hip', 'qs_jit.hip']
+SOURCES = ['qs_api.hip', 'qs_kernels.hip', 'qs_fused.hip', 'qs_plan.hip', 'qs_jit.hip', 'qs_noalloc.hip']
 
 HIPCC = os.environ.get('HIPCC', '/opt/rocm/bin/hipcc')
 FLAGS = [

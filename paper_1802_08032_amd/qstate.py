@@ -119,6 +119,7 @@ SIGNATURES = {
     'qs_calc_fidelity': (_i, [_vp, _vp, _PD]),
     'qs_save_state': (_i, [_vp, C.c_char_p]),
     'qs_load_state': (_i, [_vp, C.c_char_p]),
+    'qs_prob_noalloc': (_i, [_i, _vp, _i, _i, _i, _i, _vp, _vp]),
 }
 
 
@@ -166,6 +167,15 @@ def philox_draws(seed: int, stream: int, first: int, count: int) -> np.ndarray:
     out = np.empty(max(count, 0), dtype=np.float64)  # the library rejects a negative count
     _check(lib().qs_philox_draws(seed & (2**64 - 1), stream & (2**64 - 1), first, count, out.ctypes.data_as(_PD)))
     return out
+
+
+def prob_noalloc(device: int, dev_amps: int, n: int, kind: int, prec: int, qubit: int, dev_out: int,
+                 stream: int = 0):
+    """qs_prob_noalloc: the probability reduction over caller-owned device
+    amplitudes, two doubles written to the device address dev_out; allocates
+    nothing (include/qstate_noalloc.h)."""
+    _check(lib().qs_prob_noalloc(device, C.c_void_p(dev_amps), n, kind, prec, qubit, C.c_void_p(dev_out),
+                                 C.c_void_p(stream)))
 
 
 def reg_bytes(n: int, kind: int = STATEVEC, prec: int = C128) -> int:

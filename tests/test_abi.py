@@ -1,5 +1,5 @@
 """CPU checks of the C-ABI library: it loads, exports every symbol that
-include/qstate.h declares, and its byte accounting follows the paper's
+include/*.h declare, and its byte accounting follows the paper's
 16 x 2^n B per double-precision state vector (Sec. II.B.1).  No kernels run."""
 import os
 import re
@@ -7,11 +7,11 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, 'include', 'qstate.h')
+INCLUDE = os.path.join(ROOT, 'include')
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = ''.join(open(os.path.join(INCLUDE, f)).read() for f in sorted(os.listdir(INCLUDE)) if f.endswith('.h'))
     text = re.sub(r'/\*.*?\*/', '', text, flags=re.S)
     return sorted(set(re.findall(r'\b(qs_[a-z0-9_]+)\s*\(', text)))
 
