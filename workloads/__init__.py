@@ -9,4 +9,5 @@ from .circuits import (  # noqa: F401
     Op, haar_unitary, layered_circuit, noisy_circuit, param_circuit,
     measurement_draws, gate_counts, product_layer, inverse, random_state,
     random_gate_ops, serving_requests, X, H, ry, rz, haar_unitary_k, random_kraus, random_multi_ops,
+    paper_random_circuit, SQRT_X, SQRT_Y,
 )

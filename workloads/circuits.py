@@ -13,6 +13,9 @@ workloads below keep that shape with rules of their own:
   and amplitude damping, in that order.
 * ``param_circuit``    -- per layer RY(theta) then RZ(phi) on every qubit with
   angles uniform in [0, 2 pi), then a CZ ladder on (q, q+1).
+* ``paper_random_circuit`` -- the paper's gate set {H, T, CZ, X^1/2, Y^1/2}
+  on a fixed linear topology (see its docstring); its gate count for 30
+  qubits at depth 100 is the one the paper prints.
 
 Everything is drawn from ``numpy.random.Generator(PCG64(seed))`` so that the
 oracle and the GPU path receive identical gate lists.  Measurement draws use
@@ -29,6 +32,11 @@ import numpy as np
 # into the bit=r amplitude, as in Eq. 1).
 X = np.array([[0, 1], [1, 0]], dtype=np.complex128)
 H = np.array([[1, 1], [1, -1]], dtype=np.complex128) / math.sqrt(2.0)
+
+
+# square roots of X and Y (their squares are X and Y)
+SQRT_X = np.array([[1 + 1j, 1 - 1j], [1 - 1j, 1 + 1j]], dtype=np.complex128) / 2.0
+SQRT_Y = np.array([[1 + 1j, -1 - 1j], [1 + 1j, 1 + 1j]], dtype=np.complex128) / 2.0
 
 
 def ry(theta: float) -> np.ndarray:
@@ -274,3 +282,46 @@ def serving_requests(count: int, rate: float, seed: int = 7, sv_range=(12, 30), 
         out.append({'rid': rid, 'density': dm, 'n': n, 'depth': depth, 'family': family, 'ops': ops,
                     'arrival': t, 'draws': measurement_draws(seed, rid, n)})
     return out
+
+
+def paper_random_circuit(n: int, depth: int, seed: int) -> list[Op]:
+    """Random circuit over the paper's gate set {H, T, CZ, X^1/2, Y^1/2}
+    (Sec. II.C): a fixed topology for given (n, depth) and a random sequence
+    of single-qubit gates.
+
+    * Cycle 0 puts H on every qubit.
+    * Cycle c = 1..depth applies CZ on the nearest-neighbour pairs (q, q+1)
+      with q = (c - 1) mod 3, (c - 1) mod 3 + 3, ... (three pair classes in
+      turn, so each qubit meets both neighbours).
+    * In the same cycle every qubit that was in a CZ in the previous cycle
+      and is not in one now gets a single-qubit gate: T if its only earlier
+      single-qubit gate is the initial H, else one of {T, X^1/2, Y^1/2}
+      drawn uniformly among those differing from its previous gate.
+
+    At 30 qubits and depth 100 this gives 1020 single-qubit and 967 CZ gates,
+    the counts the paper states for that size.  T is diag(1, e^(i pi/4)) and
+    CZ a phase of pi on |11>, both written as phase ops."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ops: list[Op] = [Op('u', target=q, u=H) for q in range(n)]
+    last = ['h'] * n
+    busy_prev: set = set()
+    for c in range(depth):
+        pairs = [(q, q + 1) for q in range(c % 3, n - 1, 3)]
+        busy = {q for p in pairs for q in p}
+        for q in range(n):
+            if q not in busy_prev or q in busy:
+                continue
+            if last[q] == 'h':
+                g = 't'
+            else:
+                choices = [k for k in ('t', 'sx', 'sy') if k != last[q]]
+                g = choices[int(rng.integers(0, len(choices)))]
+            if g == 't':
+                ops.append(Op('phase', qubits=(q,), angle=math.pi / 4.0, target=q))
+            else:
+                ops.append(Op('u', target=q, u=SQRT_X if g == 'sx' else SQRT_Y))
+            last[q] = g
+        for a, b in pairs:
+            ops.append(Op('phase', qubits=(a, b), angle=math.pi, controls=(a,), target=b))
+        busy_prev = busy
+    return ops
