@@ -352,6 +352,15 @@ qs_status qs_circuit_run_tiled(qs_reg r, qs_circuit c, int tile_qubits, int thre
  * qubit; tile_qubits then counts vector qubits (at most 2N). */
 qs_status qs_circuit_run_compiled(qs_reg r, qs_circuit c, int tile_qubits, int thread_bits,
                                   int max_phases, int contig_qubits, int* n_passes);
+/* qs_circuit_run_compiled starting from the basis state |basis_index>
+ * (|j><j| for a density matrix): the first pass forms its tiles of that
+ * state instead of reading the register, so the initialisation costs no
+ * separate write pass and the first pass no read.  For an empty circuit
+ * the register is simply set to the basis state.  QS_E_ARG for an index
+ * outside [0, 2^n). */
+qs_status qs_circuit_run_compiled_from_basis(qs_reg r, qs_circuit c, int tile_qubits, int thread_bits,
+                                             int max_phases, int contig_qubits, uint64_t basis_index,
+                                             int* n_passes);
 /* Host-only: the generated HIP source of pass `pass` for an n-qubit
  * register of kind `kind` and precision `prec` (copied into buf,
  * NUL-terminated, truncated to cap - 1 bytes; *len gets the full length,

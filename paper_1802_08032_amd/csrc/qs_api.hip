@@ -1179,6 +1179,19 @@ qs_status qs_circuit_run_compiled(qs_reg r, qs_circuit c, int tile_qubits, int t
     return qs::run_compiled_sv(r, c, cfg, n_passes);
 }
 
+qs_status qs_circuit_run_compiled_from_basis(qs_reg r, qs_circuit c, int tile_qubits, int thread_bits,
+                                             int max_phases, int contig_qubits, uint64_t basis_index,
+                                             int* n_passes)
+{
+    qs_status s = circuit_check(r, c);
+    if (s) return s;
+    if ((s = check_compiled_shape(r->prec, r->nbits, tile_qubits, thread_bits, max_phases, contig_qubits))) return s;
+    if (r->n < 64 && basis_index >= (1ull << r->n)) return qs::set_error(QS_E_ARG, "basis index out of range");
+    qs::FusedConfig cfg{thread_bits, tile_qubits - thread_bits, max_phases};
+    cfg.contig = contig_qubits ? contig_qubits : std::min(6, r->nbits);
+    return qs::run_compiled_sv(r, c, cfg, n_passes, &basis_index);
+}
+
 qs_status qs_circuit_source(qs_circuit c, int n, int kind, int prec, int tile_qubits, int thread_bits,
                             int max_phases, int contig_qubits, int pass, char* buf, size_t cap, size_t* len,
                             int* n_passes)

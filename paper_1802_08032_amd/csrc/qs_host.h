@@ -152,7 +152,10 @@ qs_status batch_update(qs_batch_s* b);
 // qubit are merged into one 4x4 (qs_plan.hip).
 std::vector<OpRec> dm_vector_ops(const std::vector<OpRec>& ops, int N);
 // Run-time compiled passes (qs_jit.hip).
-qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passes);
+// init_index != nullptr: the first pass forms the basis state |*init_index>
+// (|j><j| for a density matrix) instead of reading the register.
+qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passes,
+                          const uint64_t* init_index = nullptr);
 qs_status generate_sources(const std::vector<OpRec>& ops, int n, int kind, int prec, FusedConfig cfg,
                            std::vector<std::string>& out);
 // Per-operation execution of one recorded op (qs_api.hip).

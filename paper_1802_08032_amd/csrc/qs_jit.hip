@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <complex>
 #include <memory>
 #include <mutex>
 #include <sstream>
@@ -131,19 +132,74 @@ __device__ __forceinline__ void qs_cm(R fr, R fi, V& a)
     r.y = fr * a.y + fi * a.x;
     a = r;
 }
+// Unit-diagonal core of a dense gate: (a, b) <- (a + k b, b - conj(k) a),
+// k = kr + i ki; two multiply-adds per output component.
+__device__ __forceinline__ void qs_core(R kr, R ki, V& a, V& b)
+{
+    V na, nb;
+    na.x = kr * b.x + a.x;
+    na.x = -ki * b.y + na.x;
+    na.y = kr * b.y + a.y;
+    na.y = ki * b.x + na.y;
+    nb.x = -kr * a.x + b.x;
+    nb.x = -ki * a.y + nb.x;
+    nb.y = -kr * a.y + b.y;
+    nb.y = ki * a.x + nb.y;
+    a = na;
+    b = nb;
+}
+// Amplitude i of the basis state |idx>.
+__device__ __forceinline__ V qs_basis(unsigned long long i, unsigned long long idx)
+{
+    V v;
+    v.x = i == idx ? (R)1 : (R)0;
+    v.y = (R)0;
+    return v;
+}
 )";
 
-GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB, bool dbl)
+using Cx = std::complex<double>;
+
+// A dense 2x2 gate U (row-major) written as diag(d0, d1) times a core with
+// unit diagonal: form 2 keeps the amplitudes in place,
+//   U = diag(u00, u11) [[1, k], [-conj(k), 1]],  k = u01 / u00,
+// form 3 exchanges them,
+//   U = diag(u01, u10) [[k, 1], [1, -conj(k)]],  k = u00 / u01,
+// whichever has |k| <= 1.  Form 0: U is diagonal; form 1: anti-diagonal
+// (a pure exchange).  Both identities need U unitary (u10 = -u11 conj(k),
+// resp. u11 = -u10 conj(k)); form -1 when that fails by more than 1e-14.
+struct CoreForm {
+    int form;
+    Cx k, d0, d1;
+};
+
+CoreForm core_form(const Cx (&u)[2][2])
+{
+    if (u[0][1] == 0.0 && u[1][0] == 0.0) return {0, 0.0, u[0][0], u[1][1]};
+    if (u[0][0] == 0.0 && u[1][1] == 0.0) return {1, 0.0, u[0][1], u[1][0]};
+    if (std::abs(u[0][0]) >= std::abs(u[0][1])) {
+        const Cx k = u[0][1] / u[0][0];
+        if (std::abs(u[1][0] + u[1][1] * std::conj(k)) > 1e-14) return {-1, 0.0, 0.0, 0.0};
+        return {2, k, u[0][0], u[1][1]};
+    }
+    const Cx k = u[0][0] / u[0][1];
+    if (std::abs(u[1][1] + u[1][0] * std::conj(k)) > 1e-14) return {-1, 0.0, 0.0, 0.0};
+    return {3, k, u[0][1], u[1][0]};
+}
+
+GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB, bool dbl, bool init)
 {
     const int K = TB + RB, E = 1 << RB;
     GenOut g;
-    std::ostringstream s;
-    s << (dbl ? "typedef double R;\ntypedef double2 V;\n" : "typedef float R;\ntypedef float2 V;\n");
-    s << kPrelude;
-    s << "extern \"C\" __global__ void __launch_bounds__(" << (1 << TB)
-      << ") qs_pass(V* __restrict__ amp, const R* __restrict__ mats, unsigned long long ntiles)\n{\n";
-    s << "    __shared__ V lds[" << (1 << K) << "];\n";
-    s << "    const unsigned tid = threadIdx.x;\n";
+    std::ostringstream s;     // loop body: the ops
+    std::ostringstream head;  // kernel header and prologue
+    head << (dbl ? "typedef double R;\ntypedef double2 V;\n" : "typedef float R;\ntypedef float2 V;\n");
+    head << kPrelude;
+    head << "extern \"C\" __global__ void __launch_bounds__(" << (1 << TB)
+         << ") qs_pass(V* __restrict__ amp, const R* __restrict__ mats, unsigned long long ntiles"
+         << (init ? ", unsigned long long init_index" : "") << ")\n{\n";
+    head << "    __shared__ V lds[" << (1 << K) << "];\n";
+    head << "    const unsigned tid = threadIdx.x;\n";
 
     std::vector<int> local(64, -1);
     for (int j = 0; j < K; ++j) local[P.S[j]] = j;
@@ -155,10 +211,9 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     };
     std::vector<uint64_t> ldthr, ldreg, stthr, streg;
     global_imgs(P.phases.front().lay, ldthr, ldreg);
-    (void)K;
     global_imgs(P.store, stthr, streg);
-    s << "    const unsigned long long ldt = " << tid_expr(ldthr, false, true) << ";\n";
-    s << "    const unsigned long long stt = " << tid_expr(stthr, false, true) << ";\n";
+    head << "    const unsigned long long ldt = " << tid_expr(ldthr, false, true) << ";\n";
+    head << "    const unsigned long long stt = " << tid_expr(stthr, false, true) << ";\n";
 
     // re-layout transitions: (from, to) pairs, including the final one
     struct Trans {
@@ -177,24 +232,10 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
         std::vector<uint64_t> wi, ri;
         for (int b = 0; b < TB; ++b) wi.push_back(trans[t].img[trans[t].from->thr[b]]);
         for (int b = 0; b < TB; ++b) ri.push_back(trans[t].img[trans[t].to->thr[b]]);
-        s << "    const unsigned tw" << t << " = " << tid_expr(wi, true, false) << ";\n";
-        s << "    const unsigned tr" << t << " = " << tid_expr(ri, true, false) << ";\n";
+        head << "    const unsigned tw" << t << " = " << tid_expr(wi, true, false) << ";\n";
+        head << "    const unsigned tr" << t << " = " << tid_expr(ri, true, false) << ";\n";
     }
 
-    // Tile loop with a one-tile prefetch: tile t + gridDim.x is loaded while
-    // tile t is computed.  The matrix pointer is made to depend
-    // on the tile (the added term is always 0) so that the scalar matrix loads
-    // stay in the loop instead of being hoisted out of it.
-    s << "    unsigned long long tile = blockIdx.x;\n";
-    s << "    if (tile >= ntiles) return;\n";
-    s << "    auto ins = [](unsigned long long t) -> unsigned long long {\n";
-    s << "        unsigned long long b = t;\n";
-    for (int j = 0; j < K; ++j) {
-        const int p = P.S[j];
-        s << "        b = ((b >> " << p << ") << " << (p + 1) << ") | (b & " << hex64((1ull << p) - 1) << ");\n";
-    }
-    s << "        return b;\n    };\n";
-    s << "    unsigned long long base = ins(tile);\n";
     auto reg_off = [&](const std::vector<uint64_t>& img, int r, bool use_xor) {
         uint64_t o = 0;
         for (int b = 0; b < RB; ++b)
@@ -202,28 +243,12 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
         return o;
     };
     // Amplitudes stream through once per pass, so loads and stores are
-    // marked non-temporal.
+    // marked non-temporal.  The first pass of a run that starts from a basis
+    // state forms its tiles instead of reading them.
     auto ld = [&](const std::string& bvar, int r) {
-        return "qs_ldnt(&amp[" + bvar + " + ldt + " + hex64(reg_off(ldreg, r, false)) + "])";
+        const std::string at = bvar + " + ldt + " + hex64(reg_off(ldreg, r, false));
+        return init ? "qs_basis(" + at + ", init_index)" : "qs_ldnt(&amp[" + at + "])";
     };
-    for (int r = 0; r < E; ++r) s << "    V v" << r << " = " << ld("base", r) << ";\n";
-    // Drain the first tile's loads before the loop.  The compiler's wait
-    // analysis merges the loop entry with the back edge; with these loads
-    // still pending at the entry it makes every iteration wait for the loads
-    // of the next tile before computing the current one.
-    s << "    __builtin_amdgcn_s_waitcnt(0x0F70);\n";
-    s << "    for (;;) {\n";
-    // z is always 0; LDS addresses derived from it are computed in the loop
-    // next to their use instead of being hoisted and held in registers.
-    s << "        const unsigned z = (unsigned)(tile >> 62);\n";
-    s << "        const R* mt = mats + z;\n";
-    s << "        const unsigned long long ntile = tile + gridDim.x;\n";
-    s << "        const bool more = ntile < ntiles;\n";
-    for (int r = 0; r < E; ++r) s << "        V n" << r << ";\n";
-    s << "        if (more) {\n";
-    s << "            const unsigned long long nb = ins(ntile);\n";
-    for (int r = 0; r < E; ++r) s << "            n" << r << " = " << ld("nb", r) << ";\n";
-    s << "        }\n";
 
     std::vector<int> name(E);
     for (int r = 0; r < E; ++r) name[r] = r;
@@ -238,6 +263,19 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     // control or as a target of a 4x4 or phase.
     std::vector<std::string> pend(RB);
     int nflip = 0;
+
+    // Deferred diagonal factors: the true state is gsc times
+    // prod_j exp(i phi[j] x_j) times what the registers hold (x_j: the bit of
+    // tile qubit j).  A dense gate's diagonal part, a one-qubit phase and the
+    // phase a NOT moves around all land here; the next dense op on qubit j
+    // takes exp(i phi[j] x_j) into its matrix on the host, and whatever is
+    // left is multiplied in once before the tile is stored.  A register bit
+    // with a pending flip never carries a phase (has_phi false).
+    std::vector<double> phi(K, 0.0);
+    std::vector<bool> has_phi(K, false);
+    Cx gsc(1.0, 0.0);
+    bool any_deferred = false;
+
     auto materialize = [&](uint32_t bits) {
         for (int b = 0; b < RB; ++b) {
             if (!((bits >> b) & 1) || pend[b].empty()) continue;
@@ -252,6 +290,26 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
             s << "        }\n";
             pend[b].clear();
         }
+    };
+    // multiply the registers at positions `regs` by the constant f
+    auto mul_regs = [&](const std::vector<int>& regs, Cx f) {
+        if (regs.empty()) return;
+        const size_t off = g.mats.size();
+        g.mats.push_back(f.real());
+        g.mats.push_back(f.imag());
+        s << "        { const R fr = mt[" << off << "], fi = mt[" << off + 1 << "];";
+        for (int r : regs) s << " qs_cm(fr, fi, " << vn(r) << ");";
+        s << " }\n";
+    };
+    // apply the deferred phase of tile qubit j, held at register bit b
+    auto flush_phase = [&](int j, int b) {
+        if (!has_phi[j]) return;
+        std::vector<int> regs;
+        for (int r = 0; r < E; ++r)
+            if ((r >> b) & 1) regs.push_back(r);
+        mul_regs(regs, std::polar(1.0, phi[j]));
+        phi[j] = 0.0;
+        has_phi[j] = false;
     };
     auto flip_expr = [&](const std::vector<uint64_t>& img, bool wide) {
         std::string e;
@@ -304,6 +362,11 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     for (size_t ph = 0; ph < P.phases.size(); ++ph) {
         const Layout& L = P.phases[ph].lay;
         if (ph > 0) emit_relayout(tcount++);
+        auto reg_bit = [&](int j) {
+            for (int b = 0; b < RB; ++b)
+                if (L.reg[b] == j) return b;
+            return -1;
+        };
         for (int idx : P.phases[ph].ops) {
             const OpRec& op = all[idx];
             uint32_t rmask = 0, tmask = 0;
@@ -326,6 +389,16 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
                     }
             };
             for (int q : op.ctrls) classify(q);
+            // a one-qubit phase on a tile qubit is deferred (no code)
+            if (op.kind == 2 && op.ctrls.size() == 1 && local[op.ctrls[0]] >= 0) {
+                const int j = local[op.ctrls[0]], b = reg_bit(j);
+                if (b < 0 || pend[b].empty()) {
+                    phi[j] += op.angle;
+                    has_phi[j] = true;
+                    any_deferred = true;
+                    continue;
+                }
+            }
             std::string cond;
             if (gmask) cond = "((base & " + hex64(gmask) + ") == " + hex64(gmask) + ")";
             if (tmask) {
@@ -345,34 +418,63 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
                 continue;
             }
             if (op.kind == 4) {  // 4x4 on two register bits
-                int b1 = -1, b2 = -1;
-                for (int k = 0; k < RB; ++k) {
-                    if (L.reg[k] == local[op.target]) b1 = k;
-                    if (L.reg[k] == local[op.target2]) b2 = k;
-                }
+                const int j1 = local[op.target], j2 = local[op.target2];
+                const int b1 = reg_bit(j1), b2 = reg_bit(j2);
                 materialize((1u << b1) | (1u << b2));
-                for (int k = 0; k < 32; ++k) g.mats.push_back(op.m4[k]);
+                // deferred phases of both qubits go into the columns
+                Cx dcol[4];
+                for (int c = 0; c < 4; ++c)
+                    dcol[c] = std::polar(1.0, ((c & 1) && has_phi[j1] ? phi[j1] : 0.0) +
+                                                  ((c & 2) && has_phi[j2] ? phi[j2] : 0.0));
+                const bool deferred = has_phi[j1] || has_phi[j2];
+                for (int k = 0; k < 16; ++k) {
+                    const Cx m = Cx(op.m4[2 * k], op.m4[2 * k + 1]) * dcol[k % 4];
+                    g.mats.push_back(m.real());
+                    g.mats.push_back(m.imag());
+                }
+                phi[j1] = phi[j2] = 0.0;
+                has_phi[j1] = has_phi[j2] = false;
+                const size_t doff = g.mats.size();
+                if (deferred)
+                    for (int c = 0; c < 4; ++c) {
+                        g.mats.push_back(dcol[c].real());
+                        g.mats.push_back(dcol[c].imag());
+                    }
                 s << "        {\n            R m[32];\n";
                 for (int k = 0; k < 32; ++k) s << "            m[" << k << "] = mt[" << off + k << "];\n";
                 if (!cond.empty()) {
+                    // lanes the condition excludes keep only the deferred diagonal
                     s << "            const bool c = " << cond << ";\n";
                     for (int k = 0; k < 32; ++k) {
-                        const bool diag = (k % 2 == 0) && ((k / 2) % 5 == 0);
-                        s << "            m[" << k << "] = c ? m[" << k << "] : (R)" << (diag ? 1 : 0) << ";\n";
+                        const int e = k / 2, rr = e / 4, cc = e % 4;
+                        if (rr == cc && deferred)
+                            s << "            m[" << k << "] = c ? m[" << k << "] : mt[" << doff + 2 * cc + (k & 1)
+                              << "];\n";
+                        else
+                            s << "            m[" << k << "] = c ? m[" << k << "] : (R)"
+                              << ((rr == cc && k % 2 == 0) ? 1 : 0) << ";\n";
                     }
                 }
                 for (int r0 = 0; r0 < E; ++r0) {
                     if (((r0 >> b1) & 1) || ((r0 >> b2) & 1)) continue;
-                    if (((uint32_t)r0 & rmask) != rmask) continue;
+                    if (((uint32_t)r0 & rmask) != rmask) {
+                        // registers the controls exclude keep only the deferred diagonal
+                        if (deferred)
+                            for (int c = 1; c < 4; ++c) {
+                                const int r = r0 | ((c & 1) << b1) | ((c >> 1) << b2);
+                                s << "            qs_cm(mt[" << doff + 2 * c << "], mt[" << doff + 2 * c + 1 << "], "
+                                  << vn(r) << ");\n";
+                            }
+                        continue;
+                    }
                     s << "            qs_ap4(m, " << vn(r0) << ", " << vn(r0 | (1 << b1)) << ", " << vn(r0 | (1 << b2))
                       << ", " << vn(r0 | (1 << b1) | (1 << b2)) << ");\n";
                 }
                 s << "        }\n";
                 continue;
             }
-            int b = -1;
-            for (int k = 0; k < RB; ++k)
-                if (L.reg[k] == local[op.target]) b = k;
+            const int j = local[op.target];
+            const int b = reg_bit(j);
             if (op.kind == 1) {  // NOT
                 if (cond.empty()) {
                     // a permutation of register names (a pending flip on b commutes with it)
@@ -381,7 +483,34 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
                         if (((uint32_t)r0 & rmask) != rmask) continue;
                         std::swap(name[r0], name[r0 | (1 << b)]);
                     }
-                } else if (rmask == 0) {
+                    if (!has_phi[j]) continue;
+                    // the stored state went through X where the controls are
+                    // set; keep exp(i phi x_t) deferred for every register:
+                    // X exp(i phi x_t) = exp(i phi) exp(-i phi x_t) X
+                    const double a = phi[j];
+                    if (rmask == 0) {
+                        gsc *= std::polar(1.0, a);
+                        phi[j] = -a;
+                    } else if (__builtin_popcount(rmask) == 1) {
+                        // exp(i a (x_t xor x_c)) = exp(i a x_t) exp(i a x_c) exp(-2 i a x_t x_c)
+                        const int bc = __builtin_ctz(rmask), jc = L.reg[bc];
+                        phi[jc] += a;
+                        has_phi[jc] = true;
+                        std::vector<int> regs;
+                        for (int r = 0; r < E; ++r)
+                            if (((r >> b) & 1) && ((r >> bc) & 1)) regs.push_back(r);
+                        mul_regs(regs, std::polar(1.0, -2.0 * a));
+                    } else {
+                        std::vector<int> r0s, r1s;
+                        for (int r = 0; r < E; ++r)
+                            if (((uint32_t)r & rmask) == rmask) (((r >> b) & 1) ? r1s : r0s).push_back(r);
+                        mul_regs(r0s, std::polar(1.0, a));
+                        mul_regs(r1s, std::polar(1.0, -a));
+                    }
+                    continue;
+                }
+                flush_phase(j, b);  // a conditional exchange cannot keep a deferred phase
+                if (rmask == 0) {
                     const std::string f = "f" + std::to_string(nflip++);
                     s << "        const bool " << f << " = " << (pend[b].empty() ? "" : "(" + pend[b] + ") != ") << "("
                       << cond << ");\n";
@@ -400,13 +529,64 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
                 }
                 continue;
             }
-            for (int k = 0; k < 8; ++k) g.mats.push_back(op.u[k]);
+            // dense 2x2; the deferred phase of the target goes into column 1
+            Cx u[2][2];
+            for (int i = 0; i < 2; ++i)
+                for (int c = 0; c < 2; ++c) u[i][c] = Cx(op.u[2 * (2 * i + c)], op.u[2 * (2 * i + c) + 1]);
+            const double pj = has_phi[j] ? phi[j] : 0.0;
+            const bool deferred = has_phi[j];
+            if (deferred) {
+                u[0][1] *= std::polar(1.0, pj);
+                u[1][1] *= std::polar(1.0, pj);
+            }
+            if (cond.empty() && rmask == 0 && pend[b].empty()) {
+                const CoreForm cf = core_form(u);
+                if (cf.form >= 0) {
+                    if (cf.form == 2 || cf.form == 3) {
+                        g.mats.push_back(cf.k.real());
+                        g.mats.push_back(cf.k.imag());
+                        s << "        { const R kr = mt[" << off << "], ki = mt[" << off + 1 << "];";
+                    }
+                    for (int r0 = 0; r0 < E; ++r0) {
+                        if ((r0 >> b) & 1) continue;
+                        const int r1 = r0 | (1 << b);
+                        if (cf.form == 2) s << " qs_core(kr, ki, " << vn(r0) << ", " << vn(r1) << ");";
+                        if (cf.form == 3) s << " qs_core(kr, ki, " << vn(r1) << ", " << vn(r0) << ");";
+                        if (cf.form == 1 || cf.form == 3) std::swap(name[r0], name[r1]);
+                    }
+                    if (cf.form == 2 || cf.form == 3) s << " }\n";
+                    gsc *= cf.d0;
+                    phi[j] = std::arg(cf.d1 / cf.d0);
+                    has_phi[j] = true;
+                    any_deferred = true;
+                    continue;
+                }
+            }
+            // full matrix: lanes or registers the controls exclude keep only
+            // the deferred phase of the target
+            phi[j] = 0.0;
+            has_phi[j] = false;
+            for (int i = 0; i < 2; ++i)
+                for (int c = 0; c < 2; ++c) {
+                    g.mats.push_back(u[i][c].real());
+                    g.mats.push_back(u[i][c].imag());
+                }
+            const Cx ep = std::polar(1.0, pj);
+            if (deferred) {
+                g.mats.push_back(ep.real());
+                g.mats.push_back(ep.imag());
+            }
             s << "        {\n            R m[8];\n";
             for (int k = 0; k < 8; ++k) s << "            m[" << k << "] = mt[" << off + k << "];\n";
             if (!cond.empty()) {
                 s << "            const bool c = " << cond << ";\n";
-                for (int k = 0; k < 8; ++k)
-                    s << "            m[" << k << "] = c ? m[" << k << "] : (R)" << ((k == 0 || k == 6) ? 1 : 0) << ";\n";
+                for (int k = 0; k < 8; ++k) {
+                    if (deferred && (k == 6 || k == 7))
+                        s << "            m[" << k << "] = c ? m[" << k << "] : mt[" << off + 8 + (k - 6) << "];\n";
+                    else
+                        s << "            m[" << k << "] = c ? m[" << k << "] : (R)" << ((k == 0 || k == 6) ? 1 : 0)
+                          << ";\n";
+                }
             }
             if (!pend[b].empty()) {
                 // flipped lanes apply X U X: rows and columns exchanged
@@ -416,10 +596,15 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
             }
             // a diagonal matrix (u01 = u10 = 0, e.g. a Z rotation) multiplies
             // each amplitude of the pair by its own entry: half the work
-            const bool diag = op.u[2] == 0.0 && op.u[3] == 0.0 && op.u[4] == 0.0 && op.u[5] == 0.0;
+            const bool diag = u[0][1] == 0.0 && u[1][0] == 0.0;
             for (int r0 = 0; r0 < E; ++r0) {
                 if ((r0 >> b) & 1) continue;
-                if (((uint32_t)r0 & rmask) != rmask) continue;
+                if (((uint32_t)r0 & rmask) != rmask) {
+                    if (deferred)
+                        s << "            qs_cm(mt[" << off + 8 << "], mt[" << off + 9 << "], " << vn(r0 | (1 << b))
+                          << ");\n";
+                    continue;
+                }
                 if (diag)
                     s << "            qs_cm(m[0], m[1], " << vn(r0) << "); qs_cm(m[6], m[7], " << vn(r0 | (1 << b)) << ");\n";
                 else
@@ -428,7 +613,56 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
             s << "        }\n";
         }
     }
-    if (final_t) emit_relayout(tcount++);
+    // Deferred factors are multiplied in where they cost least: before the
+    // final re-layout if the qubits carrying them all sit in register bits
+    // there and not after it.
+    auto lane_phases = [&](const Layout& L) {
+        int c = 0;
+        for (int b = 0; b < TB; ++b) c += has_phi[L.thr[b]] ? 1 : 0;
+        return c;
+    };
+    auto emit_deferred = [&](const Layout& L, std::ostringstream& pro) {
+        if (!any_deferred) return;
+        // register factor: gsc times the phases of the register-bit qubits
+        const size_t roff = g.mats.size();
+        for (int r = 0; r < E; ++r) {
+            double a = 0.0;
+            for (int b = 0; b < RB; ++b)
+                if (((r >> b) & 1) && has_phi[L.reg[b]]) a += phi[L.reg[b]];
+            const Cx f = gsc * std::polar(1.0, a);
+            g.mats.push_back(f.real());
+            g.mats.push_back(f.imag());
+        }
+        const int nl = lane_phases(L);
+        if (nl == 0) {
+            for (int r = 0; r < E; ++r)
+                s << "        qs_cm(mt[" << roff + 2 * r << "], mt[" << roff + 2 * r + 1 << "], " << vn(r) << ");\n";
+            return;
+        }
+        // lane factor: the phases of the thread-bit qubits, fixed per lane
+        // (the layout does not change from tile to tile), formed once
+        pro << "    V lf;\n    lf.x = (R)1;\n    lf.y = (R)0;\n";
+        for (int b = 0; b < TB; ++b) {
+            if (!has_phi[L.thr[b]]) continue;
+            const size_t o = g.mats.size();
+            g.mats.push_back(cos(phi[L.thr[b]]));
+            g.mats.push_back(sin(phi[L.thr[b]]));
+            pro << "    if (tid & " << (1u << b) << "u) qs_cm(mats[" << o << "], mats[" << o + 1 << "], lf);\n";
+        }
+        for (int r = 0; r < E; ++r)
+            s << "        { V f = lf; qs_cm(mt[" << roff + 2 * r << "], mt[" << roff + 2 * r + 1 << "], f); qs_cm(f.x, f.y, "
+              << vn(r) << "); }\n";
+    };
+    std::ostringstream pro;  // per-lane constants formed before the tile loop
+    if (final_t && lane_phases(last) == 0 && lane_phases(P.store) > 0) {
+        // (bits with a pending flip carry no phase, so the register factors
+        // do not depend on the flips)
+        emit_deferred(last, pro);
+        emit_relayout(tcount++);
+    } else {
+        if (final_t) emit_relayout(tcount++);
+        emit_deferred(P.store, pro);
+    }
     s << "        const unsigned long long bs = base + stt;\n";
     const std::string fx = flip_expr(streg, true);
     if (fx.empty()) {
@@ -444,7 +678,42 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     s << "        if (!more) break;\n";
     for (int r = 0; r < E; ++r) s << "        v" << r << " = n" << r << ";\n";
     s << "        tile = ntile;\n        base = ins(tile);\n    }\n}\n";
-    g.src = s.str();
+
+    // Tile loop with a one-tile prefetch: tile t + gridDim.x is loaded while
+    // tile t is computed.  The matrix pointer is made to depend
+    // on the tile (the added term is always 0) so that the scalar matrix loads
+    // stay in the loop instead of being hoisted out of it.
+    std::ostringstream loop;
+    loop << pro.str();
+    loop << "    unsigned long long tile = blockIdx.x;\n";
+    loop << "    if (tile >= ntiles) return;\n";
+    loop << "    auto ins = [](unsigned long long t) -> unsigned long long {\n";
+    loop << "        unsigned long long b = t;\n";
+    for (int j = 0; j < K; ++j) {
+        const int p = P.S[j];
+        loop << "        b = ((b >> " << p << ") << " << (p + 1) << ") | (b & " << hex64((1ull << p) - 1) << ");\n";
+    }
+    loop << "        return b;\n    };\n";
+    loop << "    unsigned long long base = ins(tile);\n";
+    for (int r = 0; r < E; ++r) loop << "    V v" << r << " = " << ld("base", r) << ";\n";
+    // Drain the first tile's loads before the loop.  The compiler's wait
+    // analysis merges the loop entry with the back edge; with these loads
+    // still pending at the entry it makes every iteration wait for the loads
+    // of the next tile before computing the current one.
+    loop << "    __builtin_amdgcn_s_waitcnt(0x0F70);\n";
+    loop << "    for (;;) {\n";
+    // z is always 0; LDS addresses derived from it are computed in the loop
+    // next to their use instead of being hoisted and held in registers.
+    loop << "        const unsigned z = (unsigned)(tile >> 62);\n";
+    loop << "        const R* mt = mats + z;\n";
+    loop << "        const unsigned long long ntile = tile + gridDim.x;\n";
+    loop << "        const bool more = ntile < ntiles;\n";
+    for (int r = 0; r < E; ++r) loop << "        V n" << r << ";\n";
+    loop << "        if (more) {\n";
+    loop << "            const unsigned long long nb = ins(ntile);\n";
+    for (int r = 0; r < E; ++r) loop << "            n" << r << " = " << ld("nb", r) << ";\n";
+    loop << "        }\n";
+    g.src = head.str() + loop.str() + s.str();
     return g;
 }
 
@@ -603,6 +872,11 @@ struct JitPlan {
     std::vector<size_t> mat_off;  // element offset of each pass's matrices
     std::vector<int> blocks_per_cu;  // resident workgroups per CU for each pass kernel
     void* dmats = nullptr;        // device copy of all matrices
+    // pass 0 forming its tiles from a basis state instead of reading them
+    // (same matrices as pass 0), compiled on first use
+    std::string init_src;
+    hipFunction_t init_fn = nullptr;
+    int init_blocks_per_cu = 1;
 };
 
 void jit_plan_free(JitPlan* p)
@@ -615,7 +889,7 @@ void jit_plan_free(JitPlan* p)
     delete p;
 }
 
-qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passes_out)
+qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passes_out, const uint64_t* init_index)
 {
     // a density matrix runs as its 2N-qubit vector (Eq. 2)
     std::vector<OpRec> dm_ops;
@@ -647,8 +921,9 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
         std::vector<double> mats;
         std::unique_ptr<JitPlan> nj(new JitPlan());
         for (const PassPlan& P : plan) {
-            GenOut go = generate(P, ext, cfg.TB, cfg.RB, dbl);
+            GenOut go = generate(P, ext, cfg.TB, cfg.RB, dbl, false);
             if (go.bad) return set_error(QS_E_ARG, "internal: relayout swizzle outside address bits 0..2");
+            if (srcs.empty()) nj->init_src = generate(P, ext, cfg.TB, cfg.RB, dbl, true).src;
             nj->mat_off.push_back(mats.size());
             mats.insert(mats.end(), go.mats.begin(), go.mats.end());
             srcs.push_back(std::move(go.src));
@@ -689,14 +964,41 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
         J = c->jit = nj.release();
     }
     unsigned long long ntiles = 1ull << (nbits - (cfg.TB + cfg.RB));
+    unsigned long long init_at = 0;
+    if (init_index) {
+        // basis index j of a density matrix is the vector entry j + 2^N j
+        init_at = r->kind == QS_DENSITY ? *init_index + (*init_index << r->n) : *init_index;
+        if (J->fns.empty()) {
+            // no pass to fold the initialisation into
+            const Launch L{r->stream, r->env->device};
+            const uint64_t len = 1ull << nbits;
+            qs_status s = profiled(r, QS_K_INIT, [&](int*) {
+                return r->prec == QS_C128 ? launch_init_basis<double>(L, r->amp, len, init_at, 1.0, 0.0)
+                                          : launch_init_basis<float>(L, r->amp, len, init_at, 1.0, 0.0);
+            });
+            if (s) return s;
+        } else if (!J->init_fn) {
+            std::vector<hipFunction_t> f;
+            qs_status s = load_all(r->env->device, {J->init_src}, f);
+            if (s) return s;
+            int nb = 0;
+            hipError_t e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f[0], 1 << cfg.TB, 0);
+            if (e != hipSuccess) return hip_error(e, "occupancy query");
+            J->init_blocks_per_cu = std::max(1, nb);
+            J->init_fn = f[0];
+        }
+    }
     for (size_t p = 0; p < J->fns.size(); ++p) {
         void* amp = r->amp;
         const void* mp = (const char*)J->dmats + J->mat_off[p] * esz_of(r->prec);
-        void* args[] = {&amp, &mp, &ntiles};
+        const bool first_init = init_index && p == 0;
+        void* args[] = {&amp, &mp, &ntiles, &init_at};
+        const hipFunction_t fn = first_init ? J->init_fn : J->fns[p];
+        const int bpc = first_init ? J->init_blocks_per_cu : J->blocks_per_cu[p];
         // a persistent grid: the workgroups that fit on the 256 CUs at once
-        const unsigned grid = (unsigned)std::min<unsigned long long>(ntiles, 256ull * J->blocks_per_cu[p]);
+        const unsigned grid = (unsigned)std::min<unsigned long long>(ntiles, 256ull * bpc);
         qs_status s = profiled(r, QS_K_FUSED, [&](int*) {
-            return hipModuleLaunchKernel(J->fns[p], grid, 1, 1, 1u << cfg.TB, 1, 1, 0, r->stream, args, nullptr);
+            return hipModuleLaunchKernel(fn, grid, 1, 1, 1u << cfg.TB, 1, 1, 0, r->stream, args, nullptr);
         });
         if (s) return s;
     }
@@ -718,7 +1020,7 @@ qs_status generate_sources(const std::vector<OpRec>& circuit_ops, int n, int kin
     for (PassPlan& P : plan) merge_phase_ops(P, ext);
     out.clear();
     for (const PassPlan& P : plan) {
-        GenOut go = generate(P, ext, cfg.TB, cfg.RB, prec == QS_C128);
+        GenOut go = generate(P, ext, cfg.TB, cfg.RB, prec == QS_C128, false);
         if (go.bad) return set_error(QS_E_ARG, "internal: relayout swizzle outside address bits 0..2");
         out.push_back(go.src);
     }

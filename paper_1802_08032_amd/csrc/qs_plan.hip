@@ -426,13 +426,17 @@ LocalOp mul(const LocalOp& A, const LocalOp& B)  // A * B on the same qubits
     return C;
 }
 
-// Real multiply-adds per amplitude when an op is applied in registers.
+// Real multiply-adds per amplitude when an op is applied in registers.  An
+// uncontrolled dense 2x2 runs as its unit-diagonal core (its diagonal part
+// is deferred), a NOT as a register renaming (with at most a phase on the
+// quarter where control and target are set, moving a deferred phase), a
+// one-qubit phase not at all (deferred).
 double op_cost(const OpRec& op, int nregctrl)
 {
     switch (op.kind) {
-    case 0: return 8.0 / (1 << nregctrl);
-    case 1: return 0.0;  // a permutation of register names
-    case 2: return 4.0 / (1 << op.ctrls.size());
+    case 0: return nregctrl == 0 ? 4.0 : 8.0 / (1 << nregctrl);
+    case 1: return nregctrl == 0 ? 0.0 : 1.0;
+    case 2: return op.ctrls.size() == 1 ? 0.0 : 4.0 / (1 << op.ctrls.size());
     case 4: return 16.0 / (1 << nregctrl);
     default: return 1e9;
     }
@@ -511,7 +515,7 @@ void merge_phase_ops(PassPlan& P, std::vector<OpRec>& ops)
             }
             nbk.plan.push_back(idx);
             nbk.acc = acc;
-            const double full = nb == 1 ? 8.0 : 16.0;
+            const double full = nb == 1 ? 4.0 : 16.0;
             if (full < nbk.cost) {
                 OpRec m{};
                 m.target = q0;

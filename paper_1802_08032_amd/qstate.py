@@ -98,6 +98,7 @@ SIGNATURES = {
     'qs_circuit_run': (_i, [_vp, _vp, _i, _PI]),
     'qs_circuit_run_tiled': (_i, [_vp, _vp, _i, _i, _i, _PI]),
     'qs_circuit_run_compiled': (_i, [_vp, _vp, _i, _i, _i, _i, _PI]),
+    'qs_circuit_run_compiled_from_basis': (_i, [_vp, _vp, _i, _i, _i, _i, _u64, _PI]),
     'qs_circuit_source': (_i, [_vp, _i, _i, _i, _i, _i, _i, _i, _i, C.c_char_p, _sz, C.POINTER(_sz), _PI]),
     'qs_batch_create': (_i, [_vp, _vp, _i, _i, C.POINTER(_vp)]),
     'qs_batch_destroy': (_i, [_vp]),
@@ -502,10 +503,16 @@ class Circuit:
         return passes.value
 
     def run_compiled(self, reg: Register, tile_qubits: int, thread_bits: int, max_phases: int = 0,
-                     contig_qubits: int = 0) -> int:
+                     contig_qubits: int = 0, init_basis: int | None = None) -> int:
+        """Run-time compiled fused passes; with init_basis, the register
+        first becomes |init_basis> inside the first pass."""
         passes = C.c_int()
-        _check(lib().qs_circuit_run_compiled(reg.h, self.h, tile_qubits, thread_bits, max_phases,
-                                             contig_qubits, C.byref(passes)))
+        if init_basis is None:
+            _check(lib().qs_circuit_run_compiled(reg.h, self.h, tile_qubits, thread_bits, max_phases,
+                                                 contig_qubits, C.byref(passes)))
+        else:
+            _check(lib().qs_circuit_run_compiled_from_basis(reg.h, self.h, tile_qubits, thread_bits, max_phases,
+                                                            contig_qubits, init_basis, C.byref(passes)))
         return passes.value
 
     def source(self, n: int, prec: int, tile_qubits: int, thread_bits: int, pass_index: int = 0,

@@ -138,3 +138,47 @@ def test_compiled_plan_is_keyed_by_register_kind(q, env, first):
     c.close()
     sv.close()
     dm.close()
+
+
+@pytest.mark.parametrize('kind_name,prec_name,n,index', [('STATEVEC', 'C128', 14, 0), ('STATEVEC', 'C128', 14, 5),
+                                                         ('STATEVEC', 'C128', 20, (1 << 20) - 1),
+                                                         ('STATEVEC', 'C64', 16, 9), ('DENSITY', 'C128', 6, 3)])
+def test_compiled_run_from_basis_state(q, env, kind_name, prec_name, n, index):
+    """qs_circuit_run_compiled_from_basis: the first pass forms |index>
+    (|index><index| for a density matrix) instead of reading the register,
+    which holds garbage beforehand; the result equals the oracle's run from
+    that basis state, and an empty circuit just sets the basis state."""
+    kind, prec = getattr(q, kind_name), getattr(q, prec_name)
+    if kind == q.DENSITY:
+        ops = noisy_circuit(n, 3, 21)
+        ref = O.run_dm(n, ops, init_index=index)
+        tile = (10, 7, 0, 3)
+    else:
+        ops = layered_circuit(n, 4, 22, mcphase=True)
+        ref = O.run_sv(n, ops, init_index=index)
+        tile = (12, 8, 0, 4) if prec == q.C128 else (14, 10, 0, 5)
+    reg = q.Register(env, n, kind, prec)
+    reg.init_plus()  # overwritten without being read
+    c = q.Circuit(ops)
+    passes = c.run_compiled(reg, *tile, init_basis=index)
+    got = reg.get_amps()
+    log(f'from basis {index}: {kind_name} {prec_name} n={n}, {passes} passes')
+    if prec == q.C128:
+        assert max_abs(got, ref) <= 1e-12
+    else:
+        assert abs(fidelity_deficit(ref, got)) <= 1e-5
+    # the same plan without the folded initialisation
+    reg.init_basis(index)
+    assert c.run_compiled(reg, *tile) == passes
+    assert max_abs(reg.get_amps(), got) <= (1e-14 if prec == q.C128 else 1e-6)
+    c.close()
+    empty = q.Circuit([])
+    reg.init_plus()
+    empty.run_compiled(reg, *tile, init_basis=index)
+    pos = index + (index << n) if kind == q.DENSITY else index
+    amps = reg.get_amps()
+    assert amps[pos] == 1.0 and np.count_nonzero(amps) == 1
+    with pytest.raises(q.QStateError, match='QS_E_ARG'):
+        empty.run_compiled(reg, *tile, init_basis=1 << n)
+    empty.close()
+    reg.close()
