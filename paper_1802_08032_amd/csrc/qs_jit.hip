@@ -30,10 +30,20 @@
 namespace qs {
 namespace {
 
+// Diagonal factors deferred from pass to pass: the true state is gsc times
+// prod_q exp(i phi[q] x_q) (over global qubits q with has[q]) times the
+// stored state.
+struct Deferred {
+    double phi[64] = {};
+    bool has[64] = {};
+    std::complex<double> gsc = 1.0;
+};
+
 struct GenOut {
     std::string src;
-    std::vector<double> mats;  // 8 values per op that reads a matrix or phase
+    std::vector<double> mats;  // kernel data: matrices, core coefficients, phases
     bool bad = false;          // a relayout's swizzle broke the address split
+    Deferred out;              // deferred factors after the pass
 };
 
 std::string hex64(uint64_t v)
@@ -187,7 +197,12 @@ CoreForm core_form(const Cx (&u)[2][2])
     return {3, k, u[0][1], u[1][0]};
 }
 
-GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB, bool dbl, bool init)
+// `in`: factors deferred by earlier passes.  `last`: multiply every deferred
+// factor in before storing (otherwise they are handed on in GenOut::out, and
+// only multiplied in early when the global factor would leave the range the
+// precision keeps comfortably).
+GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB, bool dbl, bool init,
+                const Deferred& in, bool last_pass)
 {
     const int K = TB + RB, E = 1 << RB;
     GenOut g;
@@ -269,12 +284,25 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     // tile qubit j).  A dense gate's diagonal part, a one-qubit phase and the
     // phase a NOT moves around all land here; the next dense op on qubit j
     // takes exp(i phi[j] x_j) into its matrix on the host, and whatever is
-    // left is multiplied in once before the tile is stored.  A register bit
-    // with a pending flip never carries a phase (has_phi false).
+    // left is multiplied in once before the tile is stored.  Phases refer to
+    // the true state, so they are unaffected by pending flips, except where
+    // they are multiplied into registers: there a flipped lane holds the
+    // amplitude of true bit value 1 in the register of stored bit 0.
     std::vector<double> phi(K, 0.0);
     std::vector<bool> has_phi(K, false);
-    Cx gsc(1.0, 0.0);
-    bool any_deferred = false;
+    Cx gsc = in.gsc;
+    bool any_deferred = gsc != Cx(1.0, 0.0);
+    for (int j = 0; j < K; ++j) {
+        phi[j] = in.phi[P.S[j]];
+        has_phi[j] = in.has[P.S[j]];
+        any_deferred = any_deferred || has_phi[j];
+    }
+    // deferred phases of qubits outside the tile (multiplied in by the last
+    // pass, from the tile index: its bit i is the i-th qubit outside S)
+    std::vector<int> outside;
+    for (int q = 0; q < 64; ++q)
+        if (local[q] < 0 && in.has[q]) outside.push_back(q);
+    any_deferred = any_deferred || (last_pass && !outside.empty());
 
     auto materialize = [&](uint32_t bits) {
         for (int b = 0; b < RB; ++b) {
@@ -304,6 +332,7 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     // apply the deferred phase of tile qubit j, held at register bit b
     auto flush_phase = [&](int j, int b) {
         if (!has_phi[j]) return;
+        materialize(1u << b);
         std::vector<int> regs;
         for (int r = 0; r < E; ++r)
             if ((r >> b) & 1) regs.push_back(r);
@@ -391,13 +420,11 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
             for (int q : op.ctrls) classify(q);
             // a one-qubit phase on a tile qubit is deferred (no code)
             if (op.kind == 2 && op.ctrls.size() == 1 && local[op.ctrls[0]] >= 0) {
-                const int j = local[op.ctrls[0]], b = reg_bit(j);
-                if (b < 0 || pend[b].empty()) {
-                    phi[j] += op.angle;
-                    has_phi[j] = true;
-                    any_deferred = true;
-                    continue;
-                }
+                const int j = local[op.ctrls[0]];
+                phi[j] += op.angle;
+                has_phi[j] = true;
+                any_deferred = true;
+                continue;
             }
             std::string cond;
             if (gmask) cond = "((base & " + hex64(gmask) + ") == " + hex64(gmask) + ")";
@@ -487,6 +514,7 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
                     // the stored state went through X where the controls are
                     // set; keep exp(i phi x_t) deferred for every register:
                     // X exp(i phi x_t) = exp(i phi) exp(-i phi x_t) X
+                    if (rmask) materialize(1u << b);  // the fix-up below reads true bit values
                     const double a = phi[j];
                     if (rmask == 0) {
                         gsc *= std::polar(1.0, a);
@@ -539,13 +567,20 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
                 u[0][1] *= std::polar(1.0, pj);
                 u[1][1] *= std::polar(1.0, pj);
             }
-            if (cond.empty() && rmask == 0 && pend[b].empty()) {
+            if (cond.empty() && rmask == 0) {
                 const CoreForm cf = core_form(u);
                 if (cf.form >= 0) {
                     if (cf.form == 2 || cf.form == 3) {
                         g.mats.push_back(cf.k.real());
                         g.mats.push_back(cf.k.imag());
-                        s << "        { const R kr = mt[" << off << "], ki = mt[" << off + 1 << "];";
+                        // a lane whose pair on bit b is stored exchanged applies
+                        // X C X, the core of -conj(k); the deferred diagonal
+                        // refers to the true state and is the same for all lanes
+                        if (pend[b].empty())
+                            s << "        { const R kr = mt[" << off << "], ki = mt[" << off + 1 << "];";
+                        else
+                            s << "        { const R kr = (" << pend[b] << ") ? -mt[" << off << "] : mt[" << off
+                              << "], ki = mt[" << off + 1 << "];";
                     }
                     for (int r0 = 0; r0 < E; ++r0) {
                         if ((r0 >> b) & 1) continue;
@@ -633,8 +668,19 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
             g.mats.push_back(f.real());
             g.mats.push_back(f.imag());
         }
+        // register bits holding a deferred phase under a pending flip: a
+        // flipped lane keeps true bit value v of such a bit in the register
+        // of stored value 1 - v, so its factor differs by exp(+-i phi)
+        std::vector<int> fb;
+        for (int b = 0; b < RB; ++b)
+            if (!pend[b].empty() && has_phi[L.reg[b]]) fb.push_back(b);
+        while (fb.size() > 2) {
+            materialize(1u << fb.back());
+            fb.pop_back();
+        }
         const int nl = lane_phases(L);
-        if (nl == 0) {
+        const bool tilefac = last_pass && !outside.empty();
+        if (nl == 0 && fb.empty() && !tilefac) {
             for (int r = 0; r < E; ++r)
                 s << "        qs_cm(mt[" << roff + 2 * r << "], mt[" << roff + 2 * r + 1 << "], " << vn(r) << ");\n";
             return;
@@ -649,19 +695,82 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
             g.mats.push_back(sin(phi[L.thr[b]]));
             pro << "    if (tid & " << (1u << b) << "u) qs_cm(mats[" << o << "], mats[" << o + 1 << "], lf);\n";
         }
-        for (int r = 0; r < E; ++r)
-            s << "        { V f = lf; qs_cm(mt[" << roff + 2 * r << "], mt[" << roff + 2 * r + 1 << "], f); qs_cm(f.x, f.y, "
-              << vn(r) << "); }\n";
+        // per tile: the phases of qubits outside the tile, from tables over
+        // 8-bit slices of the tile index
+        if (tilefac) {
+            std::vector<int> rank(64, -1);  // tile-index bit of each qubit outside S
+            for (int q = 0, i = 0; q < 64; ++q)
+                if (local[q] < 0) rank[q] = i++;
+            s << "        V tf;\n        tf.x = (R)1;\n        tf.y = (R)0;\n";
+            for (int c = 0; c < 8; ++c) {
+                std::vector<int> qs;
+                for (int q : outside)
+                    if (rank[q] >= 8 * c && rank[q] < 8 * c + 8) qs.push_back(q);
+                if (qs.empty()) continue;
+                const size_t o = g.mats.size();
+                for (int v = 0; v < 256; ++v) {
+                    double a = 0.0;
+                    for (int q : qs)
+                        if ((v >> (rank[q] - 8 * c)) & 1) a += in.phi[q];
+                    g.mats.push_back(cos(a));
+                    g.mats.push_back(sin(a));
+                }
+                s << "        { const unsigned ix = (unsigned)((tile >> " << 8 * c << ") & 255ull); qs_cm(mt[" << o
+                  << " + 2 * ix], mt[" << o + 1 << " + 2 * ix], tf); }\n";
+            }
+        }
+        // per tile: one lane factor per combination of stored values of the
+        // flipped bits
+        const int nv = 1 << fb.size();
+        for (int v = 0; v < nv; ++v) {
+            s << "        V lf" << v << " = lf;\n";
+            if (tilefac) s << "        qs_cm(tf.x, tf.y, lf" << v << ");\n";
+            for (size_t i = 0; i < fb.size(); ++i) {
+                const double a = phi[L.reg[fb[i]]] * (((v >> i) & 1) ? -1.0 : 1.0);
+                const size_t o = g.mats.size();
+                g.mats.push_back(cos(a));
+                g.mats.push_back(sin(a));
+                s << "        if (" << pend[fb[i]] << ") qs_cm(mt[" << o << "], mt[" << o + 1 << "], lf" << v << ");\n";
+            }
+        }
+        for (int r = 0; r < E; ++r) {
+            int v = 0;
+            for (size_t i = 0; i < fb.size(); ++i) v |= ((r >> fb[i]) & 1) << i;
+            s << "        { V f = lf" << v << "; qs_cm(mt[" << roff + 2 * r << "], mt[" << roff + 2 * r + 1
+              << "], f); qs_cm(f.x, f.y, " << vn(r) << "); }\n";
+        }
     };
     std::ostringstream pro;  // per-lane constants formed before the tile loop
-    if (final_t && lane_phases(last) == 0 && lane_phases(P.store) > 0) {
-        // (bits with a pending flip carry no phase, so the register factors
-        // do not depend on the flips)
-        emit_deferred(last, pro);
-        emit_relayout(tcount++);
-    } else {
+    // hand the factors on, unless this is the last pass or the global factor
+    // has become small (|gsc| <= 1 shrinks by each core; the stored state
+    // grows by 1 / |gsc|)
+    const bool multiply_in = last_pass || std::abs(gsc) < (dbl ? 0x1p-300 : 0x1p-30);
+    g.out = in;
+    if (!multiply_in) {
         if (final_t) emit_relayout(tcount++);
-        emit_deferred(P.store, pro);
+        for (int j = 0; j < K; ++j) {
+            g.out.phi[P.S[j]] = phi[j];
+            g.out.has[P.S[j]] = has_phi[j];
+        }
+        g.out.gsc = gsc;
+    } else {
+        if (final_t && lane_phases(last) == 0 && lane_phases(P.store) > 0) {
+            emit_deferred(last, pro);
+            emit_relayout(tcount++);
+        } else {
+            if (final_t) emit_relayout(tcount++);
+            emit_deferred(P.store, pro);
+        }
+        for (int j = 0; j < K; ++j) {
+            g.out.phi[P.S[j]] = 0.0;
+            g.out.has[P.S[j]] = false;
+        }
+        if (last_pass)
+            for (int q : outside) {
+                g.out.phi[q] = 0.0;
+                g.out.has[q] = false;
+            }
+        g.out.gsc = 1.0;
     }
     s << "        const unsigned long long bs = base + stt;\n";
     const std::string fx = flip_expr(streg, true);
@@ -920,10 +1029,13 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
         std::vector<std::string> srcs;
         std::vector<double> mats;
         std::unique_ptr<JitPlan> nj(new JitPlan());
-        for (const PassPlan& P : plan) {
-            GenOut go = generate(P, ext, cfg.TB, cfg.RB, dbl, false);
+        Deferred carry;
+        for (size_t p = 0; p < plan.size(); ++p) {
+            const bool lastp = p + 1 == plan.size();
+            GenOut go = generate(plan[p], ext, cfg.TB, cfg.RB, dbl, false, carry, lastp);
             if (go.bad) return set_error(QS_E_ARG, "internal: relayout swizzle outside address bits 0..2");
-            if (srcs.empty()) nj->init_src = generate(P, ext, cfg.TB, cfg.RB, dbl, true).src;
+            if (p == 0) nj->init_src = generate(plan[p], ext, cfg.TB, cfg.RB, dbl, true, carry, lastp).src;
+            carry = go.out;
             nj->mat_off.push_back(mats.size());
             mats.insert(mats.end(), go.mats.begin(), go.mats.end());
             srcs.push_back(std::move(go.src));
@@ -1019,9 +1131,11 @@ qs_status generate_sources(const std::vector<OpRec>& circuit_ops, int n, int kin
     std::vector<OpRec> ext(ops);
     for (PassPlan& P : plan) merge_phase_ops(P, ext);
     out.clear();
-    for (const PassPlan& P : plan) {
-        GenOut go = generate(P, ext, cfg.TB, cfg.RB, prec == QS_C128, false);
+    Deferred carry;
+    for (size_t p = 0; p < plan.size(); ++p) {
+        GenOut go = generate(plan[p], ext, cfg.TB, cfg.RB, prec == QS_C128, false, carry, p + 1 == plan.size());
         if (go.bad) return set_error(QS_E_ARG, "internal: relayout swizzle outside address bits 0..2");
+        carry = go.out;
         out.push_back(go.src);
     }
     return QS_OK;
