@@ -184,6 +184,67 @@ def paper_leg(q, torch, log, n=32, depth=100, seed=7):
     return out
 
 
+def cpu_configs_leg(log, budget_s=5.0):
+    """The oracle on the host cores for the other workloads, with all OpenMP
+    threads and with one:
+    * 16-qubit depth-20 layered circuit (Haar layer + CNOT brick, 470 gates), whole;
+    * the 512 registers of 10..20 qubits with depth-16 RY/RZ + CZ circuits:
+      one register of every size present, each circuit whole, weighted by the
+      number of registers of that size (one thread: sizes above 16 scaled from
+      size 16 by the amplitude ratio, labelled);
+    * the 14-qubit noisy density matrix (1015 ops): the first ops until the
+      budget runs out, scaled to the whole list (labelled)."""
+    import oracle as O
+    from workloads import layered_circuit, noisy_circuit, param_circuit
+    threads = int(os.environ.get('OMP_NUM_THREADS', os.cpu_count() or 1))
+    out = {'cpu_model': cpu_model(), 'kind': 'oracle'}
+    c0 = layered_circuit(16, 20, seed=0)
+    rng = np.random.Generator(np.random.PCG64(3))
+    sizes = [int(v) for v in rng.integers(10, 21, 512)]
+    counts = {n: sizes.count(n) for n in sorted(set(sizes))}
+    dm_ops = noisy_circuit(14, 10, 2)
+    for label, nthr in (('all_threads', threads), ('one_thread', 1)):
+        prev = O.set_threads(nthr)
+        try:
+            t0 = time.perf_counter()
+            O.run_sv(16, c0)
+            t_c0 = time.perf_counter() - t0
+            per_size, scaled = {}, []
+            for n in counts:
+                if nthr == 1 and n > 16:
+                    per_size[n] = per_size[16] * (1 << (n - 16))
+                    scaled.append(n)
+                    continue
+                ops = param_circuit(n, 16, 1000 + sizes.index(n))
+                t0 = time.perf_counter()
+                O.run_sv(n, ops)
+                per_size[n] = time.perf_counter() - t0
+            t_batch = sum(counts[n] * per_size[n] for n in counts)
+            rho = O.dm_zero(14)
+            t0 = time.perf_counter()
+            done = 0
+            for op in dm_ops:
+                O.apply_dm(rho, 14, op)
+                done += 1
+                if time.perf_counter() - t0 > budget_s:
+                    break
+            t_dm = (time.perf_counter() - t0) / done * len(dm_ops)
+        finally:
+            O.set_threads(prev)
+        out[label] = {
+            'cores': nthr,
+            'c0_16q_layered_circuits_per_s': 1.0 / t_c0, 'c0_gates_per_s': len(c0) / t_c0,
+            'c3_512_registers_circuits_per_s': 512 / t_batch,
+            'c3_sample': ('one whole circuit per register size, weighted by the size counts'
+                          + (f'; sizes {scaled} scaled from 16 qubits' if scaled else '')),
+            'c2_14q_noisy_dm_s': t_dm, 'c2_ops_per_s': len(dm_ops) / t_dm,
+            'c2_sample': f'first {done} of {len(dm_ops)} ops timed, scaled to all',
+        }
+        log(f"cpu {label}: c0 {1.0 / t_c0:.2f} circuits/s, c3 {512 / t_batch:.1f} circuits/s, "
+            f"c2 {t_dm:.0f} s per circuit")
+    return out
+
+
 def c64_33q_leg(q, torch, log, depth=10):
     """33-qubit depth-10 layered circuit (the 32-qubit workload's generator)
     in complex64 (64 GiB), scored against a complex128 run of the same
@@ -345,10 +406,10 @@ def dm_leg(q, torch, log, N=14, depth=10, seed=2):
     return out
 
 
-EXTRAS = ('unfused', 'pertarget', 'measure', 'cpu', 'paper', 'c64', 'batched', 'serving', 'dm')
+EXTRAS = ('unfused', 'pertarget', 'measure', 'cpu', 'cpuconfigs', 'paper', 'c64', 'batched', 'serving', 'dm')
 
 
-def serving_leg(q, torch, log, count=40):
+def serving_leg(q, torch, log, count=200):
     """Mixed request stream (80 % state vectors of 12..30 qubits, 20 % noisy
     density matrices of 8..13 qubits, log-uniform sizes, depth 5..40, every
     qubit measured at the end), admitted by HBM bytes against 256 GiB with 8
@@ -584,6 +645,9 @@ def main():
     env.close()
     del reg
     torch.cuda.empty_cache()
+    if 'cpuconfigs' in legs:
+        log('cpu baselines of the other workloads')
+        out['cpu_baseline_other_workloads'] = cpu_configs_leg(log)
     if 'paper' in legs:
         log('paper-shaped random circuit')
         out['paper_circuit'] = paper_leg(q, torch, log)

@@ -325,12 +325,18 @@ qs_status qs_circuit_size(qs_circuit c, int* n_ops);
  * counting vector qubits.  *n_passes (may be NULL) receives the number of
  * full-state kernel passes launched. */
 qs_status qs_circuit_run(qs_reg r, qs_circuit c, int fusion_qubits, int* n_passes);
-/* Fused run of a state-vector circuit with an explicit tile shape (used by
- * the autotuner): tiles of 2^tile_qubits amplitudes held by 2^thread_bits
- * threads, at most max_phases register layouts per pass (0: default).
- * Shapes (thread_bits, tile_qubits - thread_bits) compiled in: (6,3) (7,3)
- * (8,3) (8,4) (9,3) (8,5) (9,4) (10,3), and for QS_C64 also (9,5) (10,4).
- * QS_E_ARG for other shapes or a tile wider than the register. */
+/* Fused run with an explicit tile shape through the generic pass kernel
+ * (no run-time compilation, so any circuit starts at once): tiles of
+ * 2^tile_qubits amplitudes held by 2^thread_bits threads, at most
+ * max_phases register layouts per pass (0: default).  Uncontrolled dense
+ * gates run as unit-diagonal cores with their diagonal part deferred to the
+ * next op on the qubit (or the end of the circuit), as in the compiled
+ * passes.  A density matrix runs as its 2N-qubit vector (Eq. 2: gates on q
+ * and conj on q + N, channels as 4x4 superoperators on (q, q + N));
+ * tile_qubits then counts vector qubits.  Shapes (thread_bits, tile_qubits
+ * - thread_bits) compiled in: (6,3) (7,3) (8,3) (8,4) (9,3) (9,4) (10,3),
+ * and for QS_C64 also (8,5) (9,5) (10,4).  QS_E_ARG for other shapes or a
+ * tile wider than the register. */
 qs_status qs_circuit_run_tiled(qs_reg r, qs_circuit c, int tile_qubits, int thread_bits,
                                int max_phases, int* n_passes);
 /* As qs_circuit_run_tiled, but each pass runs a kernel generated for that

@@ -4,7 +4,8 @@ Chooses the tile shape of the run-time compiled passes -- tile qubits K
 (fusion width), thread bits TB (workgroup size 2^TB, so 2^(K-TB) amplitudes
 per thread) and the number of low qubits kept contiguous in HBM -- by timing
 candidates on the caller's own register and circuit.  Results are cached in
-a JSON file keyed by (device name, qubits, precision, circuit structure).
+a JSON file ($QS_TUNE_CACHE, else $QS_JIT_CACHE, else ~/.cache/qstate)
+keyed by (device name, qubits, precision, circuit structure).
 """
 from __future__ import annotations
 
@@ -25,7 +26,8 @@ CANDIDATES = {
 
 
 def _cache_path() -> str:
-    d = os.environ.get('QS_JIT_CACHE') or os.path.join(os.path.expanduser('~'), '.cache', 'qstate')
+    d = (os.environ.get('QS_TUNE_CACHE') or os.environ.get('QS_JIT_CACHE')
+         or os.path.join(os.path.expanduser('~'), '.cache', 'qstate'))
     os.makedirs(d, exist_ok=True)
     return os.path.join(d, 'tune.json')
 

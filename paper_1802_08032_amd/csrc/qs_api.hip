@@ -1144,11 +1144,10 @@ qs_status qs_circuit_run_tiled(qs_reg r, qs_circuit c, int tile_qubits, int thre
 {
     qs_status s = circuit_check(r, c);
     if (s) return s;
-    if (r->kind != QS_STATEVEC) return qs::set_error(QS_E_KIND, "tiled runs need a state vector");
     const int RB = tile_qubits - thread_bits;
     if (!qs::fused_shape_supported(r->prec, thread_bits, RB))
         return qs::set_error(QS_E_ARG, "unsupported tile shape");
-    if (tile_qubits > r->n) return qs::set_error(QS_E_ARG, "tile wider than the register");
+    if (tile_qubits > r->nbits) return qs::set_error(QS_E_ARG, "tile wider than the register");
     if (max_phases < 0) return qs::set_error(QS_E_ARG, "negative phase cap");
     return qs::run_fused_sv(r, c->ops, qs::FusedConfig{thread_bits, RB, max_phases}, n_passes);
 }
@@ -1229,6 +1228,7 @@ qs_status qs_circuit_source(qs_circuit c, int n, int kind, int prec, int tile_qu
 
 static void batch_free(qs_batch b)
 {
+    qs::batch_plans_free(b->plans);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->dbuf) (void)hipFree(b->dbuf);

@@ -24,6 +24,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <complex>
+#include <memory>
 #include <vector>
 
 #include "qs_device.h"
@@ -54,11 +56,13 @@ struct FPass {
 
 struct FOp {
     int kind;        // specialised op code (see apply_op)
-    int rb;          // target register bit (dense / not)
+    int rb;          // target register bit (dense / not / core)
     uint32_t rmask;  // register bits that must be 1
     uint32_t tmask;  // thread-index bits that must be 1
     uint64_t gmask;  // global qubits outside the tile that must be 1
-    double m[8];     // dense matrix, or phase factor in m[0], m[1]
+    double m[8];     // dense matrix, phase factor in m[0], m[1], or core coefficient k in m[0], m[1]
+    uint32_t aux;    // 4x4 ops: entry of the 4x4 matrix table
+    uint32_t pad;
 };
 
 // In-register op application.  Conditions that are the same for the whole
@@ -142,7 +146,84 @@ __device__ __forceinline__ void phase_op(typename C2<T>::type (&v)[1 << RB], T f
 //   code = 32 + 4 * rb + variant   NOT
 //   code = 64 + lane               phase (lane: thread-bit controls present)
 //   code = 96 + 4 * rb + variant   diagonal dense gate (u01 = u10 = 0)
-enum : int { kDense = 0, kNot = 32, kPhase = 64, kDiag = 96 };
+//   code = 128 + 4 * rb            unit-diagonal core, amplitudes in place:
+//                                  (a, b) <- (a + k b, b - conj(k) a)
+//   code = 160 + 4 * rb            core with the pair exchanged:
+//                                  (a, b) <- (k a + b, a - conj(k) b)
+//   code = 192 + pair              4x4 on register bits (b1 < b2), pair index
+//                                  of (b1, b2), matrix in the 4x4 table
+//   code = 255                     nothing (a gate whose effect is deferred)
+enum : int { kDense = 0, kNot = 32, kPhase = 64, kDiag = 96, kCoreA = 128, kCoreB = 160, kDense4 = 192, kNop = 255 };
+
+// Register-bit pairs of the 4x4 ops, indexed by (b1 < b2) in lexical order.
+constexpr int kPairB1[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
+constexpr int kPairB2[10] = {1, 2, 3, 4, 2, 3, 4, 3, 4, 4};
+
+template <typename T, int RB, int RBIT, bool EXCH>
+__device__ __forceinline__ void core_case(typename C2<T>::type (&v)[1 << RB], const FOp& op)
+{
+    using V = typename C2<T>::type;
+    const T kr = (T)op.m[0], ki = (T)op.m[1];
+#pragma unroll
+    for (int r0 = 0; r0 < (1 << RB); ++r0) {
+        if (r0 & (1 << RBIT)) continue;
+        const V a = v[r0], b = v[r0 | (1 << RBIT)];
+        V na, nb;
+        if constexpr (!EXCH) {  // a + k b, b - conj(k) a
+            na.x = kr * b.x + a.x;
+            na.x = -ki * b.y + na.x;
+            na.y = kr * b.y + a.y;
+            na.y = ki * b.x + na.y;
+            nb.x = -kr * a.x + b.x;
+            nb.x = -ki * a.y + nb.x;
+            nb.y = -kr * a.y + b.y;
+            nb.y = ki * a.x + nb.y;
+        } else {  // k a + b, a - conj(k) b
+            na.x = kr * a.x + b.x;
+            na.x = -ki * a.y + na.x;
+            na.y = kr * a.y + b.y;
+            na.y = ki * a.x + na.y;
+            nb.x = -kr * b.x + a.x;
+            nb.x = -ki * b.y + nb.x;
+            nb.y = -kr * b.y + a.y;
+            nb.y = ki * b.x + nb.y;
+        }
+        v[r0] = na;
+        v[r0 | (1 << RBIT)] = nb;
+    }
+}
+
+// 4x4 complex matrix m (row-major, index bit(B1) + 2 bit(B2)) on every
+// register quad.
+template <typename T, int RB, int B1, int B2>
+__device__ __forceinline__ void dense4_case(typename C2<T>::type (&v)[1 << RB], const T* __restrict__ m)
+{
+    using V = typename C2<T>::type;
+#pragma unroll
+    for (int r0 = 0; r0 < (1 << RB); ++r0) {
+        if ((r0 >> B1) & 1 || (r0 >> B2) & 1) continue;
+        const int r[4] = {r0, r0 | (1 << B1), r0 | (1 << B2), r0 | (1 << B1) | (1 << B2)};
+        const V x[4] = {v[r[0]], v[r[1]], v[r[2]], v[r[3]]};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            // one product or multiply-add per statement
+            T re = m[8 * i] * x[0].x;
+            T im = m[8 * i] * x[0].y;
+            re = -m[8 * i + 1] * x[0].y + re;
+            im = m[8 * i + 1] * x[0].x + im;
+#pragma unroll
+            for (int j = 1; j < 4; ++j) {
+                const T mr = m[2 * (4 * i + j)], mi = m[2 * (4 * i + j) + 1];
+                re = mr * x[j].x + re;
+                re = -mi * x[j].y + re;
+                im = mr * x[j].y + im;
+                im = mi * x[j].x + im;
+            }
+            v[r[i]].x = re;
+            v[r[i]].y = im;
+        }
+    }
+}
 
 template <typename T, int RB, int RBIT, int VAR>
 __device__ __forceinline__ void dense_case(typename C2<T>::type (&v)[1 << RB], const FOp& op, uint32_t tid)
@@ -202,7 +283,8 @@ __device__ __forceinline__ void phase_case(typename C2<T>::type (&v)[1 << RB], c
 }
 
 template <typename T, int RB>
-__device__ __forceinline__ void apply_op(typename C2<T>::type (&v)[1 << RB], const FOp& op, uint32_t tid)
+__device__ __forceinline__ void apply_op(typename C2<T>::type (&v)[1 << RB], const FOp& op, uint32_t tid,
+                                         const T* __restrict__ m4tab)
 {
     switch (op.kind) {
 #define QS_DENSE(RBIT)                                                                   \
@@ -220,6 +302,17 @@ __device__ __forceinline__ void apply_op(typename C2<T>::type (&v)[1 << RB], con
     case kDiag + 4 * RBIT + 3: if constexpr (RB > RBIT) diag_case<T, RB, RBIT, 3>(v, op, tid); break;
     QS_DENSE(0) QS_DENSE(1) QS_DENSE(2) QS_DENSE(3) QS_DENSE(4)
 #undef QS_DENSE
+#define QS_CORE(RBIT)                                                                                    \
+    case kCoreA + 4 * RBIT: if constexpr (RB > RBIT) core_case<T, RB, RBIT, false>(v, op); break;        \
+    case kCoreB + 4 * RBIT: if constexpr (RB > RBIT) core_case<T, RB, RBIT, true>(v, op); break;
+    QS_CORE(0) QS_CORE(1) QS_CORE(2) QS_CORE(3) QS_CORE(4)
+#undef QS_CORE
+#define QS_D4(P)                                                                                         \
+    case kDense4 + P:                                                                                    \
+        if constexpr (RB > kPairB2[P]) dense4_case<T, RB, kPairB1[P], kPairB2[P]>(v, m4tab + 32 * op.aux); \
+        break;
+    QS_D4(0) QS_D4(1) QS_D4(2) QS_D4(3) QS_D4(4) QS_D4(5) QS_D4(6) QS_D4(7) QS_D4(8) QS_D4(9)
+#undef QS_D4
     case kPhase + 0: phase_case<T, RB, false>(v, op, tid); break;
     case kPhase + 1: phase_case<T, RB, true>(v, op, tid); break;
     default: break;
@@ -266,8 +359,9 @@ __device__ __forceinline__ void relayout(typename C2<T>::type (&v)[1 << RB],
 // tile's qubits.
 template <typename T, int TB, int RB>
 __device__ __forceinline__ void process_tile(typename C2<T>::type* __restrict__ amp, const FPass* __restrict__ P,
-                                             const FOp* __restrict__ ops, uint64_t tile,
-                                             typename C2<T>::type* lds, uint32_t tid, bool zero_init = false)
+                                             const FOp* __restrict__ ops, const T* __restrict__ m4tab,
+                                             uint64_t tile, typename C2<T>::type* lds, uint32_t tid,
+                                             bool zero_init = false)
 {
     using V = typename C2<T>::type;
     constexpr int E = 1 << RB;
@@ -293,7 +387,7 @@ __device__ __forceinline__ void process_tile(typename C2<T>::type* __restrict__ 
         for (int o = F.op_begin; o < F.op_end; ++o) {
             const FOp& op = ops[o];
             if ((base & op.gmask) != op.gmask) continue;  // same for the whole tile
-            apply_op<T, RB>(v, op, tid);
+            apply_op<T, RB>(v, op, tid, m4tab);
         }
     }
     if (P->final_transpose) relayout<T, TB, RB>(v, lds, P->fin, tid);
@@ -304,12 +398,13 @@ __device__ __forceinline__ void process_tile(typename C2<T>::type* __restrict__ 
 template <typename T, int TB, int RB>
 __global__ __launch_bounds__(1 << TB) void k_fused(typename C2<T>::type* __restrict__ amp,
                                                    const FPass* __restrict__ P,
-                                                   const FOp* __restrict__ ops, uint64_t ntiles)
+                                                   const FOp* __restrict__ ops, const T* __restrict__ m4tab,
+                                                   uint64_t ntiles)
 {
     using V = typename C2<T>::type;
     __shared__ V lds[1 << (TB + RB)];
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-        process_tile<T, TB, RB>(amp, P, ops, tile, lds, threadIdx.x);
+        process_tile<T, TB, RB>(amp, P, ops, m4tab, tile, lds, threadIdx.x);
 }
 
 // Batched registers.  Every register's circuit is planned into passes; the
@@ -335,7 +430,8 @@ template <typename T, int TB, int RB>
 __global__ __launch_bounds__(1 << TB) void k_batch(const BatchReg* __restrict__ regs,
                                                    const BatchItem* __restrict__ items, int nitems,
                                                    const FPass* __restrict__ passes,
-                                                   const FOp* __restrict__ ops, int init)
+                                                   const FOp* __restrict__ ops, const T* __restrict__ m4tab,
+                                                   int init)
 {
     using V = typename C2<T>::type;
     __shared__ V lds[1 << (TB + RB)];
@@ -346,7 +442,7 @@ __global__ __launch_bounds__(1 << TB) void k_batch(const BatchReg* __restrict__ 
         const FPass* P = passes + R.pass0 + it.pass;
         const bool zi = init && it.pass == 0;
         for (uint32_t tile = it.tile0; tile < it.tile1; ++tile)
-            process_tile<T, TB, RB>((V*)R.amp, P, ops, tile, lds, tid, zi);
+            process_tile<T, TB, RB>((V*)R.amp, P, ops, m4tab, tile, lds, tid, zi);
     }
 }
 
@@ -449,14 +545,82 @@ FOp encode_op(const OpRec& op, const PassPlan& P, const Layout& L)
     return f;
 }
 
-// Device form of a planned pass list, appended to hp / hops (op indices in
-// the phases are positions in hops).
-void serialize(const std::vector<PassPlan>& plan, const std::vector<OpRec>& ops, int TB, int RB,
-               std::vector<FPass>& hp, std::vector<FOp>& hops, std::vector<int>* src = nullptr)
+using Cx = std::complex<double>;
+
+// Multiply the amplitudes whose register bits `rmask`, thread bits `tmask`
+// and outside qubits `gmask` are all 1 by f.
+FOp phase_fop(uint32_t rmask, uint32_t tmask, uint64_t gmask, Cx f)
+{
+    FOp o;
+    memset(&o, 0, sizeof(o));
+    o.kind = kPhase + (tmask ? 1 : 0);
+    o.rmask = rmask;
+    o.tmask = tmask;
+    o.gmask = gmask;
+    o.m[0] = f.real();
+    o.m[1] = f.imag();
+    return o;
+}
+
+// Diagonal factors deferred by the lowering (see lower_passes): the true
+// state is gsc times prod_q exp(i phi[q] x_q) over the qubits with has[q],
+// times the stored state.  Which qubits carry a factor, and whether gsc was
+// touched, depends only on the op structure, not on matrix values, so a
+// circuit with new parameters lowers to the same number of ops.
+struct Defer {
+    double phi[64] = {};
+    bool has[64] = {};
+    Cx gsc = 1.0;
+    bool gsc_used = false;
+    int shrink = 0;  // cores since gsc was last multiplied in
+};
+
+// Every core scales gsc by |d0| >= 1/sqrt 2, and the stored state grows by
+// the inverse; after this many cores gsc is multiplied in (2^-30 keeps
+// complex64 amplitudes far from overflow, 2^-500 complex128 ones).
+inline int max_shrink(int prec) { return prec == QS_C128 ? 1000 : 60; }
+
+// A dense 2x2 gate U written as diag(d0, d1) times a unit-diagonal core:
+// form 2: U = diag(u00, u11) [[1, k], [-conj(k), 1]], k = u01 / u00;
+// form 3: U = diag(u01, u10) [[k, 1], [1, -conj(k)]], k = u00 / u01;
+// whichever has |k| <= 1.  Form 0: U diagonal; form 1: anti-diagonal.  Both
+// identities need U unitary; form -1 when that fails by more than 1e-14.
+struct CoreForm {
+    int form;
+    Cx k, d0, d1;
+};
+
+CoreForm core_form(const Cx (&u)[2][2])
+{
+    if (u[0][1] == 0.0 && u[1][0] == 0.0) return {0, 0.0, u[0][0], u[1][1]};
+    if (u[0][0] == 0.0 && u[1][1] == 0.0) return {1, 0.0, u[0][1], u[1][0]};
+    if (std::abs(u[0][0]) >= std::abs(u[0][1])) {
+        const Cx k = u[0][1] / u[0][0];
+        if (std::abs(u[1][0] + u[1][1] * std::conj(k)) > 1e-14) return {-1, 0.0, 0.0, 0.0};
+        return {2, k, u[0][0], u[1][1]};
+    }
+    const Cx k = u[0][0] / u[0][1];
+    if (std::abs(u[1][1] + u[1][0] * std::conj(k)) > 1e-14) return {-1, 0.0, 0.0, 0.0};
+    return {3, k, u[0][1], u[1][0]};
+}
+
+// Device form of a planned pass list, appended to hp / hops / m4 (op
+// indices in the phases are positions in hops; 4x4 ops index m4 in blocks
+// of 32 values).  The ops are lowered on the way: an uncontrolled dense
+// gate becomes its unit-diagonal core (half the multiply-adds) and its
+// diagonal part, like every one-qubit phase, is deferred; the next dense or
+// 4x4 op on that qubit takes the deferred phase into its matrix on the host
+// (free), a NOT moves it, and the last pass multiplies in what is left.
+void serialize(const std::vector<PassPlan>& plan, const std::vector<OpRec>& ops, int TB, int RB, int prec,
+               std::vector<FPass>& hp, std::vector<FOp>& hops, std::vector<double>& m4)
 {
     const int K = TB + RB;
+    Defer d;
     for (size_t p = 0; p < plan.size(); ++p) {
         const PassPlan& P = plan[p];
+        const bool last_pass = p + 1 == plan.size();
+        std::vector<int> local(64, -1);
+        for (int j = 0; j < K; ++j) local[P.S[j]] = j;
         FPass F;
         memset(&F, 0, sizeof(F));
         F.nphases = (int)P.phases.size();
@@ -472,12 +636,160 @@ void serialize(const std::vector<PassPlan>& plan, const std::vector<OpRec>& ops,
         }
         for (size_t ph = 0; ph < P.phases.size(); ++ph) {
             FPhase& Fp = F.ph[ph];
-            const Layout& prev = ph ? P.phases[ph - 1].lay : P.phases[ph].lay;
-            fill_phase(Fp, prev, P.phases[ph].lay, K);
+            const Layout& L = P.phases[ph].lay;
+            const Layout& prev = ph ? P.phases[ph - 1].lay : L;
+            fill_phase(Fp, prev, L, K);
             Fp.op_begin = (int)hops.size();
+            auto reg_bit = [&](int q) {
+                for (int b = 0; b < RB; ++b)
+                    if (L.reg[b] == local[q]) return b;
+                return -1;
+            };
+            auto flush = [&](int q) {  // multiply in the deferred phase of register-bit qubit q
+                if (!d.has[q]) return;
+                hops.push_back(phase_fop(1u << reg_bit(q), 0, 0, std::polar(1.0, d.phi[q])));
+                d.phi[q] = 0.0;
+                d.has[q] = false;
+            };
             for (int idx : P.phases[ph].ops) {
-                hops.push_back(encode_op(ops[idx], P, P.phases[ph].lay));
-                if (src) src->push_back(idx);
+                const OpRec& op = ops[idx];
+                if (op.kind == 2) {
+                    if (op.ctrls.size() == 1 && local[op.ctrls[0]] >= 0) {
+                        d.phi[op.ctrls[0]] += op.angle;
+                        d.has[op.ctrls[0]] = true;
+                    } else {
+                        hops.push_back(encode_op(op, P, L));
+                    }
+                    continue;
+                }
+                if (op.kind == 4) {  // uncontrolled 4x4 on two register bits
+                    const int q1 = op.target, q2 = op.target2;
+                    int b1 = reg_bit(q1), b2 = reg_bit(q2);
+                    Cx m[4][4];
+                    for (int i = 0; i < 4; ++i)
+                        for (int c = 0; c < 4; ++c) {
+                            const double a = ((c & 1) && d.has[q1] ? d.phi[q1] : 0.0) +
+                                             ((c & 2) && d.has[q2] ? d.phi[q2] : 0.0);
+                            m[i][c] = Cx(op.m4[2 * (4 * i + c)], op.m4[2 * (4 * i + c) + 1]) * std::polar(1.0, a);
+                        }
+                    d.phi[q1] = d.phi[q2] = 0.0;
+                    d.has[q1] = d.has[q2] = false;
+                    if (b1 > b2) {  // index bit 0 belongs to b1: exchange the two index bits
+                        Cx t[4][4];
+                        const int sw[4] = {0, 2, 1, 3};
+                        for (int i = 0; i < 4; ++i)
+                            for (int c = 0; c < 4; ++c) t[sw[i]][sw[c]] = m[i][c];
+                        for (int i = 0; i < 4; ++i)
+                            for (int c = 0; c < 4; ++c) m[i][c] = t[i][c];
+                        std::swap(b1, b2);
+                    }
+                    int pair = 0;
+                    while (!(kPairB1[pair] == b1 && kPairB2[pair] == b2)) ++pair;
+                    FOp f;
+                    memset(&f, 0, sizeof(f));
+                    f.kind = kDense4 + pair;
+                    f.aux = (uint32_t)(m4.size() / 32);
+                    for (int i = 0; i < 4; ++i)
+                        for (int c = 0; c < 4; ++c) {
+                            m4.push_back(m[i][c].real());
+                            m4.push_back(m[i][c].imag());
+                        }
+                    hops.push_back(f);
+                    continue;
+                }
+                FOp f = encode_op(op, P, L);
+                const int t = op.target, b = f.rb;
+                const bool uncond = f.rmask == 0 && f.tmask == 0 && f.gmask == 0;
+                if (op.kind == 1) {
+                    if (f.tmask || f.gmask) {  // lane- or tile-dependent exchange: no deferred phase across it
+                        flush(t);
+                        hops.push_back(f);
+                        continue;
+                    }
+                    hops.push_back(f);
+                    if (!d.has[t]) continue;
+                    // X exp(i a x_t) = exp(i a) exp(-i a x_t) X where the controls hold
+                    const double a = d.phi[t];
+                    if (uncond) {
+                        d.gsc *= std::polar(1.0, a);
+                        d.gsc_used = true;
+                        d.phi[t] = -a;
+                    } else if (__builtin_popcount(f.rmask) == 1) {
+                        // exp(i a (x_t xor x_c)) = exp(i a x_t) exp(i a x_c) exp(-2 i a x_t x_c)
+                        const int c = P.S[L.reg[__builtin_ctz(f.rmask)]];
+                        d.phi[c] += a;
+                        d.has[c] = true;
+                        hops.push_back(phase_fop(f.rmask | (1u << b), 0, 0, std::polar(1.0, -2.0 * a)));
+                    } else {
+                        hops.push_back(phase_fop(f.rmask, 0, 0, std::polar(1.0, a)));
+                        hops.push_back(phase_fop(f.rmask | (1u << b), 0, 0, std::polar(1.0, -2.0 * a)));
+                    }
+                    continue;
+                }
+                // dense 2x2 (kind 0)
+                Cx u[2][2];
+                for (int i = 0; i < 2; ++i)
+                    for (int c = 0; c < 2; ++c) u[i][c] = Cx(op.u[2 * (2 * i + c)], op.u[2 * (2 * i + c) + 1]);
+                if (!uncond) {
+                    flush(t);
+                    hops.push_back(f);
+                    continue;
+                }
+                if (d.has[t]) {
+                    u[0][1] *= std::polar(1.0, d.phi[t]);
+                    u[1][1] *= std::polar(1.0, d.phi[t]);
+                }
+                const CoreForm cf = core_form(u);
+                if (cf.form < 0) {  // not unitary to 1e-14: the full matrix, phase folded in
+                    for (int i = 0; i < 2; ++i)
+                        for (int c = 0; c < 2; ++c) {
+                            f.m[2 * (2 * i + c)] = u[i][c].real();
+                            f.m[2 * (2 * i + c) + 1] = u[i][c].imag();
+                        }
+                    f.kind = kDense + 4 * b;
+                    d.phi[t] = 0.0;
+                    d.has[t] = false;
+                    hops.push_back(f);
+                    continue;
+                }
+                static const int kind_of[4] = {kNop, kNot, kCoreA, kCoreB};
+                f.kind = kind_of[cf.form] + (cf.form == 0 ? 0 : 4 * b);
+                for (int k = 0; k < 8; ++k) f.m[k] = 0.0;
+                f.m[0] = cf.k.real();
+                f.m[1] = cf.k.imag();
+                hops.push_back(f);
+                d.gsc *= cf.d0;
+                d.gsc_used = true;
+                d.phi[t] = std::arg(cf.d1 / cf.d0);
+                d.has[t] = true;
+                if (++d.shrink >= max_shrink(prec)) {  // a fixed point in the op structure
+                    hops.push_back(phase_fop(0, 0, 0, d.gsc));
+                    d.gsc = 1.0;
+                    d.shrink = 0;
+                }
+            }
+            if (last_pass && ph + 1 == P.phases.size()) {
+                // multiply in every deferred factor, in the last layout
+                for (int q = 0; q < 64; ++q) {
+                    if (!d.has[q]) continue;
+                    const Cx e = std::polar(1.0, d.phi[q]);
+                    const int j = local[q];
+                    if (j < 0) {
+                        hops.push_back(phase_fop(0, 0, 1ull << q, e));
+                    } else {
+                        int rb = -1, tb = -1;
+                        for (int b = 0; b < RB; ++b)
+                            if (L.reg[b] == j) rb = b;
+                        for (int b = 0; b < TB; ++b)
+                            if (L.thr[b] == j) tb = b;
+                        hops.push_back(rb >= 0 ? phase_fop(1u << rb, 0, 0, e) : phase_fop(0, 1u << tb, 0, e));
+                    }
+                    d.phi[q] = 0.0;
+                    d.has[q] = false;
+                }
+                if (d.gsc_used) hops.push_back(phase_fop(0, 0, 0, d.gsc));
+                d.gsc = 1.0;
+                d.gsc_used = false;
             }
             Fp.op_end = (int)hops.size();
         }
@@ -500,22 +812,23 @@ constexpr Shape kShapes64[] = {{6, 3}, {7, 3}, {8, 3}, {8, 4}, {9, 3}, {8, 5}, {
                                {9, 5}, {10, 4}};
 
 template <typename T, int TB, int RB>
-hipError_t launch_cfg(hipStream_t s, void* amp, const FPass* P, const FOp* ops, uint64_t ntiles)
+hipError_t launch_cfg(hipStream_t s, void* amp, const FPass* P, const FOp* ops, const void* m4, uint64_t ntiles)
 {
     using V = typename C2<T>::type;
     uint64_t grid = ntiles;
     const uint64_t cap = 256ull * 16;
     if (grid > cap) grid = cap;
-    hipLaunchKernelGGL((k_fused<T, TB, RB>), dim3((unsigned)grid), dim3(1 << TB), 0, s, (V*)amp, P, ops, ntiles);
+    hipLaunchKernelGGL((k_fused<T, TB, RB>), dim3((unsigned)grid), dim3(1 << TB), 0, s, (V*)amp, P, ops,
+                       (const T*)m4, ntiles);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_fused_pass(hipStream_t s, const FusedConfig& c, void* amp, const FPass* P, const FOp* ops,
-                             uint64_t ntiles)
+                             const void* m4, uint64_t ntiles)
 {
 #define QS_SHAPE(tb, rb) \
-    if (c.TB == tb && c.RB == rb) return launch_cfg<T, tb, rb>(s, amp, P, ops, ntiles);
+    if (c.TB == tb && c.RB == rb) return launch_cfg<T, tb, rb>(s, amp, P, ops, m4, ntiles);
     QS_SHAPE(6, 3) QS_SHAPE(7, 3) QS_SHAPE(8, 3) QS_SHAPE(8, 4) QS_SHAPE(9, 3)
     QS_SHAPE(9, 4) QS_SHAPE(10, 3)
     if constexpr (sizeof(T) == 4) {
@@ -552,49 +865,74 @@ FusedConfig default_fused_config(int prec, int k, int n)
     return c;
 }
 
-qs_status run_fused_sv(qs_reg r, const std::vector<OpRec>& ops, FusedConfig cfg, int* passes_out)
+// The 4x4 table in the register's precision.
+std::vector<char> m4_bytes(const std::vector<double>& m4, int prec)
+{
+    std::vector<char> out;
+    if (prec == QS_C128) {
+        out.assign((const char*)m4.data(), (const char*)(m4.data() + m4.size()));
+    } else {
+        std::vector<float> f(m4.begin(), m4.end());
+        out.assign((const char*)f.data(), (const char*)(f.data() + f.size()));
+    }
+    if (out.empty()) out.resize(sizeof(double));
+    return out;
+}
+
+qs_status run_fused_sv(qs_reg r, const std::vector<OpRec>& circuit_ops, FusedConfig cfg, int* passes_out)
 {
     if (cfg.max_phases <= 0 || cfg.max_phases > kPhMax) cfg.max_phases = kPhMax;
-    if (cfg.TB == 0 || cfg.TB + cfg.RB > r->n) {  // too small to tile: one kernel per op
-        for (const OpRec& op : ops) {
+    const int nbits = r->nbits;
+    if (cfg.TB == 0 || cfg.TB + cfg.RB > nbits) {  // too small to tile: one kernel per op
+        for (const OpRec& op : circuit_ops) {
             qs_status s = apply_op(r, op);
             if (s) return s;
         }
-        if (passes_out) *passes_out = (int)ops.size();
+        if (passes_out) *passes_out = (int)circuit_ops.size();
         return QS_OK;
     }
+    // a density matrix runs as its 2N-qubit vector (Eq. 2): gates on q and
+    // conj on q + N, channels as 4x4 superoperators on (q, q + N)
+    std::vector<OpRec> dm_ops;
+    if (r->kind == QS_DENSITY) dm_ops = dm_vector_ops(circuit_ops, r->n);
+    const std::vector<OpRec>& ops = r->kind == QS_DENSITY ? dm_ops : circuit_ops;
     const int TB = cfg.TB, RB = cfg.RB, K = TB + RB;
-    std::vector<PassPlan> plan = plan_passes(ops, r->n, TB, RB, cfg.max_phases, 1 << 12, std::min(4, TB));
+    std::vector<PassPlan> plan = plan_passes(ops, nbits, TB, RB, cfg.max_phases, 1 << 12, std::min(4, TB));
 
     // serialise passes + ops
     std::vector<FPass> hp;
     std::vector<FOp> hops;
-    serialize(plan, ops, TB, RB, hp, hops);
+    std::vector<double> m4;
+    serialize(plan, ops, TB, RB, r->prec, hp, hops, m4);
     if (hops.empty()) hops.push_back(FOp{});
+    const std::vector<char> m4b = m4_bytes(m4, r->prec);
 
     const size_t pbytes = hp.size() * sizeof(FPass), obytes = hops.size() * sizeof(FOp);
-    std::vector<char> host(pbytes + obytes);
+    const size_t moff = (pbytes + obytes + 255) & ~(size_t)255;
+    std::vector<char> host(moff + m4b.size());
     memcpy(host.data(), hp.data(), pbytes);
     memcpy(host.data() + pbytes, hops.data(), obytes);
+    memcpy(host.data() + moff, m4b.data(), m4b.size());
     // stream-ordered plan buffer: no device-wide synchronisation, so
     // registers on other streams keep running
     void* dbuf = nullptr;
-    hipError_t e = hipMallocAsync(&dbuf, pbytes + obytes, r->stream);
+    hipError_t e = hipMallocAsync(&dbuf, host.size(), r->stream);
     if (e != hipSuccess) return hip_error(e, "plan buffer");
     // from pageable memory the copy has left `host` when the call returns
-    e = hipMemcpyAsync(dbuf, host.data(), pbytes + obytes, hipMemcpyHostToDevice, r->stream);
+    e = hipMemcpyAsync(dbuf, host.data(), host.size(), hipMemcpyHostToDevice, r->stream);
     if (e != hipSuccess) {
         (void)hipFreeAsync(dbuf, r->stream);
         return hip_error(e, "plan upload");
     }
     const FPass* dP = (const FPass*)dbuf;
     const FOp* dO = (const FOp*)((char*)dbuf + pbytes);
-    const uint64_t ntiles = 1ull << (r->n - K);
+    const void* dM = (const char*)dbuf + moff;
+    const uint64_t ntiles = 1ull << (nbits - K);
     qs_status st = QS_OK;
     for (size_t p = 0; p < hp.size() && st == QS_OK; ++p) {
         st = profiled(r, QS_K_FUSED, [&](int*) {
-            return r->prec == QS_C128 ? launch_fused_pass<double>(r->stream, cfg, r->amp, dP + p, dO, ntiles)
-                                      : launch_fused_pass<float>(r->stream, cfg, r->amp, dP + p, dO, ntiles);
+            return r->prec == QS_C128 ? launch_fused_pass<double>(r->stream, cfg, r->amp, dP + p, dO, dM, ntiles)
+                                      : launch_fused_pass<float>(r->stream, cfg, r->amp, dP + p, dO, dM, ntiles);
         });
     }
     // released once the passes that read it have run
@@ -621,7 +959,8 @@ hipError_t batch_launch_t(qs_batch_s* b, int init)
         const int grid = std::min(count, b->grid);
         hipLaunchKernelGGL((k_batch<T, TB, RB>), dim3(grid), dim3(1 << TB), 0, b->stream,
                            (const BatchReg*)(base + b->off_regs), items + b->level_off[p], count,
-                           (const FPass*)(base + b->off_passes), (const FOp*)(base + b->off_ops), init);
+                           (const FPass*)(base + b->off_passes), (const FOp*)(base + b->off_ops),
+                           (const T*)(base + b->off_m4), init);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -664,10 +1003,16 @@ int batch_occupancy_p(int TB, int RB)
 
 }  // namespace
 
+struct BatchPlans {
+    std::vector<std::vector<PassPlan>> plans;  // per register
+    std::vector<bool> placeholder;             // an empty circuit's identity pass
+};
+
+void batch_plans_free(BatchPlans* p) { delete p; }
+
 qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
                       const std::vector<const std::vector<OpRec>*>& circs, int tile_qubits)
 {
-    b->op_src.clear();
     int nmin = 64;
     for (qs_reg r : regs) nmin = std::min(nmin, r->n);
     const FusedConfig cfg = default_fused_config(b->prec, tile_qubits, nmin);
@@ -677,11 +1022,17 @@ qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
     b->RB = cfg.RB;
     std::vector<FPass> hp;
     std::vector<FOp> hops;
+    std::vector<double> m4;
     std::vector<BatchReg> hr(regs.size());
     const int contig = std::min(4, cfg.TB);
     const int K = cfg.TB + cfg.RB;
     int maxpasses = 0;
     std::vector<uint64_t> per_item(regs.size());
+    std::unique_ptr<BatchPlans> bp(new BatchPlans());
+    b->reg_op_begin.assign(regs.size(), 0);
+    b->reg_op_count.assign(regs.size(), 0);
+    b->reg_m4_begin.assign(regs.size(), 0);
+    b->reg_m4_count.assign(regs.size(), 0);
     for (size_t i = 0; i < regs.size(); ++i) {
         std::vector<OpRec> none;
         const std::vector<OpRec>* ops = circs[i];
@@ -702,18 +1053,20 @@ qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
         hr[i].npasses = (int)plan.size();
         hr[i].pad = 0;
         maxpasses = std::max(maxpasses, (int)plan.size());
-        std::vector<int> src;
-        serialize(plan, *ops, cfg.TB, cfg.RB, hp, hops, &src);
-        // the placeholder of an empty circuit has no source op: updates skip it
-        for (int idx : src) b->op_src.push_back(ops == &none ? std::make_pair(-1, -1) : std::make_pair((int)i, idx));
+        b->reg_op_begin[i] = hops.size();
+        b->reg_m4_begin[i] = m4.size();
+        serialize(plan, *ops, cfg.TB, cfg.RB, b->prec, hp, hops, m4);
+        b->reg_op_count[i] = hops.size() - b->reg_op_begin[i];
+        b->reg_m4_count[i] = m4.size() - b->reg_m4_begin[i];
+        bp->plans.push_back(std::move(plan));
+        bp->placeholder.push_back(ops == &none);
     }
     if (hp.empty()) hp.push_back(FPass{});
-    if (hops.empty()) {
-        hops.push_back(FOp{});
-        b->op_src.push_back({-1, -1});
-    }
+    if (hops.empty()) hops.push_back(FOp{});
     b->circ_ops.assign(circs.begin(), circs.end());
     b->host_ops.assign((const char*)hops.data(), (const char*)(hops.data() + hops.size()));
+    b->host_m4 = m4;
+    const std::vector<char> m4b = m4_bytes(m4, b->prec);
     // items level by level; within a level the largest registers first
     std::vector<uint32_t> byn(regs.size());
     for (size_t i = 0; i < byn.size(); ++i) byn[i] = (uint32_t)i;
@@ -737,12 +1090,14 @@ qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
     b->off_order = align(hr.size() * sizeof(BatchReg));
     b->off_passes = align(b->off_order + items.size() * sizeof(BatchItem));
     b->off_ops = align(b->off_passes + hp.size() * sizeof(FPass));
-    const size_t total = align(b->off_ops + hops.size() * sizeof(FOp));
+    b->off_m4 = align(b->off_ops + hops.size() * sizeof(FOp));
+    const size_t total = align(b->off_m4 + m4b.size());
     std::vector<char> host(total, 0);
     memcpy(host.data() + b->off_regs, hr.data(), hr.size() * sizeof(BatchReg));
     memcpy(host.data() + b->off_order, items.data(), items.size() * sizeof(BatchItem));
     memcpy(host.data() + b->off_passes, hp.data(), hp.size() * sizeof(FPass));
     memcpy(host.data() + b->off_ops, hops.data(), hops.size() * sizeof(FOp));
+    memcpy(host.data() + b->off_m4, m4b.data(), m4b.size());
     hipError_t e = hipMalloc(&b->dbuf, total);
     if (e != hipSuccess) return hip_error(e, "batch plan buffer");
     e = hipMemcpy(b->dbuf, host.data(), total, hipMemcpyHostToDevice);
@@ -751,36 +1106,42 @@ qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
                                           : batch_occupancy_p<float>(cfg.TB, cfg.RB);
     b->grid = (int)(256L * per_cu);
     b->passes_total = (int)hp.size();
+    b->plans = bp.release();
     return QS_OK;
 }
 
 qs_status batch_update(qs_batch_s* b)
 {
+    // lower every register's plan again with the circuits' current values:
+    // the structure (and so the op count) is unchanged, only the kernel data
+    // (matrices, core coefficients, deferred phases) follows the parameters
     FOp* ops = (FOp*)b->host_ops.data();
-    const size_t n = b->host_ops.size() / sizeof(FOp);
-    for (size_t k = 0; k < n; ++k) {
-        const int ci = b->op_src[k].first, oi = b->op_src[k].second;
-        if (ci < 0) continue;
-        const std::vector<OpRec>& cops = *b->circ_ops[ci];
-        if (oi >= (int)cops.size()) return set_error(QS_E_ARG, "a batched circuit lost operations");
-        const OpRec& op = cops[oi];
-        FOp& f = ops[k];
-        if (op.kind == 2) {
-            f.m[0] = cos(op.angle);
-            f.m[1] = sin(op.angle);
-        } else if (op.kind == 0) {
-            // the dense / diagonal choice follows the new matrix; register
-            // bit and condition variant (the low 5 bits) stay
-            const bool diag = op.u[2] == 0.0 && op.u[3] == 0.0 && op.u[4] == 0.0 && op.u[5] == 0.0;
-            f.kind = (diag ? kDiag : kDense) + (f.kind & 31);
-            for (int q = 0; q < 8; ++q) f.m[q] = op.u[q];
+    for (size_t i = 0; i < b->regs.size(); ++i) {
+        if (b->plans->placeholder[i]) continue;
+        std::vector<FPass> hp;
+        std::vector<FOp> hops;
+        std::vector<double> m4;
+        serialize(b->plans->plans[i], *b->circ_ops[i], b->TB, b->RB, b->prec, hp, hops, m4);
+        if (hops.size() != b->reg_op_count[i] || m4.size() != b->reg_m4_count[i])
+            return set_error(QS_E_ARG, "a batched circuit changed its structure");
+        for (size_t k = 0; k < hops.size(); ++k) {
+            FOp f = hops[k];
+            if (f.kind >= kDense4 && f.kind < kDense4 + 10) f.aux += (uint32_t)(b->reg_m4_begin[i] / 32);
+            ops[b->reg_op_begin[i] + k] = f;
         }
+        std::copy(m4.begin(), m4.end(), b->host_m4.begin() + b->reg_m4_begin[i]);
     }
-    // from pageable memory the copy has left host_ops when the call returns;
-    // on the batch stream it follows earlier runs and precedes later ones
-    const hipError_t e = hipMemcpyAsync((char*)b->dbuf + b->off_ops, b->host_ops.data(), b->host_ops.size(),
-                                        hipMemcpyHostToDevice, b->stream);
+    // from pageable memory the copies have left the host tables when the
+    // calls return; on the batch stream they follow earlier runs and precede
+    // later ones
+    hipError_t e = hipMemcpyAsync((char*)b->dbuf + b->off_ops, b->host_ops.data(), b->host_ops.size(),
+                                  hipMemcpyHostToDevice, b->stream);
     if (e != hipSuccess) return hip_error(e, "batch parameter upload");
+    if (!b->host_m4.empty()) {
+        const std::vector<char> m4b = m4_bytes(b->host_m4, b->prec);
+        e = hipMemcpyAsync((char*)b->dbuf + b->off_m4, m4b.data(), m4b.size(), hipMemcpyHostToDevice, b->stream);
+        if (e != hipSuccess) return hip_error(e, "batch parameter upload");
+    }
     return QS_OK;
 }
 

@@ -62,6 +62,8 @@ struct OpRec {
 namespace qs {
 struct JitPlan;
 void jit_plan_free(JitPlan* p);
+struct BatchPlans;
+void batch_plans_free(BatchPlans* p);
 }  // namespace qs
 
 struct qs_circuit_s {
@@ -84,20 +86,22 @@ struct qs_batch_s {
     std::vector<qs_reg> regs;
     std::vector<hipStream_t> reg_streams;  // distinct streams of the registers
     hipEvent_t ev_in, ev_out;
-    void* dbuf = nullptr;          // BatchReg[] + BatchItem[] + FPass[] + FOp[]
-    size_t off_regs, off_order, off_passes, off_ops;
+    void* dbuf = nullptr;          // BatchReg[] + BatchItem[] + FPass[] + FOp[] + 4x4 table
+    size_t off_regs, off_order, off_passes, off_ops, off_m4;
     int nitems = 0;
     std::vector<int> level_off, level_count;  // items of each pass level
     double* dprobs = nullptr;      // 2 doubles per register
     double* hprobs = nullptr;      // pinned copy
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    // parameter updates (qs_batch_update): the circuits, the source (circuit,
-    // op index) of every op slot of the device table (-1: padding), and a
-    // host copy of that table
+    // parameter updates (qs_batch_update): the circuits, their pass plans,
+    // the range of op slots and 4x4 table entries each register's lowered
+    // ops occupy, and host copies of the op table and the 4x4 table
     std::vector<const std::vector<OpRec>*> circ_ops;
-    std::vector<std::pair<int, int>> op_src;
+    qs::BatchPlans* plans = nullptr;
+    std::vector<size_t> reg_op_begin, reg_op_count, reg_m4_begin, reg_m4_count;
     std::vector<char> host_ops;
+    std::vector<double> host_m4;
 };
 
 namespace qs {

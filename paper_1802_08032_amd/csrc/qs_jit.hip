@@ -37,6 +37,7 @@ struct Deferred {
     double phi[64] = {};
     bool has[64] = {};
     std::complex<double> gsc = 1.0;
+    int shrink = 0;  // cores since gsc was last multiplied in
 };
 
 struct GenOut {
@@ -291,6 +292,11 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     std::vector<double> phi(K, 0.0);
     std::vector<bool> has_phi(K, false);
     Cx gsc = in.gsc;
+    int shrink = in.shrink;
+    // every core scales gsc by |d0| >= 1/sqrt 2 and the stored state by the
+    // inverse: after this many cores gsc is multiplied in (2^-30 keeps
+    // complex64 amplitudes far from overflow, 2^-500 complex128 ones)
+    const int max_shrink = dbl ? 1000 : 60;
     bool any_deferred = gsc != Cx(1.0, 0.0);
     for (int j = 0; j < K; ++j) {
         phi[j] = in.phi[P.S[j]];
@@ -594,6 +600,13 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
                     phi[j] = std::arg(cf.d1 / cf.d0);
                     has_phi[j] = true;
                     any_deferred = true;
+                    if (++shrink >= max_shrink) {
+                        std::vector<int> all(E);
+                        for (int r = 0; r < E; ++r) all[r] = r;
+                        mul_regs(all, gsc);
+                        gsc = 1.0;
+                        shrink = 0;
+                    }
                     continue;
                 }
             }
@@ -741,10 +754,8 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
         }
     };
     std::ostringstream pro;  // per-lane constants formed before the tile loop
-    // hand the factors on, unless this is the last pass or the global factor
-    // has become small (|gsc| <= 1 shrinks by each core; the stored state
-    // grows by 1 / |gsc|)
-    const bool multiply_in = last_pass || std::abs(gsc) < (dbl ? 0x1p-300 : 0x1p-30);
+    // hand the factors on, unless this is the last pass
+    const bool multiply_in = last_pass;
     g.out = in;
     if (!multiply_in) {
         if (final_t) emit_relayout(tcount++);
@@ -753,6 +764,7 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
             g.out.has[P.S[j]] = has_phi[j];
         }
         g.out.gsc = gsc;
+        g.out.shrink = shrink;
     } else {
         if (final_t && lane_phases(last) == 0 && lane_phases(P.store) > 0) {
             emit_deferred(last, pro);
@@ -771,6 +783,7 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
                 g.out.has[q] = false;
             }
         g.out.gsc = 1.0;
+        g.out.shrink = 0;
     }
     s << "        const unsigned long long bs = base + stt;\n";
     const std::string fx = flip_expr(streg, true);

@@ -54,11 +54,18 @@ class Result:
         return self.finished - self.arrival
 
 
+# thread bits of the generic fused kernel's tile for each tile width
+# (complex128 takes 9 at 13 qubits: 16 registers per thread, not 32)
+_TB_OF = {9: 6, 10: 7, 11: 8, 12: 8, 13: 8, 14: 9}
+
+
 class GpuExecutor:
     """Runs one request: register on the slot's stream, |0..0>, the circuit
-    (fused for state vectors of at least `min_fused` qubits, one kernel per
-    op otherwise), then measures qubits 0..n-1 in order (one measure-all
-    call: a histogram walk and a single collapse)."""
+    (fused through the generic pass kernel for state vectors of at least
+    `min_fused` qubits and for density matrices whose 2N-qubit vector holds a
+    tile of at least 9 qubits, one kernel per op otherwise), then measures
+    qubits 0..n-1 in order (one measure-all call: a histogram walk and a
+    single collapse)."""
 
     def __init__(self, env: Q.Env, prec: int = Q.C128, slots: int = 8, fusion: int = 12,
                  min_fused: int = 12, keep_amps: bool = False):
@@ -79,8 +86,13 @@ class GpuExecutor:
             try:
                 reg.init_zero()
                 circ = Q.Circuit(req.ops)
-                fused = req.kind == Q.STATEVEC and req.n >= self.min_fused
-                circ.run(reg, self.fusion if fused else 0)
+                if req.kind == Q.DENSITY and 2 * req.n >= 9:
+                    k = min(self.fusion, 2 * req.n, 14 if self.prec == Q.C64 else 13)
+                    tb = 9 if (k == 13 and self.prec == Q.C128) else _TB_OF[k]
+                    circ.run_tiled(reg, k, tb)
+                else:
+                    fused = req.kind == Q.STATEVEC and req.n >= self.min_fused
+                    circ.run(reg, self.fusion if fused else 0)
                 circ.close()
                 outs, probs = reg.measure_all(req.draws[:req.n])
                 amps = reg.get_amps() if self.keep_amps else None

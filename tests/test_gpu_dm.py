@@ -215,3 +215,25 @@ def test_dm_measure_all_matches_sequential_measurement(q, env, N):
     assert max(abs(a - b) for a, b in zip(p, probs)) <= TOL128
     assert max_abs(reg.get_amps(), ref) <= TOL128
     reg.close()
+
+
+@pytest.mark.parametrize('N,tile,tb', [(5, 10, 7), (7, 12, 8), (10, 13, 9)])
+def test_generic_fused_kernel_on_density_matrices(q, env, N, tile, tb):
+    """qs_circuit_run_tiled on a density matrix: the generic pass kernel runs
+    the 2N-qubit vector with uncontrolled gates and their channels as 4x4
+    superoperators, controlled gates as pairs of 2x2 ops (cores with deferred
+    phases where uncontrolled), against the oracle's literal Eq. 2 passes and
+    Kraus sums; at N = 10 each workgroup walks several tiles."""
+    ops = noisy_circuit(N, 4, 40 + N) + random_gate_ops(N, 16, 50 + N, max_controls=2)
+    ref = O.run_dm(N, ops)
+    for prec in (q.C128, q.C64):
+        reg = q.Register(env, N, q.DENSITY, prec)
+        reg.init_zero()
+        c = q.Circuit(ops)
+        passes = c.run_tiled(reg, tile, tb)
+        got = reg.get_amps()
+        c.close()
+        reg.close()
+        err = max_abs(got, ref)
+        log(f'generic fused density matrix N={N} tile={tile} prec={prec}: {passes} passes, max abs error {err:.2e}')
+        assert err <= (TOL128 if prec == q.C128 else 1e-5)

@@ -182,3 +182,31 @@ def test_compiled_run_from_basis_state(q, env, kind_name, prec_name, n, index):
         empty.run_compiled(reg, *tile, init_basis=1 << n)
     empty.close()
     reg.close()
+
+
+@pytest.mark.parametrize('prec_name', ['C64', 'C128'])
+def test_deferred_global_factor_stays_in_range(q, env, prec_name):
+    """800 Hadamards on one register (H H = I, so the state returns to
+    |0..0>): each runs as a core whose deferred factor has magnitude 1/sqrt 2,
+    so without multiplying the global factor in along the way the stored
+    complex64 amplitudes would grow by 2^400 and overflow.  Both fused paths
+    (compiled and generic) must return |0..0>."""
+    from workloads import H, Op
+    prec = getattr(q, prec_name)
+    n = 14
+    ops = [Op('u', target=k % n, u=H) for k in range(2 * n * 28)]
+    tol = 1e-12 if prec == q.C128 else 1e-5
+    for how in ('compiled', 'generic'):
+        reg = q.Register(env, n, q.STATEVEC, prec)
+        reg.init_zero()
+        c = q.Circuit(ops)
+        if how == 'compiled':
+            c.run_compiled(reg, 12, 8, 0, 4)
+        else:
+            c.run(reg, 12)
+        amps = reg.get_amps()
+        c.close()
+        reg.close()
+        log(f'{len(ops)} Hadamards, {how} {prec_name}: |amp[0] - 1| = {abs(amps[0] - 1):.2e}')
+        assert np.all(np.isfinite(amps))
+        assert abs(amps[0] - 1.0) <= tol and np.max(np.abs(amps[1:])) <= tol
