@@ -292,13 +292,19 @@ def batched_leg(q, torch, log, reps=5):
     rng = np.random.Generator(np.random.PCG64(3))
     sizes = [int(v) for v in rng.integers(10, 21, 512)]
     ops = [param_circuit(n, 16, 1000 + i) for i, n in enumerate(sizes)]
+    from paper_1802_08032_amd import autotune
     env = q.Env(0)
     out = {'registers': len(sizes), 'depth': 16, 'gates': int(sum(len(o) for o in ops))}
     amps = {}
     for name, prec in (('c128', q.C128), ('c64', q.C64)):
         regs = [q.Register(env, n, q.STATEVEC, prec) for n in sizes]
         circs = [q.Circuit(o) for o in ops]
-        b = q.Batch(regs, circs, 10)
+        # tile width chosen by the autotuner (graph replays of this batch)
+        tuned = autotune.tune_batch(regs, circs, ops, log=log)
+        out[f'batched_{name}_tile_qubits'] = tuned['tile_qubits']
+        out[f'batched_{name}_autotune'] = [{k: t[k] for k in ('tile_qubits', 'seconds', 'passes')}
+                                           for t in tuned.get('trials', [])]
+        b = q.Batch(regs, circs, tuned['tile_qubits'])
         b.capture(init_zero=True)
         b.replay()
         torch.cuda.synchronize()
@@ -518,7 +524,8 @@ def main():
     ms_per_step = dt / args.steps * 1e3
 
     # dominant kernel: the fused tile pass, one HBM read + write of the state
-    bytes_per_launch = 2 * elem * (1 << n)
+    # (the first pass forms |0..0> and only writes)
+    bytes_per_launch = (2 * passes - 1) * elem * (1 << n) / max(1, passes)
     avg_ms = fused_ms / max(1, launches)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
 

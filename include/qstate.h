@@ -380,11 +380,12 @@ qs_status qs_circuit_source(qs_circuit c, int n, int kind, int prec, int tile_qu
 /* Bind `count` state-vector registers to `count` circuits (circuits[i] runs
  * on regs[i]).  All registers must share one environment and precision and
  * hold at least 9 qubits.  Every circuit is planned into fused passes of
- * tiles of min(tile_qubits, smallest register) qubits (9..13 for QS_C128,
- * 9..14 for QS_C64).  A run is one launch per pass level: launch p
- * applies pass p of every register that has one, its tiles spread over all
+ * tiles of tile_qubits qubits (9..13 for QS_C128, 9..14 for QS_C64); a
+ * register narrower than that is a single tile of its own width.  A run is
+ * one launch per pass level and tile shape: it applies pass p of every
+ * register of that shape that has one, its tiles spread over all
  * workgroups (largest registers first); launch boundaries order a
- * register's passes.  The batch keeps device copies of the
+ * register's passes, and no workgroup waits for another.  The batch keeps device copies of the
  * plans; registers and circuits must outlive it.  Parameter changes
  * (qs_circuit_set_*) are seen after qs_batch_update; adding ops to a
  * batched circuit is not supported.  Work runs on the batch's own stream, ordered after

@@ -949,35 +949,32 @@ qs_status run_fused_sv(qs_reg r, const std::vector<OpRec>& circuit_ops, FusedCon
 namespace {
 
 template <typename T, int TB, int RB>
-hipError_t batch_launch_t(qs_batch_s* b, int init)
+hipError_t batch_launch_t(qs_batch_s* b, const qs_batch_s::Launch& L, int init)
 {
     const char* base = (const char*)b->dbuf;
     const BatchItem* items = (const BatchItem*)(base + b->off_order);
-    for (size_t p = 0; p < b->level_off.size(); ++p) {
-        const int count = b->level_count[p];
-        if (count == 0) continue;
-        const int grid = std::min(count, b->grid);
-        hipLaunchKernelGGL((k_batch<T, TB, RB>), dim3(grid), dim3(1 << TB), 0, b->stream,
-                           (const BatchReg*)(base + b->off_regs), items + b->level_off[p], count,
-                           (const FPass*)(base + b->off_passes), (const FOp*)(base + b->off_ops),
-                           (const T*)(base + b->off_m4), init);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    hipLaunchKernelGGL((k_batch<T, TB, RB>), dim3(std::min(L.count, L.grid)), dim3(1 << TB), 0, b->stream,
+                       (const BatchReg*)(base + b->off_regs), items + L.off, L.count,
+                       (const FPass*)(base + b->off_passes), (const FOp*)(base + b->off_ops),
+                       (const T*)(base + b->off_m4), init);
+    return hipGetLastError();
 }
 
 template <typename T>
 hipError_t batch_launch_p(qs_batch_s* b, int init)
 {
+    for (const qs_batch_s::Launch& L : b->launches) {
+        hipError_t e = hipErrorInvalidValue;
 #define QS_B(tb, rb) \
-    if (b->TB == tb && b->RB == rb) return batch_launch_t<T, tb, rb>(b, init);
-    QS_B(6, 3) QS_B(7, 3) QS_B(8, 3) QS_B(8, 4) QS_B(9, 3) QS_B(9, 4) QS_B(10, 3)
-    if constexpr (sizeof(T) == 4) {
-        QS_B(8, 5) QS_B(9, 5) QS_B(10, 4)
-    }
+    if (L.TB == tb && L.RB == rb) e = batch_launch_t<T, tb, rb>(b, L, init);
+        QS_B(6, 3) QS_B(7, 3) QS_B(8, 3) QS_B(8, 4) QS_B(9, 3) QS_B(9, 4) QS_B(10, 3)
+        if constexpr (sizeof(T) == 4) {
+            QS_B(8, 5) QS_B(9, 5) QS_B(10, 4)
+        }
 #undef QS_B
-    return hipErrorInvalidValue;
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <typename T, int TB, int RB>
@@ -1015,18 +1012,18 @@ qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
 {
     int nmin = 64;
     for (qs_reg r : regs) nmin = std::min(nmin, r->n);
-    const FusedConfig cfg = default_fused_config(b->prec, tile_qubits, nmin);
-    if (cfg.TB == 0 || cfg.TB + cfg.RB > nmin)
-        return set_error(QS_E_ARG, "batched registers need at least 9 qubits and a tile no wider than the smallest");
+    const FusedConfig cfg = default_fused_config(b->prec, tile_qubits, 64);
+    if (cfg.TB == 0 || nmin < 9)
+        return set_error(QS_E_ARG, "batched registers need at least 9 qubits and a tile of 9 or more");
     b->TB = cfg.TB;
     b->RB = cfg.RB;
     std::vector<FPass> hp;
     std::vector<FOp> hops;
     std::vector<double> m4;
     std::vector<BatchReg> hr(regs.size());
-    const int contig = std::min(4, cfg.TB);
-    const int K = cfg.TB + cfg.RB;
     int maxpasses = 0;
+    b->reg_TB.assign(regs.size(), 0);
+    b->reg_RB.assign(regs.size(), 0);
     std::vector<uint64_t> per_item(regs.size());
     std::unique_ptr<BatchPlans> bp(new BatchPlans());
     b->reg_op_begin.assign(regs.size(), 0);
@@ -1044,8 +1041,12 @@ qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
             none.push_back(id);
             ops = &none;
         }
-        std::vector<PassPlan> plan = plan_passes(*ops, regs[i]->n, cfg.TB, cfg.RB, kPhMax, 1 << 12, contig);
-        const uint64_t ntiles = 1ull << (regs[i]->n - K);
+        // a register narrower than the batch tile is one tile of its own width
+        const FusedConfig rc = regs[i]->n >= cfg.TB + cfg.RB ? cfg : default_fused_config(b->prec, regs[i]->n, regs[i]->n);
+        b->reg_TB[i] = rc.TB;
+        b->reg_RB[i] = rc.RB;
+        std::vector<PassPlan> plan = plan_passes(*ops, regs[i]->n, rc.TB, rc.RB, kPhMax, 1 << 12, std::min(4, rc.TB));
+        const uint64_t ntiles = 1ull << (regs[i]->n - (rc.TB + rc.RB));
         per_item[i] = std::max<uint64_t>(1, std::min<uint64_t>(16, ntiles));  // tiles per item
         hr[i].amp = regs[i]->amp;
         hr[i].n = regs[i]->n;
@@ -1055,7 +1056,7 @@ qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
         maxpasses = std::max(maxpasses, (int)plan.size());
         b->reg_op_begin[i] = hops.size();
         b->reg_m4_begin[i] = m4.size();
-        serialize(plan, *ops, cfg.TB, cfg.RB, b->prec, hp, hops, m4);
+        serialize(plan, *ops, rc.TB, rc.RB, b->prec, hp, hops, m4);
         b->reg_op_count[i] = hops.size() - b->reg_op_begin[i];
         b->reg_m4_count[i] = m4.size() - b->reg_m4_begin[i];
         bp->plans.push_back(std::move(plan));
@@ -1072,17 +1073,27 @@ qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
     for (size_t i = 0; i < byn.size(); ++i) byn[i] = (uint32_t)i;
     std::stable_sort(byn.begin(), byn.end(), [&](uint32_t a, uint32_t c) { return hr[a].n > hr[c].n; });
     std::vector<BatchItem> items;
-    b->level_off.clear();
-    b->level_count.clear();
+    b->launches.clear();
+    std::vector<std::pair<int, int>> shapes;  // distinct tile shapes, batch shape first
+    shapes.push_back({cfg.TB, cfg.RB});
+    for (size_t i = 0; i < regs.size(); ++i)
+        if (std::find(shapes.begin(), shapes.end(), std::make_pair(b->reg_TB[i], b->reg_RB[i])) == shapes.end())
+            shapes.push_back({b->reg_TB[i], b->reg_RB[i]});
     for (int p = 0; p < maxpasses; ++p) {
-        b->level_off.push_back((int)items.size());
-        for (uint32_t i : byn) {
-            if (p >= hr[i].npasses) continue;
-            const uint64_t ntiles = 1ull << (hr[i].n - K), per = per_item[i];
-            for (uint64_t t0 = 0; t0 < ntiles; t0 += per)
-                items.push_back(BatchItem{i, (uint32_t)p, (uint32_t)t0, (uint32_t)std::min(ntiles, t0 + per)});
+        for (const auto& sh : shapes) {
+            const int off = (int)items.size();
+            for (uint32_t i : byn) {
+                if (p >= hr[i].npasses || b->reg_TB[i] != sh.first || b->reg_RB[i] != sh.second) continue;
+                const uint64_t ntiles = 1ull << (hr[i].n - (sh.first + sh.second)), per = per_item[i];
+                for (uint64_t t0 = 0; t0 < ntiles; t0 += per)
+                    items.push_back(BatchItem{i, (uint32_t)p, (uint32_t)t0, (uint32_t)std::min(ntiles, t0 + per)});
+            }
+            const int count = (int)items.size() - off;
+            if (count == 0) continue;
+            const int per_cu = b->prec == QS_C128 ? batch_occupancy_p<double>(sh.first, sh.second)
+                                                  : batch_occupancy_p<float>(sh.first, sh.second);
+            b->launches.push_back({sh.first, sh.second, off, count, (int)(256L * per_cu)});
         }
-        b->level_count.push_back((int)items.size() - b->level_off.back());
     }
     b->nitems = (int)items.size();
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -1102,9 +1113,7 @@ qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
     if (e != hipSuccess) return hip_error(e, "batch plan buffer");
     e = hipMemcpy(b->dbuf, host.data(), total, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_error(e, "batch plan upload");
-    const int per_cu = b->prec == QS_C128 ? batch_occupancy_p<double>(cfg.TB, cfg.RB)
-                                          : batch_occupancy_p<float>(cfg.TB, cfg.RB);
-    b->grid = (int)(256L * per_cu);
+    b->grid = b->launches.empty() ? 1 : b->launches.front().grid;
     b->passes_total = (int)hp.size();
     b->plans = bp.release();
     return QS_OK;
@@ -1121,7 +1130,7 @@ qs_status batch_update(qs_batch_s* b)
         std::vector<FPass> hp;
         std::vector<FOp> hops;
         std::vector<double> m4;
-        serialize(b->plans->plans[i], *b->circ_ops[i], b->TB, b->RB, b->prec, hp, hops, m4);
+        serialize(b->plans->plans[i], *b->circ_ops[i], b->reg_TB[i], b->reg_RB[i], b->prec, hp, hops, m4);
         if (hops.size() != b->reg_op_count[i] || m4.size() != b->reg_m4_count[i])
             return set_error(QS_E_ARG, "a batched circuit changed its structure");
         for (size_t k = 0; k < hops.size(); ++k) {

@@ -89,7 +89,14 @@ struct qs_batch_s {
     void* dbuf = nullptr;          // BatchReg[] + BatchItem[] + FPass[] + FOp[] + 4x4 table
     size_t off_regs, off_order, off_passes, off_ops, off_m4;
     int nitems = 0;
-    std::vector<int> level_off, level_count;  // items of each pass level
+    // launches in order: pass level by pass level, one per tile shape that
+    // has items at that level (registers narrower than the batch tile are
+    // one tile of their own width)
+    struct Launch {
+        int TB, RB, off, count, grid;
+    };
+    std::vector<Launch> launches;
+    std::vector<int> reg_TB, reg_RB;  // tile shape of each register
     double* dprobs = nullptr;      // 2 doubles per register
     double* hprobs = nullptr;      // pinned copy
     hipGraph_t graph = nullptr;

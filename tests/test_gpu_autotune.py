@@ -43,3 +43,36 @@ def test_tune_picks_caches_and_matches_the_oracle(tmp_path, monkeypatch):
     circ.close()
     reg.close()
     env.close()
+
+
+def test_tune_batch_picks_caches_and_matches_the_oracle(tmp_path, monkeypatch):
+    """tune_batch times graph replays of the caller's batch at each candidate
+    tile width, keeps the fastest and caches it; the batch at that width
+    reproduces the oracle."""
+    monkeypatch.setenv('QS_TUNE_CACHE', str(tmp_path))
+    import numpy as np
+    import paper_1802_08032_amd as q
+    from paper_1802_08032_amd import autotune
+    from workloads import param_circuit
+    env = q.Env(0)
+    sizes = [10, 12, 14, 16, 11, 13, 15, 10]
+    ops = [param_circuit(n, 6, 70 + i) for i, n in enumerate(sizes)]
+    regs = [q.Register(env, n) for n in sizes]
+    circs = [q.Circuit(o) for o in ops]
+    res = autotune.tune_batch(regs, circs, ops, candidates=[10, 12, 13], log=log)
+    assert res['tile_qubits'] in (10, 12, 13) and len(res['trials']) == 3
+    assert autotune.tune_batch(regs, circs, ops, candidates=[10, 12, 13]).get('cached') is True
+    b = q.Batch(regs, circs, res['tile_qubits'])
+    b.run(init_zero=True)
+    p0, tot = b.probs(0)
+    for i, n in enumerate(sizes):
+        ref = O.run_sv(n, ops[i])
+        assert max_abs(regs[i].get_amps(), ref) <= 1e-12
+        assert abs(p0[i] - O.sv_prob_outcome(ref, n, 0, 0)) <= 1e-12
+    assert np.max(np.abs(tot - 1.0)) <= 1e-12
+    b.close()
+    for c in circs:
+        c.close()
+    for r in regs:
+        r.close()
+    env.close()

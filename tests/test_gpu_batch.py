@@ -6,7 +6,7 @@ import pytest
 
 import oracle as O
 from tests.gpu_util import fidelity_deficit, log, max_abs
-from workloads import param_circuit, random_gate_ops
+from workloads import Op, param_circuit, random_gate_ops, ry, rz
 
 pytestmark = pytest.mark.gpu
 
@@ -116,7 +116,8 @@ def test_c3_workload_512_registers(q, env, prec_name):
     ops = [param_circuit(n, 16, 1000 + i) for i, n in enumerate(sizes)]
     circs = [q.Circuit(o) for o in ops]
     log(f'c3 {prec_name}: 512 registers')
-    b = q.Batch(regs, circs, 10)
+    # registers of 10 and 11 qubits are single tiles of their own width
+    b = q.Batch(regs, circs, 12)
     b.capture(init_zero=True)
     b.replay()
     p0, tot = b.probs(0)
@@ -220,3 +221,45 @@ def test_compiled_circuit_sees_parameter_changes(q, env):
     assert max_abs(reg.get_amps(), O.run_sv(n, no)) <= 1e-12
     c.close()
     reg.close()
+
+
+@pytest.mark.parametrize('prec_name', ['C128', 'C64'])
+def test_registers_narrower_than_the_batch_tile(q, env, prec_name):
+    """A batch tile wider than some registers: those run as single tiles of
+    their own width (own kernel shape, own launches), the rest with the
+    batch tile; eager runs, graph replays and parameter updates all match
+    the oracle."""
+    prec = getattr(q, prec_name)
+    sizes = [9, 14, 10, 11, 13, 12, 15, 9, 12]
+    regs, ops, circs, b = make_batch(q, env, sizes, prec, 3, 60, 13)
+    log(f'batch narrower registers {prec_name}: {b.info()}')
+    tol = 1e-12 if prec == q.C128 else 1e-5
+
+    def check(op_lists):
+        for i, n in enumerate(sizes):
+            ref = O.run_sv(n, op_lists[i])
+            got = regs[i].get_amps()
+            if prec == q.C128:
+                assert max_abs(got, ref) <= tol, (i, n, max_abs(got, ref))
+            else:
+                assert fidelity_deficit(ref, got) <= tol, (i, n)
+    b.run(init_zero=True)
+    check(ops)
+    b.capture(init_zero=True)
+    b.replay()
+    check(ops)
+    # new angles for every rotation, taken into the captured graph
+    rng = np.random.default_rng(5)
+    new_ops = []
+    for c, o in zip(circs, ops):
+        lst = list(o)
+        for k, op in enumerate(lst):
+            if op.kind == 'u':
+                u = ry(float(rng.uniform(0, 6.28))) if abs(op.u[0, 1]) > 0 else rz(float(rng.uniform(0, 6.28)))
+                c.set_unitary(k, u)
+                lst[k] = Op('u', target=op.target, controls=op.controls, u=u)
+        new_ops.append(lst)
+    b.update()
+    b.replay()
+    check(new_ops)
+    close_all(b, regs, circs)
