@@ -374,6 +374,16 @@ qs_status qs_circuit_run_compiled_from_basis(qs_reg r, qs_circuit c, int tile_qu
 qs_status qs_circuit_source(qs_circuit c, int n, int kind, int prec, int tile_qubits, int thread_bits,
                             int max_phases, int contig_qubits, int pass, char* buf, size_t cap,
                             size_t* len, int* n_passes);
+/* Host-only: the kernel data (matrices, core coefficients, deferred
+ * factors) that pass `pass` of the same generated set reads through its
+ * `mats` argument, as doubles (a QS_C64 pass receives them rounded to
+ * float).  Copies min(cap, *len) values into buf (buf may be NULL when
+ * cap is 0); *len gets the full count, *n_passes the pass count.  With the
+ * source this lets a caller run or inspect a pass without a GPU.  Needs
+ * no GPU. */
+qs_status qs_circuit_pass_data(qs_circuit c, int n, int kind, int prec, int tile_qubits, int thread_bits,
+                               int max_phases, int contig_qubits, int pass, double* buf, size_t cap,
+                               size_t* len, int* n_passes);
 
 /* ---- batches: many independent registers in one persistent launch ------- */
 

@@ -1191,9 +1191,12 @@ qs_status qs_circuit_run_compiled_from_basis(qs_reg r, qs_circuit c, int tile_qu
     return qs::run_compiled_sv(r, c, cfg, n_passes, &basis_index);
 }
 
-qs_status qs_circuit_source(qs_circuit c, int n, int kind, int prec, int tile_qubits, int thread_bits,
-                            int max_phases, int contig_qubits, int pass, char* buf, size_t cap, size_t* len,
-                            int* n_passes)
+namespace {
+
+// The generated pass set of `c` for an n-qubit register (sources and kernel data).
+qs_status generated_passes(qs_circuit c, int n, int kind, int prec, int tile_qubits, int thread_bits,
+                           int max_phases, int contig_qubits, std::vector<std::string>& srcs,
+                           std::vector<std::vector<double>>& mats)
 {
     if (!valid_circ(c)) return qs::set_error(QS_E_HANDLE, "invalid circuit handle");
     if (prec != QS_C64 && prec != QS_C128) return qs::set_error(QS_E_ARG, "unknown precision");
@@ -1207,10 +1210,21 @@ qs_status qs_circuit_source(qs_circuit c, int n, int kind, int prec, int tile_qu
         for (int q : op.ctrls)
             if (q >= n) return qs::set_error(QS_E_ARG, "circuit qubit outside the register");
     }
-    std::vector<std::string> srcs;
     qs::FusedConfig cfg{thread_bits, tile_qubits - thread_bits, max_phases};
     cfg.contig = contig_qubits ? contig_qubits : std::min(6, nbits);
-    qs::generate_sources(c->ops, n, kind, prec, cfg, srcs);
+    return qs::generate_sources(c->ops, n, kind, prec, cfg, srcs, &mats);
+}
+
+}  // namespace
+
+qs_status qs_circuit_source(qs_circuit c, int n, int kind, int prec, int tile_qubits, int thread_bits,
+                            int max_phases, int contig_qubits, int pass, char* buf, size_t cap, size_t* len,
+                            int* n_passes)
+{
+    std::vector<std::string> srcs;
+    std::vector<std::vector<double>> mats;
+    qs_status s = generated_passes(c, n, kind, prec, tile_qubits, thread_bits, max_phases, contig_qubits, srcs, mats);
+    if (s) return s;
     if (n_passes) *n_passes = (int)srcs.size();
     if (pass < 0 || pass >= (int)srcs.size()) return qs::set_error(QS_E_ARG, "no such pass");
     const std::string& src = srcs[pass];
@@ -1220,6 +1234,23 @@ qs_status qs_circuit_source(qs_circuit c, int n, int kind, int prec, int tile_qu
         memcpy(buf, src.data(), k);
         buf[k] = '\0';
     }
+    return QS_OK;
+}
+
+qs_status qs_circuit_pass_data(qs_circuit c, int n, int kind, int prec, int tile_qubits, int thread_bits,
+                               int max_phases, int contig_qubits, int pass, double* buf, size_t cap, size_t* len,
+                               int* n_passes)
+{
+    std::vector<std::string> srcs;
+    std::vector<std::vector<double>> mats;
+    qs_status s = generated_passes(c, n, kind, prec, tile_qubits, thread_bits, max_phases, contig_qubits, srcs, mats);
+    if (s) return s;
+    if (n_passes) *n_passes = (int)srcs.size();
+    if (pass < 0 || pass >= (int)srcs.size()) return qs::set_error(QS_E_ARG, "no such pass");
+    const std::vector<double>& m = mats[pass];
+    if (len) *len = m.size();
+    if (cap > 0 && !buf) return qs::set_error(QS_E_ARG, "null buffer");
+    if (cap > 0) memcpy(buf, m.data(), std::min(cap, m.size()) * sizeof(double));
     return QS_OK;
 }
 

@@ -168,7 +168,7 @@ std::vector<OpRec> dm_vector_ops(const std::vector<OpRec>& ops, int N);
 qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passes,
                           const uint64_t* init_index = nullptr);
 qs_status generate_sources(const std::vector<OpRec>& ops, int n, int kind, int prec, FusedConfig cfg,
-                           std::vector<std::string>& out);
+                           std::vector<std::string>& out, std::vector<std::vector<double>>* mats = nullptr);
 // Per-operation execution of one recorded op (qs_api.hip).
 qs_status apply_op(qs_reg r, const OpRec& op);
 

@@ -31,13 +31,16 @@ namespace qs {
 namespace {
 
 // Diagonal factors deferred from pass to pass: the true state is gsc times
-// prod_q exp(i phi[q] x_q) (over global qubits q with has[q]) times the
-// stored state.
+// prod_q mul[q]^(x_q) (over global qubits q with has[q]) times the stored
+// state.
 struct Deferred {
-    double phi[64] = {};
+    std::complex<double> mul[64];
     bool has[64] = {};
     std::complex<double> gsc = 1.0;
-    int shrink = 0;  // cores since gsc was last multiplied in
+    Deferred()
+    {
+        for (std::complex<double>& m : mul) m = 1.0;
+    }
 };
 
 struct GenOut {
@@ -143,7 +146,7 @@ __device__ __forceinline__ void qs_cm(R fr, R fi, V& a)
     r.y = fr * a.y + fi * a.x;
     a = r;
 }
-// Unit-diagonal core of a dense gate: (a, b) <- (a + k b, b - conj(k) a),
+// Unit-diagonal core of a unitary gate: (a, b) <- (a + k b, b - conj(k) a),
 // k = kr + i ki; two multiply-adds per output component.
 __device__ __forceinline__ void qs_core(R kr, R ki, V& a, V& b)
 {
@@ -159,6 +162,57 @@ __device__ __forceinline__ void qs_core(R kr, R ki, V& a, V& b)
     a = na;
     b = nb;
 }
+// Unit-diagonal core of any 2x2 matrix: (a, b) <- (a + k0 b, b + k1 a),
+// k0 = k0r + i k0i, k1 = k1r + i k1i.
+__device__ __forceinline__ void qs_core_g(R k0r, R k0i, R k1r, R k1i, V& a, V& b)
+{
+    V na, nb;
+    na.x = k0r * b.x + a.x;
+    na.x = -k0i * b.y + na.x;
+    na.y = k0r * b.y + a.y;
+    na.y = k0i * b.x + na.y;
+    nb.x = k1r * a.x + b.x;
+    nb.x = -k1i * a.y + nb.x;
+    nb.y = k1r * a.y + b.y;
+    nb.y = k1i * a.x + nb.y;
+    a = na;
+    b = nb;
+}
+// Unit-diagonal core of a 4x4 gate: x_i <- x_i + sum_{j != i} c_ij x_j for
+// the four members at once; c holds the twelve c_ij row by row (j != i),
+// real and imaginary parts interleaved.
+__device__ __forceinline__ void qs_core4(const R (&c)[24], V& a, V& b, V& d, V& e)
+{
+    const V x[4] = {a, b, d, e};
+    V y[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        R re = x[i].x, im = x[i].y;
+        int k = 6 * i;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (j == i) continue;
+            re = c[k] * x[j].x + re;
+            re = -c[k + 1] * x[j].y + re;
+            im = c[k] * x[j].y + im;
+            im = c[k + 1] * x[j].x + im;
+            k += 2;
+        }
+        y[i].x = re;
+        y[i].y = im;
+    }
+    a = y[0];
+    b = y[1];
+    d = y[2];
+    e = y[3];
+}
+// A kernel-data value kept in scalar registers: selecting between two such
+// values per lane then costs a select, not a per-lane load.
+__device__ __forceinline__ R qs_s(R x)
+{
+    asm("" : "+s"(x));
+    return x;
+}
 // Amplitude i of the basis state |idx>.
 __device__ __forceinline__ V qs_basis(unsigned long long i, unsigned long long idx)
 {
@@ -171,37 +225,9 @@ __device__ __forceinline__ V qs_basis(unsigned long long i, unsigned long long i
 
 using Cx = std::complex<double>;
 
-// A dense 2x2 gate U (row-major) written as diag(d0, d1) times a core with
-// unit diagonal: form 2 keeps the amplitudes in place,
-//   U = diag(u00, u11) [[1, k], [-conj(k), 1]],  k = u01 / u00,
-// form 3 exchanges them,
-//   U = diag(u01, u10) [[k, 1], [1, -conj(k)]],  k = u00 / u01,
-// whichever has |k| <= 1.  Form 0: U is diagonal; form 1: anti-diagonal
-// (a pure exchange).  Both identities need U unitary (u10 = -u11 conj(k),
-// resp. u11 = -u10 conj(k)); form -1 when that fails by more than 1e-14.
-struct CoreForm {
-    int form;
-    Cx k, d0, d1;
-};
-
-CoreForm core_form(const Cx (&u)[2][2])
-{
-    if (u[0][1] == 0.0 && u[1][0] == 0.0) return {0, 0.0, u[0][0], u[1][1]};
-    if (u[0][0] == 0.0 && u[1][1] == 0.0) return {1, 0.0, u[0][1], u[1][0]};
-    if (std::abs(u[0][0]) >= std::abs(u[0][1])) {
-        const Cx k = u[0][1] / u[0][0];
-        if (std::abs(u[1][0] + u[1][1] * std::conj(k)) > 1e-14) return {-1, 0.0, 0.0, 0.0};
-        return {2, k, u[0][0], u[1][1]};
-    }
-    const Cx k = u[0][0] / u[0][1];
-    if (std::abs(u[1][1] + u[1][0] * std::conj(k)) > 1e-14) return {-1, 0.0, 0.0, 0.0};
-    return {3, k, u[0][1], u[1][0]};
-}
-
-// `in`: factors deferred by earlier passes.  `last`: multiply every deferred
-// factor in before storing (otherwise they are handed on in GenOut::out, and
-// only multiplied in early when the global factor would leave the range the
-// precision keeps comfortably).
+// `in`: factors deferred by earlier passes.  `last_pass`: multiply every
+// deferred factor in before storing (otherwise the per-qubit factors are
+// handed on in GenOut::out).
 GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB, bool dbl, bool init,
                 const Deferred& in, bool last_pass)
 {
@@ -274,41 +300,46 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     // to the registers right away.  pend[b] names a per-lane bool: where it is
     // true, the registers of every pair on register bit b hold the two
     // amplitudes the other way round.  The flip is folded into the next LDS or
-    // HBM write address, into the matrix of a later gate on bit b (rows and
-    // columns exchanged), or applied with selects when an op needs bit b as a
-    // control or as a target of a 4x4 or phase.
+    // HBM write address, into a later gate on bit b, or applied with selects
+    // when an op needs bit b as a control or as a 4x4 target.
     std::vector<std::string> pend(RB);
     int nflip = 0;
 
-    // Deferred diagonal factors: the true state is gsc times
-    // prod_j exp(i phi[j] x_j) times what the registers hold (x_j: the bit of
-    // tile qubit j).  A dense gate's diagonal part, a one-qubit phase and the
-    // phase a NOT moves around all land here; the next dense op on qubit j
-    // takes exp(i phi[j] x_j) into its matrix on the host, and whatever is
-    // left is multiplied in once before the tile is stored.  Phases refer to
-    // the true state, so they are unaffected by pending flips, except where
-    // they are multiplied into registers: there a flipped lane holds the
-    // amplitude of true bit value 1 in the register of stored bit 0.
-    std::vector<double> phi(K, 0.0);
-    std::vector<bool> has_phi(K, false);
+    // Deferred diagonal factors.  The true state is
+    //   gsc * prod_j mul[j]^(x_j) * prod_{j<k} qmul[j][k]^(x_j x_k)
+    // times what the registers hold (x_j: the bit of tile qubit j; only
+    // entries with has / hasq set).  A dense gate's diagonal part, a
+    // one-qubit phase and the factors a NOT moves around land here; the next
+    // dense or 4x4 op on the qubit takes them into its matrix on the host,
+    // and whatever is left is multiplied in before the tile is stored (the
+    // per-qubit factors only by the last pass).  The factors refer to the
+    // true state, so they are unaffected by pending flips, except where they
+    // are multiplied into registers (a flipped lane holds true bit value 1
+    // in the register of stored bit 0).  Pair factors only ever join two
+    // register-bit qubits with no pending flip.
+    std::vector<Cx> mul(K, 1.0);
+    std::vector<bool> has(K, false);
+    std::vector<std::vector<Cx>> qmul(K, std::vector<Cx>(K, 1.0));
+    std::vector<std::vector<bool>> hasq(K, std::vector<bool>(K, false));
     Cx gsc = in.gsc;
-    int shrink = in.shrink;
-    // every core scales gsc by |d0| >= 1/sqrt 2 and the stored state by the
-    // inverse: after this many cores gsc is multiplied in (2^-30 keeps
-    // complex64 amplitudes far from overflow, 2^-500 complex128 ones)
-    const int max_shrink = dbl ? 1000 : 60;
     bool any_deferred = gsc != Cx(1.0, 0.0);
     for (int j = 0; j < K; ++j) {
-        phi[j] = in.phi[P.S[j]];
-        has_phi[j] = in.has[P.S[j]];
-        any_deferred = any_deferred || has_phi[j];
+        mul[j] = in.mul[P.S[j]];
+        has[j] = in.has[P.S[j]];
+        any_deferred = any_deferred || has[j];
     }
-    // deferred phases of qubits outside the tile (multiplied in by the last
-    // pass, from the tile index: its bit i is the i-th qubit outside S)
+    // factors of qubits outside the tile (multiplied in by the last pass,
+    // from the tile index: its bit i is the i-th qubit outside S)
     std::vector<int> outside;
     for (int q = 0; q < 64; ++q)
         if (local[q] < 0 && in.has[q]) outside.push_back(q);
     any_deferred = any_deferred || (last_pass && !outside.empty());
+    // Cores scale gsc by |d0| and the stored state by the inverse; per-qubit
+    // factors of other magnitude than 1 come from 4x4 cores.  Factors are
+    // multiplied in before the stored state leaves a range the precision
+    // keeps comfortably.
+    const double lo = dbl ? 0x1p-300 : 0x1p-30, hi = 1.0 / lo;
+    const double qlo = dbl ? 0x1p-100 : 0x1p-12, qhi = 1.0 / qlo;
 
     auto materialize = [&](uint32_t bits) {
         for (int b = 0; b < RB; ++b) {
@@ -335,16 +366,57 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
         for (int r : regs) s << " qs_cm(fr, fi, " << vn(r) << ");";
         s << " }\n";
     };
-    // apply the deferred phase of tile qubit j, held at register bit b
-    auto flush_phase = [&](int j, int b) {
-        if (!has_phi[j]) return;
-        materialize(1u << b);
+    auto all_regs_with = [&](uint32_t bits) {
         std::vector<int> regs;
         for (int r = 0; r < E; ++r)
-            if ((r >> b) & 1) regs.push_back(r);
-        mul_regs(regs, std::polar(1.0, phi[j]));
-        phi[j] = 0.0;
-        has_phi[j] = false;
+            if (((uint32_t)r & bits) == bits) regs.push_back(r);
+        return regs;
+    };
+    // current register bit of tile qubit j in layout L (-1: a thread bit)
+    auto reg_bit_in = [&](const Layout& L, int j) {
+        for (int b = 0; b < RB; ++b)
+            if (L.reg[b] == j) return b;
+        return -1;
+    };
+    const Layout* cur = &P.phases.front().lay;
+    auto partners = [&](int j) {
+        std::vector<int> ks;
+        for (int k = 0; k < K; ++k)
+            if (k != j && hasq[j][k]) ks.push_back(k);
+        return ks;
+    };
+    // multiply in the pair factor of (j, k), both register bits
+    auto flush_pair = [&](int j, int k) {
+        if (!hasq[j][k]) return;
+        mul_regs(all_regs_with((1u << reg_bit_in(*cur, j)) | (1u << reg_bit_in(*cur, k))), qmul[j][k]);
+        hasq[j][k] = hasq[k][j] = false;
+        qmul[j][k] = qmul[k][j] = 1.0;
+    };
+    auto flush_pairs_of = [&](int j, int except) {
+        for (int k : partners(j))
+            if (k != except) flush_pair(j, k);
+    };
+    // multiply in every factor of tile qubit j, held at register bit b
+    auto flush_qubit = [&](int j, int b) {
+        flush_pairs_of(j, -1);
+        if (!has[j]) return;
+        materialize(1u << b);
+        mul_regs(all_regs_with(1u << b), mul[j]);
+        mul[j] = 1.0;
+        has[j] = false;
+    };
+    auto keep_in_range = [&]() {
+        for (int j = 0; j < K; ++j)
+            for (int k : partners(j))
+                if (std::abs(qmul[j][k]) < qlo || std::abs(qmul[j][k]) > qhi) flush_pair(j, k);
+        for (int j = 0; j < K; ++j) {
+            const int b = reg_bit_in(*cur, j);
+            if (has[j] && b >= 0 && (std::abs(mul[j]) < qlo || std::abs(mul[j]) > qhi)) flush_qubit(j, b);
+        }
+        if (std::abs(gsc) < lo || std::abs(gsc) > hi) {
+            mul_regs(all_regs_with(0), gsc);
+            gsc = 1.0;
+        }
     };
     auto flip_expr = [&](const std::vector<uint64_t>& img, bool wide) {
         std::string e;
@@ -359,6 +431,11 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     size_t tcount = 0;
     auto emit_relayout = [&](size_t t) {
         const Trans& T = trans[t];
+        // pair factors join register bits only: multiply in those whose
+        // qubits leave the register bits
+        for (int j = 0; j < K; ++j)
+            for (int k : partners(j))
+                if (k > j && (reg_bit_in(*T.to, j) < 0 || reg_bit_in(*T.to, k) < 0)) flush_pair(j, k);
         std::vector<uint64_t> wreg, rreg;
         for (int b = 0; b < RB; ++b) wreg.push_back(T.img[T.from->reg[b]]);
         for (int b = 0; b < RB; ++b) rreg.push_back(T.img[T.to->reg[b]]);
@@ -392,16 +469,13 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
         s << "        QS_BAR();\n";
         for (int r = 0; r < E; ++r) s << "        v" << r << " = w" << t << "_" << r << ";\n";
         for (int r = 0; r < E; ++r) name[r] = r;
+        cur = T.to;
     };
 
     for (size_t ph = 0; ph < P.phases.size(); ++ph) {
         const Layout& L = P.phases[ph].lay;
         if (ph > 0) emit_relayout(tcount++);
-        auto reg_bit = [&](int j) {
-            for (int b = 0; b < RB; ++b)
-                if (L.reg[b] == j) return b;
-            return -1;
-        };
+        auto reg_bit = [&](int j) { return reg_bit_in(L, j); };
         for (int idx : P.phases[ph].ops) {
             const OpRec& op = all[idx];
             uint32_t rmask = 0, tmask = 0;
@@ -427,8 +501,8 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
             // a one-qubit phase on a tile qubit is deferred (no code)
             if (op.kind == 2 && op.ctrls.size() == 1 && local[op.ctrls[0]] >= 0) {
                 const int j = local[op.ctrls[0]];
-                phi[j] += op.angle;
-                has_phi[j] = true;
+                mul[j] *= std::polar(1.0, op.angle);
+                has[j] = true;
                 any_deferred = true;
                 continue;
             }
@@ -439,8 +513,10 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
                 cond = cond.empty() ? t : cond + " && " + t;
             }
             materialize(rmask);  // register controls are read as they stand
-            const size_t off = g.mats.size();
+            // (kernel data offsets are taken right before an op's data is
+            // appended: flushes of deferred factors append their own first)
             if (op.kind == 2) {  // phase on the registers whose masked bits are 1
+                const size_t off = g.mats.size();
                 g.mats.insert(g.mats.end(), {cos(op.angle), sin(op.angle), 0, 0, 0, 0, 0, 0});
                 s << "        {\n            R fr = mt[" << off << "], fi = mt[" << off + 1 << "];\n";
                 if (!cond.empty())
@@ -454,19 +530,97 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
                 const int j1 = local[op.target], j2 = local[op.target2];
                 const int b1 = reg_bit(j1), b2 = reg_bit(j2);
                 materialize((1u << b1) | (1u << b2));
-                // deferred phases of both qubits go into the columns
+                flush_pairs_of(j1, j2);
+                flush_pairs_of(j2, j1);
+                // the deferred factors of both qubits and of the pair go into the columns
                 Cx dcol[4];
-                for (int c = 0; c < 4; ++c)
-                    dcol[c] = std::polar(1.0, ((c & 1) && has_phi[j1] ? phi[j1] : 0.0) +
-                                                  ((c & 2) && has_phi[j2] ? phi[j2] : 0.0));
-                const bool deferred = has_phi[j1] || has_phi[j2];
-                for (int k = 0; k < 16; ++k) {
-                    const Cx m = Cx(op.m4[2 * k], op.m4[2 * k + 1]) * dcol[k % 4];
-                    g.mats.push_back(m.real());
-                    g.mats.push_back(m.imag());
+                for (int c = 0; c < 4; ++c) {
+                    dcol[c] = 1.0;
+                    if ((c & 1) && has[j1]) dcol[c] *= mul[j1];
+                    if ((c & 2) && has[j2]) dcol[c] *= mul[j2];
+                    if (c == 3 && hasq[j1][j2]) dcol[c] *= qmul[j1][j2];
                 }
-                phi[j1] = phi[j2] = 0.0;
-                has_phi[j1] = has_phi[j2] = false;
+                const bool deferred = has[j1] || has[j2] || hasq[j1][j2];
+                Cx m[4][4];
+                for (int i = 0; i < 4; ++i)
+                    for (int c = 0; c < 4; ++c) m[i][c] = Cx(op.m4[2 * (4 * i + c)], op.m4[2 * (4 * i + c) + 1]) * dcol[c];
+                mul[j1] = mul[j2] = 1.0;
+                has[j1] = has[j2] = false;
+                qmul[j1][j2] = qmul[j2][j1] = 1.0;
+                hasq[j1][j2] = hasq[j2][j1] = false;
+                if (cond.empty() && rmask == 0) {
+                    // unit-diagonal core: M = D C P, P a permutation of the
+                    // four members (register renames), D = diag deferred
+                    static const int perms[24][4] = {
+                        {0, 1, 2, 3}, {0, 1, 3, 2}, {0, 2, 1, 3}, {0, 2, 3, 1}, {0, 3, 1, 2}, {0, 3, 2, 1},
+                        {1, 0, 2, 3}, {1, 0, 3, 2}, {1, 2, 0, 3}, {1, 2, 3, 0}, {1, 3, 0, 2}, {1, 3, 2, 0},
+                        {2, 0, 1, 3}, {2, 0, 3, 1}, {2, 1, 0, 3}, {2, 1, 3, 0}, {2, 3, 0, 1}, {2, 3, 1, 0},
+                        {3, 0, 1, 2}, {3, 0, 2, 1}, {3, 1, 0, 2}, {3, 1, 2, 0}, {3, 2, 0, 1}, {3, 2, 1, 0}};
+                    int best = -1;
+                    double bestv = 0.0;
+                    for (int p = 0; p < 24; ++p) {
+                        double v = 1.0;
+                        for (int i = 0; i < 4; ++i) v *= std::abs(m[i][perms[p][i]]);
+                        if (v > bestv) {
+                            bestv = v;
+                            best = p;
+                        }
+                    }
+                    if (best >= 0) {
+                        const int* pi = perms[best];
+                        Cx D[4];
+                        for (int i = 0; i < 4; ++i) D[i] = m[i][pi[i]];
+                        const Cx n1 = D[1] / D[0], n2 = D[2] / D[0], nq = D[3] * D[0] / (D[1] * D[2]);
+                        bool ok = true;
+                        for (const Cx& x : {n1, n2, nq})
+                            ok = ok && std::abs(x) >= qlo && std::abs(x) <= qhi;
+                        double cmax = 0.0;
+                        for (int i = 0; i < 4; ++i)
+                            for (int c = 0; c < 4; ++c)
+                                if (c != i) cmax = std::max(cmax, std::abs(m[i][pi[c]] / D[i]));
+                        ok = ok && cmax <= (dbl ? 1e100 : 1e6);
+                        if (ok) {
+                            // y_i = x_{pi(i)} + sum_{c != i} C[i][c] x_{pi(c)}: the
+                            // member registers in the order pi, outputs in
+                            // place, then renamed to their positions
+                            const size_t off = g.mats.size();
+                            for (int i = 0; i < 4; ++i)
+                                for (int c = 0; c < 4; ++c) {
+                                    if (c == i) continue;
+                                    const Cx cc = m[i][pi[c]] / D[i];
+                                    g.mats.push_back(cc.real());
+                                    g.mats.push_back(cc.imag());
+                                }
+                            s << "        {\n            R c[24];\n";
+                            for (int k = 0; k < 24; ++k) s << "            c[" << k << "] = mt[" << off + k << "];\n";
+                            for (int r0 = 0; r0 < E; ++r0) {
+                                if (((r0 >> b1) & 1) || ((r0 >> b2) & 1)) continue;
+                                const int rr[4] = {r0, r0 | (1 << b1), r0 | (1 << b2), r0 | (1 << b1) | (1 << b2)};
+                                s << "            qs_core4(c, " << vn(rr[pi[0]]) << ", " << vn(rr[pi[1]]) << ", "
+                                  << vn(rr[pi[2]]) << ", " << vn(rr[pi[3]]) << ");\n";
+                                int nn[4];
+                                for (int i = 0; i < 4; ++i) nn[i] = name[rr[pi[i]]];
+                                for (int i = 0; i < 4; ++i) name[rr[i]] = nn[i];
+                            }
+                            s << "        }\n";
+                            gsc *= D[0];
+                            mul[j1] = n1;
+                            mul[j2] = n2;
+                            qmul[j1][j2] = qmul[j2][j1] = nq;
+                            has[j1] = has[j2] = true;
+                            hasq[j1][j2] = hasq[j2][j1] = true;
+                            any_deferred = true;
+                            keep_in_range();
+                            continue;
+                        }
+                    }
+                }
+                const size_t off = g.mats.size();
+                for (int i = 0; i < 4; ++i)
+                    for (int c = 0; c < 4; ++c) {
+                        g.mats.push_back(m[i][c].real());
+                        g.mats.push_back(m[i][c].imag());
+                    }
                 const size_t doff = g.mats.size();
                 if (deferred)
                     for (int c = 0; c < 4; ++c) {
@@ -509,117 +663,190 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
             const int j = local[op.target];
             const int b = reg_bit(j);
             if (op.kind == 1) {  // NOT
-                if (cond.empty()) {
-                    // a permutation of register names (a pending flip on b commutes with it)
-                    for (int r0 = 0; r0 < E; ++r0) {
-                        if ((r0 >> b) & 1) continue;
-                        if (((uint32_t)r0 & rmask) != rmask) continue;
-                        std::swap(name[r0], name[r0 | (1 << b)]);
-                    }
-                    if (!has_phi[j]) continue;
-                    // the stored state went through X where the controls are
-                    // set; keep exp(i phi x_t) deferred for every register:
-                    // X exp(i phi x_t) = exp(i phi) exp(-i phi x_t) X
-                    if (rmask) materialize(1u << b);  // the fix-up below reads true bit values
-                    const double a = phi[j];
+                if (!cond.empty()) {
+                    flush_qubit(j, b);  // a conditional exchange cannot keep a deferred factor
                     if (rmask == 0) {
-                        gsc *= std::polar(1.0, a);
-                        phi[j] = -a;
-                    } else if (__builtin_popcount(rmask) == 1) {
-                        // exp(i a (x_t xor x_c)) = exp(i a x_t) exp(i a x_c) exp(-2 i a x_t x_c)
-                        const int bc = __builtin_ctz(rmask), jc = L.reg[bc];
-                        phi[jc] += a;
-                        has_phi[jc] = true;
-                        std::vector<int> regs;
-                        for (int r = 0; r < E; ++r)
-                            if (((r >> b) & 1) && ((r >> bc) & 1)) regs.push_back(r);
-                        mul_regs(regs, std::polar(1.0, -2.0 * a));
+                        const std::string f = "f" + std::to_string(nflip++);
+                        s << "        const bool " << f << " = " << (pend[b].empty() ? "" : "(" + pend[b] + ") != ")
+                          << "(" << cond << ");\n";
+                        pend[b] = f;
                     } else {
-                        std::vector<int> r0s, r1s;
-                        for (int r = 0; r < E; ++r)
-                            if (((uint32_t)r & rmask) == rmask) (((r >> b) & 1) ? r1s : r0s).push_back(r);
-                        mul_regs(r0s, std::polar(1.0, a));
-                        mul_regs(r1s, std::polar(1.0, -a));
+                        s << "        {\n            const bool c = " << cond << ";\n";
+                        for (int r0 = 0; r0 < E; ++r0) {
+                            if ((r0 >> b) & 1) continue;
+                            if (((uint32_t)r0 & rmask) != rmask) continue;
+                            const std::string A = vn(r0), B = vn(r0 | (1 << b));
+                            s << "            { const V ta = " << A << ", tb = " << B << "; " << A
+                              << ".x = c ? tb.x : ta.x; " << A << ".y = c ? tb.y : ta.y; " << B << ".x = c ? ta.x : tb.x; "
+                              << B << ".y = c ? ta.y : tb.y; }\n";
+                        }
+                        s << "        }\n";
                     }
                     continue;
                 }
-                flush_phase(j, b);  // a conditional exchange cannot keep a deferred phase
-                if (rmask == 0) {
-                    const std::string f = "f" + std::to_string(nflip++);
-                    s << "        const bool " << f << " = " << (pend[b].empty() ? "" : "(" + pend[b] + ") != ") << "("
-                      << cond << ");\n";
-                    pend[b] = f;
-                } else {
-                    s << "        {\n            const bool c = " << cond << ";\n";
-                    for (int r0 = 0; r0 < E; ++r0) {
-                        if ((r0 >> b) & 1) continue;
-                        if (((uint32_t)r0 & rmask) != rmask) continue;
-                        const std::string A = vn(r0), B = vn(r0 | (1 << b));
-                        s << "            { const V ta = " << A << ", tb = " << B << "; " << A << ".x = c ? tb.x : ta.x; "
-                          << A << ".y = c ? tb.y : ta.y; " << B << ".x = c ? ta.x : tb.x; " << B
-                          << ".y = c ? ta.y : tb.y; }\n";
-                    }
-                    s << "        }\n";
+                // the stored state goes through X where the controls are set,
+                // a permutation of register names (a pending flip on b
+                // commutes with it); the deferred factors follow the
+                // substitution x_t -> x_t xor (controls)
+                const int nc = __builtin_popcount(rmask);
+                const int jc = nc == 1 ? L.reg[__builtin_ctz(rmask)] : -1;
+                if (nc > 1) flush_qubit(j, b);
+                if (nc == 1 && (has[j] || !partners(j).empty())) {
+                    materialize(1u << b);  // pair factors join flip-free bits
+                    flush_pairs_of(j, jc);
                 }
+                for (int r0 = 0; r0 < E; ++r0) {
+                    if ((r0 >> b) & 1) continue;
+                    if (((uint32_t)r0 & rmask) != rmask) continue;
+                    std::swap(name[r0], name[r0 | (1 << b)]);
+                }
+                if (nc == 0) {
+                    // x_t -> 1 - x_t: mul^x_t -> mul (1/mul)^x_t; q^(x_t x_k) -> q^x_k (1/q)^(x_t x_k)
+                    if (has[j]) {
+                        gsc *= mul[j];
+                        mul[j] = 1.0 / mul[j];
+                    }
+                    for (int k : partners(j)) {
+                        mul[k] = (has[k] ? mul[k] : Cx(1.0)) * qmul[j][k];
+                        has[k] = true;
+                        qmul[j][k] = qmul[k][j] = 1.0 / qmul[j][k];
+                    }
+                } else if (nc == 1 && (has[j] || hasq[j][jc])) {
+                    // x_t -> x_t xor x_c = x_t + x_c - 2 x_t x_c; (x_t xor x_c) x_c = x_c - x_t x_c
+                    const Cx mt_ = has[j] ? mul[j] : Cx(1.0), q_ = hasq[j][jc] ? qmul[j][jc] : Cx(1.0);
+                    mul[jc] = (has[jc] ? mul[jc] : Cx(1.0)) * mt_ * q_;
+                    has[jc] = true;
+                    qmul[j][jc] = qmul[jc][j] = 1.0 / (mt_ * mt_ * q_);
+                    hasq[j][jc] = hasq[jc][j] = true;
+                }
+                keep_in_range();
                 continue;
             }
-            // dense 2x2; the deferred phase of the target goes into column 1
+            // dense 2x2 on register bit b
             Cx u[2][2];
             for (int i = 0; i < 2; ++i)
                 for (int c = 0; c < 2; ++c) u[i][c] = Cx(op.u[2 * (2 * i + c)], op.u[2 * (2 * i + c) + 1]);
-            const double pj = has_phi[j] ? phi[j] : 0.0;
-            const bool deferred = has_phi[j];
-            if (deferred) {
-                u[0][1] *= std::polar(1.0, pj);
-                u[1][1] *= std::polar(1.0, pj);
-            }
             if (cond.empty() && rmask == 0) {
-                const CoreForm cf = core_form(u);
-                if (cf.form >= 0) {
-                    if (cf.form == 2 || cf.form == 3) {
-                        g.mats.push_back(cf.k.real());
-                        g.mats.push_back(cf.k.imag());
-                        // a lane whose pair on bit b is stored exchanged applies
-                        // X C X, the core of -conj(k); the deferred diagonal
-                        // refers to the true state and is the same for all lanes
-                        if (pend[b].empty())
-                            s << "        { const R kr = mt[" << off << "], ki = mt[" << off + 1 << "];";
-                        else
-                            s << "        { const R kr = (" << pend[b] << ") ? -mt[" << off << "] : mt[" << off
-                              << "], ki = mt[" << off + 1 << "];";
+                if (!pend[b].empty()) flush_pairs_of(j, -1);  // classes and flips do not mix
+                const std::vector<int> ps = partners(j);
+                const int ncls = 1 << ps.size();
+                const Cx mj = has[j] ? mul[j] : Cx(1.0);
+                // class v: the partners' bits; column 1 of U takes mul[j] and
+                // the pair factors of the partners that are set
+                std::vector<Cx> mv(ncls);
+                for (int v = 0; v < ncls; ++v) {
+                    mv[v] = mj;
+                    for (size_t i = 0; i < ps.size(); ++i)
+                        if ((v >> i) & 1) mv[v] *= qmul[j][ps[i]];
+                }
+                // one form for every class (|u00| against |u01 mv|)
+                int form = -1;
+                bool uniform = true;
+                for (int v = 0; v < ncls; ++v) {
+                    int f;
+                    const Cx a01 = u[0][1] * mv[v], a11 = u[1][1] * mv[v];
+                    if (a01 == 0.0 && u[1][0] == 0.0) f = 0;
+                    else if (u[0][0] == 0.0 && a11 == 0.0) f = 1;
+                    else if (std::abs(u[0][0] * a11) >= std::abs(a01 * u[1][0]) && u[0][0] != 0.0 && a11 != 0.0) f = 2;
+                    else if (a01 != 0.0 && u[1][0] != 0.0) f = 3;
+                    else f = -1;
+                    if (v == 0) form = f;
+                    else if (f != form) uniform = false;
+                }
+                if (form >= 0 && uniform) {
+                    // per register pair: a' = a + k0 b, b' = b + k1 a (form 2);
+                    // form 3 is form 2 on the exchanged pair (a rename).  For a
+                    // unitary gate and unit-modulus deferred factors k1 = -conj(k0)
+                    // (one coefficient per class).  A lane whose pair is stored
+                    // exchanged applies X C X: k0 and k1 trade places.
+                    std::vector<Cx> k0s(ncls), k1s(ncls);
+                    bool skew = true;
+                    if (form >= 2)
+                        for (int v = 0; v < ncls; ++v) {
+                            const Cx a01 = u[0][1] * mv[v], a11 = u[1][1] * mv[v];
+                            k0s[v] = form == 2 ? a01 / u[0][0] : u[0][0] / a01;
+                            k1s[v] = form == 2 ? u[1][0] / a11 : a11 / u[1][0];
+                            skew = skew && std::abs(k1s[v] + std::conj(k0s[v])) <= 1e-14 * std::max(1.0, std::abs(k0s[v]));
+                        }
+                    if (form >= 2) {
+                        s << "        {";
+                        if (!pend[b].empty()) s << " const bool f_ = " << pend[b] << ";";
+                        for (int v = 0; v < ncls; ++v) {
+                            const size_t o = g.mats.size();
+                            if (skew) {
+                                // X C X has coefficient -conj(k): the sign of Re k flips
+                                g.mats.insert(g.mats.end(), {k0s[v].real(), k0s[v].imag()});
+                                s << " const R a" << v << " = " << (pend[b].empty() ? "" : "f_ ? -mt[" + std::to_string(o) + "] : ")
+                                  << "mt[" << o << "], b" << v << " = mt[" << o + 1 << "];";
+                                continue;
+                            }
+                            g.mats.insert(g.mats.end(), {k0s[v].real(), k0s[v].imag(), k1s[v].real(), k1s[v].imag()});
+                            if (pend[b].empty()) {
+                                s << " const R a" << v << " = mt[" << o << "], b" << v << " = mt[" << o + 1 << "], c" << v
+                                  << " = mt[" << o + 2 << "], d" << v << " = mt[" << o + 3 << "];";
+                            } else {
+                                s << " const R p" << v << " = qs_s(mt[" << o << "]), q" << v << " = qs_s(mt[" << o + 1
+                                  << "]), r" << v << " = qs_s(mt[" << o + 2 << "]), t" << v << " = qs_s(mt[" << o + 3
+                                  << "]); const R a" << v << " = f_ ? r" << v << " : p" << v << ", b" << v << " = f_ ? t" << v
+                                  << " : q" << v << ", c" << v << " = f_ ? p" << v << " : r" << v << ", d" << v << " = f_ ? q"
+                                  << v << " : t" << v << ";";
+                            }
+                        }
                     }
                     for (int r0 = 0; r0 < E; ++r0) {
                         if ((r0 >> b) & 1) continue;
                         const int r1 = r0 | (1 << b);
-                        if (cf.form == 2) s << " qs_core(kr, ki, " << vn(r0) << ", " << vn(r1) << ");";
-                        if (cf.form == 3) s << " qs_core(kr, ki, " << vn(r1) << ", " << vn(r0) << ");";
-                        if (cf.form == 1 || cf.form == 3) std::swap(name[r0], name[r1]);
+                        int v = 0;
+                        for (size_t i = 0; i < ps.size(); ++i) v |= ((r0 >> reg_bit(ps[i])) & 1) << i;
+                        if (form >= 2) {
+                            const std::string x = form == 2 ? vn(r0) : vn(r1), y = form == 2 ? vn(r1) : vn(r0);
+                            if (skew)
+                                s << " qs_core(a" << v << ", b" << v << ", " << x << ", " << y << ");";
+                            else
+                                s << " qs_core_g(a" << v << ", b" << v << ", c" << v << ", d" << v << ", " << x << ", " << y
+                                  << ");";
+                        }
+                        if (form == 1 || form == 3) std::swap(name[r0], name[r1]);
                     }
-                    if (cf.form == 2 || cf.form == 3) s << " }\n";
-                    gsc *= cf.d0;
-                    phi[j] = std::arg(cf.d1 / cf.d0);
-                    has_phi[j] = true;
+                    if (form >= 2) s << " }\n";
+                    // deferred diagonal: diag(d0, d1) with d0 = u00 (forms 0,
+                    // 2: column 0 is not scaled) or u01 mv (forms 1, 3)
+                    if (form == 0 || form == 2) {
+                        gsc *= u[0][0];
+                        mul[j] = u[1][1] * mj / u[0][0];
+                    } else {
+                        gsc *= u[0][1] * mj;
+                        for (int k : ps) {
+                            mul[k] = (has[k] ? mul[k] : Cx(1.0)) * qmul[j][k];
+                            has[k] = true;
+                            qmul[j][k] = qmul[k][j] = 1.0 / qmul[j][k];
+                        }
+                        mul[j] = u[1][0] / (u[0][1] * mj);
+                    }
+                    has[j] = true;
                     any_deferred = true;
-                    if (++shrink >= max_shrink) {
-                        std::vector<int> all(E);
-                        for (int r = 0; r < E; ++r) all[r] = r;
-                        mul_regs(all, gsc);
-                        gsc = 1.0;
-                        shrink = 0;
-                    }
+                    keep_in_range();
                     continue;
                 }
+                flush_pairs_of(j, -1);
             }
-            // full matrix: lanes or registers the controls exclude keep only
-            // the deferred phase of the target
-            phi[j] = 0.0;
-            has_phi[j] = false;
+            // full matrix: the deferred factor of the target goes into column
+            // 1; lanes or registers the controls exclude keep only that factor
+            flush_pairs_of(j, -1);
+            const Cx ep = has[j] ? mul[j] : Cx(1.0);
+            const bool deferred = has[j];
+            if (deferred) {
+                u[0][1] *= ep;
+                u[1][1] *= ep;
+            }
+            mul[j] = 1.0;
+            has[j] = false;
+            const size_t off = g.mats.size();
             for (int i = 0; i < 2; ++i)
                 for (int c = 0; c < 2; ++c) {
                     g.mats.push_back(u[i][c].real());
                     g.mats.push_back(u[i][c].imag());
                 }
-            const Cx ep = std::polar(1.0, pj);
             if (deferred) {
                 g.mats.push_back(ep.real());
                 g.mats.push_back(ep.imag());
@@ -664,51 +891,54 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     // Deferred factors are multiplied in where they cost least: before the
     // final re-layout if the qubits carrying them all sit in register bits
     // there and not after it.
-    auto lane_phases = [&](const Layout& L) {
+    auto lane_factors = [&](const Layout& L) {
         int c = 0;
-        for (int b = 0; b < TB; ++b) c += has_phi[L.thr[b]] ? 1 : 0;
+        for (int b = 0; b < TB; ++b) c += has[L.thr[b]] ? 1 : 0;
         return c;
     };
     auto emit_deferred = [&](const Layout& L, std::ostringstream& pro) {
         if (!any_deferred) return;
-        // register factor: gsc times the phases of the register-bit qubits
+        // register factor: gsc, the factors of the register-bit qubits and
+        // the pair factors (which join register bits only)
         const size_t roff = g.mats.size();
         for (int r = 0; r < E; ++r) {
-            double a = 0.0;
+            Cx f = gsc;
             for (int b = 0; b < RB; ++b)
-                if (((r >> b) & 1) && has_phi[L.reg[b]]) a += phi[L.reg[b]];
-            const Cx f = gsc * std::polar(1.0, a);
+                if (((r >> b) & 1) && has[L.reg[b]]) f *= mul[L.reg[b]];
+            for (int b = 0; b < RB; ++b)
+                for (int c = b + 1; c < RB; ++c)
+                    if (((r >> b) & 1) && ((r >> c) & 1) && hasq[L.reg[b]][L.reg[c]]) f *= qmul[L.reg[b]][L.reg[c]];
             g.mats.push_back(f.real());
             g.mats.push_back(f.imag());
         }
-        // register bits holding a deferred phase under a pending flip: a
-        // flipped lane keeps true bit value v of such a bit in the register
-        // of stored value 1 - v, so its factor differs by exp(+-i phi)
+        // register bits holding a factor under a pending flip: a flipped
+        // lane keeps true bit value v of such a bit in the register of stored
+        // value 1 - v, so its factor differs by mul^(+-1)
         std::vector<int> fb;
         for (int b = 0; b < RB; ++b)
-            if (!pend[b].empty() && has_phi[L.reg[b]]) fb.push_back(b);
+            if (!pend[b].empty() && has[L.reg[b]]) fb.push_back(b);
         while (fb.size() > 2) {
             materialize(1u << fb.back());
             fb.pop_back();
         }
-        const int nl = lane_phases(L);
+        const int nl = lane_factors(L);
         const bool tilefac = last_pass && !outside.empty();
         if (nl == 0 && fb.empty() && !tilefac) {
             for (int r = 0; r < E; ++r)
                 s << "        qs_cm(mt[" << roff + 2 * r << "], mt[" << roff + 2 * r + 1 << "], " << vn(r) << ");\n";
             return;
         }
-        // lane factor: the phases of the thread-bit qubits, fixed per lane
+        // lane factor: the factors of the thread-bit qubits, fixed per lane
         // (the layout does not change from tile to tile), formed once
         pro << "    V lf;\n    lf.x = (R)1;\n    lf.y = (R)0;\n";
         for (int b = 0; b < TB; ++b) {
-            if (!has_phi[L.thr[b]]) continue;
+            if (!has[L.thr[b]]) continue;
             const size_t o = g.mats.size();
-            g.mats.push_back(cos(phi[L.thr[b]]));
-            g.mats.push_back(sin(phi[L.thr[b]]));
+            g.mats.push_back(mul[L.thr[b]].real());
+            g.mats.push_back(mul[L.thr[b]].imag());
             pro << "    if (tid & " << (1u << b) << "u) qs_cm(mats[" << o << "], mats[" << o + 1 << "], lf);\n";
         }
-        // per tile: the phases of qubits outside the tile, from tables over
+        // per tile: the factors of qubits outside the tile, from tables over
         // 8-bit slices of the tile index
         if (tilefac) {
             std::vector<int> rank(64, -1);  // tile-index bit of each qubit outside S
@@ -716,17 +946,17 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
                 if (local[q] < 0) rank[q] = i++;
             s << "        V tf;\n        tf.x = (R)1;\n        tf.y = (R)0;\n";
             for (int c = 0; c < 8; ++c) {
-                std::vector<int> qs;
+                std::vector<int> qs_;
                 for (int q : outside)
-                    if (rank[q] >= 8 * c && rank[q] < 8 * c + 8) qs.push_back(q);
-                if (qs.empty()) continue;
+                    if (rank[q] >= 8 * c && rank[q] < 8 * c + 8) qs_.push_back(q);
+                if (qs_.empty()) continue;
                 const size_t o = g.mats.size();
                 for (int v = 0; v < 256; ++v) {
-                    double a = 0.0;
-                    for (int q : qs)
-                        if ((v >> (rank[q] - 8 * c)) & 1) a += in.phi[q];
-                    g.mats.push_back(cos(a));
-                    g.mats.push_back(sin(a));
+                    Cx a = 1.0;
+                    for (int q : qs_)
+                        if ((v >> (rank[q] - 8 * c)) & 1) a *= in.mul[q];
+                    g.mats.push_back(a.real());
+                    g.mats.push_back(a.imag());
                 }
                 s << "        { const unsigned ix = (unsigned)((tile >> " << 8 * c << ") & 255ull); qs_cm(mt[" << o
                   << " + 2 * ix], mt[" << o + 1 << " + 2 * ix], tf); }\n";
@@ -739,10 +969,11 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
             s << "        V lf" << v << " = lf;\n";
             if (tilefac) s << "        qs_cm(tf.x, tf.y, lf" << v << ");\n";
             for (size_t i = 0; i < fb.size(); ++i) {
-                const double a = phi[L.reg[fb[i]]] * (((v >> i) & 1) ? -1.0 : 1.0);
+                const Cx mq = mul[L.reg[fb[i]]];
+                const Cx a = ((v >> i) & 1) ? 1.0 / mq : mq;
                 const size_t o = g.mats.size();
-                g.mats.push_back(cos(a));
-                g.mats.push_back(sin(a));
+                g.mats.push_back(a.real());
+                g.mats.push_back(a.imag());
                 s << "        if (" << pend[fb[i]] << ") qs_cm(mt[" << o << "], mt[" << o + 1 << "], lf" << v << ");\n";
             }
         }
@@ -754,36 +985,38 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
         }
     };
     std::ostringstream pro;  // per-lane constants formed before the tile loop
-    // hand the factors on, unless this is the last pass
-    const bool multiply_in = last_pass;
     g.out = in;
-    if (!multiply_in) {
+    if (!last_pass) {
+        // hand the per-qubit factors and gsc on; pair factors are multiplied in
         if (final_t) emit_relayout(tcount++);
+        for (int j = 0; j < K; ++j)
+            for (int k : partners(j))
+                if (k > j) flush_pair(j, k);
         for (int j = 0; j < K; ++j) {
-            g.out.phi[P.S[j]] = phi[j];
-            g.out.has[P.S[j]] = has_phi[j];
+            g.out.mul[P.S[j]] = mul[j];
+            g.out.has[P.S[j]] = has[j];
         }
         g.out.gsc = gsc;
-        g.out.shrink = shrink;
     } else {
-        if (final_t && lane_phases(last) == 0 && lane_phases(P.store) > 0) {
+        if (final_t && lane_factors(last) == 0 && lane_factors(P.store) > 0) {
             emit_deferred(last, pro);
+            any_deferred = false;
+            for (int j = 0; j < K; ++j)
+                for (int k = 0; k < K; ++k) hasq[j][k] = false;
             emit_relayout(tcount++);
         } else {
             if (final_t) emit_relayout(tcount++);
             emit_deferred(P.store, pro);
         }
         for (int j = 0; j < K; ++j) {
-            g.out.phi[P.S[j]] = 0.0;
+            g.out.mul[P.S[j]] = 1.0;
             g.out.has[P.S[j]] = false;
         }
-        if (last_pass)
-            for (int q : outside) {
-                g.out.phi[q] = 0.0;
-                g.out.has[q] = false;
-            }
+        for (int q : outside) {
+            g.out.mul[q] = 1.0;
+            g.out.has[q] = false;
+        }
         g.out.gsc = 1.0;
-        g.out.shrink = 0;
     }
     s << "        const unsigned long long bs = base + stt;\n";
     const std::string fx = flip_expr(streg, true);
@@ -838,6 +1071,7 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     g.src = head.str() + loop.str() + s.str();
     return g;
 }
+
 
 // ---------------------------------------------------------------------------
 // Code-object cache: in memory per (device, source), and on disk under
@@ -985,6 +1219,12 @@ qs_status load_all(int device, const std::vector<std::string>& srcs, std::vector
 
 size_t esz_of(int prec) { return prec == QS_C128 ? sizeof(double) : sizeof(float); }
 
+// Estimated multiply-adds per amplitude (the planner's op costs) at which a
+// compiled pass stops streaming at the HBM rate and its arithmetic sets the
+// time.  complex128 tiles move 16 bytes per amplitude each way; complex64
+// tiles half of that at about the same instruction rate.
+double balance_point(bool dbl) { return dbl ? 120.0 : 60.0; }
+
 // Per-circuit cache of the compiled form for one (register shape, tile).
 struct JitPlan {
     int n = -1, kind = -1, prec = 0, TB = 0, RB = 0, max_phases = 0, contig = 0, device = -1;
@@ -1036,7 +1276,7 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
         const bool dbl = r->prec == QS_C128;
         // compiled plans are reused: worth the slower lookahead partition
         std::vector<PassPlan> plan =
-            plan_passes(ops, nbits, cfg.TB, cfg.RB, cfg.max_phases, 1 << 12, cfg.contig, true);
+            plan_passes(ops, nbits, cfg.TB, cfg.RB, cfg.max_phases, 1 << 12, cfg.contig, true, balance_point(dbl));
         std::vector<OpRec> ext(ops);
         for (PassPlan& P : plan) merge_phase_ops(P, ext);
         std::vector<std::string> srcs;
@@ -1133,23 +1373,26 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
 
 // Source of the specialised kernels for one circuit (inspection / tests).
 qs_status generate_sources(const std::vector<OpRec>& circuit_ops, int n, int kind, int prec, FusedConfig cfg,
-                           std::vector<std::string>& out)
+                           std::vector<std::string>& out, std::vector<std::vector<double>>* mats)
 {
     if (cfg.max_phases <= 0 || cfg.max_phases > kPhMax) cfg.max_phases = kPhMax;
     std::vector<OpRec> dm_ops;
     if (kind == QS_DENSITY) dm_ops = dm_vector_ops(circuit_ops, n);
     const std::vector<OpRec>& ops = kind == QS_DENSITY ? dm_ops : circuit_ops;
     if (kind == QS_DENSITY) n *= 2;
-    std::vector<PassPlan> plan = plan_passes(ops, n, cfg.TB, cfg.RB, cfg.max_phases, 1 << 12, cfg.contig, true);
+    std::vector<PassPlan> plan =
+        plan_passes(ops, n, cfg.TB, cfg.RB, cfg.max_phases, 1 << 12, cfg.contig, true, balance_point(prec == QS_C128));
     std::vector<OpRec> ext(ops);
     for (PassPlan& P : plan) merge_phase_ops(P, ext);
     out.clear();
+    if (mats) mats->clear();
     Deferred carry;
     for (size_t p = 0; p < plan.size(); ++p) {
         GenOut go = generate(plan[p], ext, cfg.TB, cfg.RB, prec == QS_C128, false, carry, p + 1 == plan.size());
         if (go.bad) return set_error(QS_E_ARG, "internal: relayout swizzle outside address bits 0..2");
         carry = go.out;
         out.push_back(go.src);
+        if (mats) mats->push_back(go.mats);
     }
     return QS_OK;
 }

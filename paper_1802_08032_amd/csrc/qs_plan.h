@@ -36,8 +36,12 @@ bool coalesced(const Layout& L, int contig);
 // is read from or written to HBM (contiguous runs of 2^contig amplitudes).
 // lookahead: also try a partition whose tile sets look one pass ahead
 // (slower planning; for plans that are compiled and reused).
+// balance > 0: then move ops between neighbouring passes so that no pass
+// needs much more than `balance` multiply-adds per amplitude while its
+// neighbour needs less (the arithmetic at which a pass stops being bound by
+// HBM), see rebalance().
 std::vector<PassPlan> plan_passes(const std::vector<OpRec>& all, int n, int TB, int RB, int max_phases,
-                                  int max_ops, int contig, bool lookahead = false);
+                                  int max_ops, int contig, bool lookahead = false, double balance = 0.0);
 // Within every phase of P, replace runs of ops that act on at most two
 // register qubits and carry no thread or tile condition by their product
 // (a 2x2 dense op or a 4x4 kind-4 op), wherever that takes fewer

@@ -303,6 +303,126 @@ std::vector<PassPlan> partition(const std::vector<OpRec>& all, int n, int TB, in
     return passes;
 }
 
+double op_cost(const OpRec& op, int nregctrl);
+
+// Estimated multiply-adds per amplitude of a pass's ops (controls inside
+// the tile counted as register controls), plus a charge per LDS re-layout
+// between register layouts (about two dense gates' worth of time where the
+// pass is bound by its arithmetic).
+constexpr double kRelayoutCost = 8.0;
+double pass_cost(const PassPlan& P, const std::vector<OpRec>& all)
+{
+    uint64_t inS = 0;
+    for (int q : P.S) inS |= 1ull << q;
+    double c = 0.0;
+    for (int idx : P.ops) {
+        const OpRec& op = all[idx];
+        int nc = 0;
+        if (op.kind != 2)
+            for (int q : op.ctrls) nc += (inS >> q) & 1;
+        c += op_cost(op, nc);
+    }
+    return c + kRelayoutCost * (P.phases.empty() ? 0 : P.phases.size() - 1);
+}
+
+bool replan(PassPlan& P, const std::vector<OpRec>& all, int TB, int RB, int max_phases, int contig)
+{
+    const size_t want = P.ops.size();
+    std::sort(P.ops.begin(), P.ops.end());
+    P.phases.clear();
+    plan_phases(P, all, TB, RB, max_phases, contig);
+    return P.ops.size() == want;
+}
+
+// Even out the arithmetic of neighbouring passes.  A pass costs about
+// max(hbm, its arithmetic): below `hbm` multiply-adds per amplitude it
+// streams the state at the HBM rate, above it the FP units set its time.
+// Ops move from the end of a pass to the start of the next one (or from the
+// start of a pass to the end of the previous one) while that lowers the sum
+// of the two passes' costs, or keeps it and lowers the larger of the two.  An op can move when its targets lie in the
+// other pass's tile and no op that stays in its pass and shares a qubit
+// with it lies between (so for any two ops sharing a qubit the earlier one
+// still runs in the same or an earlier pass, and within a pass ops run in
+// circuit order).
+void rebalance(std::vector<PassPlan>& passes, const std::vector<OpRec>& all, int TB, int RB, int max_phases,
+               int contig, double hbm)
+{
+    if (hbm <= 0.0 || passes.size() < 2) return;
+    std::vector<double> cost;
+    for (const PassPlan& P : passes) cost.push_back(pass_cost(P, all));
+    auto inside = [&](const PassPlan& P, const OpRec& op) {
+        uint64_t inS = 0;
+        for (int q : P.S) inS |= 1ull << q;
+        return (target_mask(op) & ~inS) == 0;
+    };
+    auto total = [&](double a, double b) { return std::max(hbm, a) + std::max(hbm, b); };
+    // move one op from passes[from] to passes[to] (to = from +- 1); false if none helps
+    auto move_one = [&](size_t from, size_t to, std::vector<char>& stuck) {
+        PassPlan& A = passes[from];
+        PassPlan& B = passes[to];
+        std::vector<int> ops = A.ops;
+        std::sort(ops.begin(), ops.end());
+        const bool fwd = to > from;
+        // the best single move: lower total, or the same total with the
+        // heavier pass lighter (that lets work travel on towards a lighter pass)
+        const double t_old = total(cost[from], cost[to]), m_old = std::max(cost[from], cost[to]);
+        double bt = t_old, bm = m_old, bc0 = 0.0, bc1 = 0.0;
+        PassPlan b0, b1;
+        bool found = false;
+        uint64_t stay = 0;
+        int tried = 0;
+        for (size_t k = 0; k < ops.size() && ops.size() > 1 && tried < 64; ++k) {
+            const int idx = fwd ? ops[ops.size() - 1 - k] : ops[k];
+            const OpRec& op = all[idx];
+            const uint64_t m = qubit_mask(op);
+            if (!stuck[idx] && !(m & stay) && inside(B, op)) {
+                ++tried;
+                PassPlan P0 = A;
+                PassPlan P1 = B;
+                P0.ops.erase(std::find(P0.ops.begin(), P0.ops.end(), idx));
+                P1.ops.push_back(idx);
+                if (replan(P0, all, TB, RB, max_phases, contig) && replan(P1, all, TB, RB, max_phases, contig)) {
+                    const double c0 = pass_cost(P0, all), c1 = pass_cost(P1, all);
+                    const double t = total(c0, c1), mx = std::max(c0, c1);
+                    if (t < bt - 1e-9 || (t < bt + 1e-9 && mx < bm - 1e-9)) {
+                        bt = t;
+                        bm = mx;
+                        bc0 = c0;
+                        bc1 = c1;
+                        b0 = std::move(P0);
+                        b1 = std::move(P1);
+                        found = true;
+                    }
+                } else {
+                    stuck[idx] = 1;  // would need more register layouts than allowed
+                }
+            }
+            stay |= m;
+        }
+        if (!found) return false;
+        A = std::move(b0);
+        B = std::move(b1);
+        cost[from] = bc0;
+        cost[to] = bc1;
+        return true;
+    };
+    std::vector<char> stuck(all.size(), 0);
+    for (int sweep = 0; sweep < 8; ++sweep) {
+        bool moved = false;
+        for (size_t p = 0; p + 1 < passes.size(); ++p) {
+            for (int guard = 0; guard < 256 && cost[p] > hbm && cost[p] > cost[p + 1]; ++guard) {
+                if (!move_one(p, p + 1, stuck)) break;
+                moved = true;
+            }
+            for (int guard = 0; guard < 256 && cost[p + 1] > hbm && cost[p + 1] > cost[p]; ++guard) {
+                if (!move_one(p + 1, p, stuck)) break;
+                moved = true;
+            }
+        }
+        if (!moved) break;
+    }
+}
+
 }  // namespace
 
 // Three partitions (greedy only, with runs, with runs and pairs of runs);
@@ -313,7 +433,7 @@ std::vector<PassPlan> partition(const std::vector<OpRec>& all, int n, int TB, in
 // That costs about as many scans as the candidates squared per pass (tens
 // of milliseconds for a few hundred ops), worth it where a plan is reused.
 std::vector<PassPlan> plan_passes(const std::vector<OpRec>& all, int n, int TB, int RB, int max_phases,
-                                  int max_ops, int contig, bool lookahead)
+                                  int max_ops, int contig, bool lookahead, double balance)
 {
     std::vector<PassPlan> best = partition(all, n, TB, RB, max_phases, max_ops, contig, 0, false);
     for (int mode = 1; mode <= 2; ++mode) {
@@ -324,6 +444,7 @@ std::vector<PassPlan> plan_passes(const std::vector<OpRec>& all, int n, int TB, 
         std::vector<PassPlan> p = partition(all, n, TB, RB, max_phases, max_ops, contig, 2, true);
         if (p.size() < best.size()) best.swap(p);
     }
+    rebalance(best, all, TB, RB, max_phases, contig, balance);
     return best;
 }
 

@@ -100,6 +100,7 @@ SIGNATURES = {
     'qs_circuit_run_compiled': (_i, [_vp, _vp, _i, _i, _i, _i, _PI]),
     'qs_circuit_run_compiled_from_basis': (_i, [_vp, _vp, _i, _i, _i, _i, _u64, _PI]),
     'qs_circuit_source': (_i, [_vp, _i, _i, _i, _i, _i, _i, _i, _i, C.c_char_p, _sz, C.POINTER(_sz), _PI]),
+    'qs_circuit_pass_data': (_i, [_vp, _i, _i, _i, _i, _i, _i, _i, _i, _PD, _sz, C.POINTER(_sz), _PI]),
     'qs_batch_create': (_i, [_vp, _vp, _i, _i, C.POINTER(_vp)]),
     'qs_batch_destroy': (_i, [_vp]),
     'qs_batch_run': (_i, [_vp, _i]),
@@ -525,6 +526,21 @@ class Circuit:
         _check(lib().qs_circuit_source(self.h, n, kind, prec, tile_qubits, thread_bits, max_phases,
                                        contig_qubits, pass_index, buf, ln.value + 1, C.byref(ln), C.byref(npass)))
         return buf.value.decode(), npass.value
+
+    def pass_data(self, n: int, prec: int, tile_qubits: int, thread_bits: int, pass_index: int = 0,
+                  max_phases: int = 0, contig_qubits: int = 0, kind: int = STATEVEC):
+        """Kernel data (float64 numpy array) that `source(...)`'s pass reads
+        through its `mats` argument; host only."""
+        import numpy as np
+        ln, npass = C.c_size_t(), C.c_int()
+        _check(lib().qs_circuit_pass_data(self.h, n, kind, prec, tile_qubits, thread_bits, max_phases,
+                                          contig_qubits, pass_index, None, 0, C.byref(ln), C.byref(npass)))
+        out = np.zeros(max(1, ln.value), dtype=np.float64)
+        _check(lib().qs_circuit_pass_data(self.h, n, kind, prec, tile_qubits, thread_bits, max_phases,
+                                          contig_qubits, pass_index,
+                                          out.ctypes.data_as(C.POINTER(C.c_double)), ln.value,
+                                          C.byref(ln), C.byref(npass)))
+        return out[:ln.value]
 
     def close(self):
         if self.h:

@@ -72,14 +72,16 @@ def test_generated_density_matrix_pass_compiles():
 
 def test_pass_merges_and_deferred_flips_in_source():
     """On the layered brick circuit the generated passes merge runs of
-    register-only gates into 4x4 ops and keep thread-controlled NOTs as
-    per-lane flips instead of register swaps; the passes still compile."""
+    register-only gates into 4x4 ops (applied as unit-diagonal 4x4 cores) and
+    keep thread-controlled NOTs as per-lane flips instead of register swaps;
+    the passes still compile."""
+    import re
     import paper_1802_08032_amd as q
     c = q.Circuit(layered_circuit(32, 10, seed=1, mcphase=True))
     _, npass = c.source(32, q.C128, 12, 8, 0, 0, 4)
     srcs = [c.source(32, q.C128, 12, 8, p, 0, 4)[0] for p in range(npass)]
-    assert any('qs_ap4(m' in s for s in srcs)
-    flips = sum(s.count('const bool f') - s.count('const bool f =') for s in srcs)
+    assert any('qs_core4(c, ' in s for s in srcs)
+    flips = sum(len(re.findall(r'const bool f[0-9]+ = ', s)) for s in srcs)
     swaps = sum(s.count('const V ta =') for s in srcs)
     # a materialised flip swaps the 8 register pairs of a 16-register thread;
     # most thread-controlled NOTs stay flips
