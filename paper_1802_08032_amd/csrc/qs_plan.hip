@@ -371,7 +371,7 @@ void rebalance(std::vector<PassPlan>& passes, const std::vector<OpRec>& all, int
         bool found = false;
         uint64_t stay = 0;
         int tried = 0;
-        for (size_t k = 0; k < ops.size() && ops.size() > 1 && tried < 64; ++k) {
+        for (size_t k = 0; k < ops.size() && ops.size() > 1 && tried < 24; ++k) {
             const int idx = fwd ? ops[ops.size() - 1 - k] : ops[k];
             const OpRec& op = all[idx];
             const uint64_t m = qubit_mask(op);
@@ -435,17 +435,67 @@ void rebalance(std::vector<PassPlan>& passes, const std::vector<OpRec>& all, int
 std::vector<PassPlan> plan_passes(const std::vector<OpRec>& all, int n, int TB, int RB, int max_phases,
                                   int max_ops, int contig, bool lookahead, double balance)
 {
-    std::vector<PassPlan> best = partition(all, n, TB, RB, max_phases, max_ops, contig, 0, false);
-    for (int mode = 1; mode <= 2; ++mode) {
-        std::vector<PassPlan> p = partition(all, n, TB, RB, max_phases, max_ops, contig, mode, false);
-        if (p.size() <= best.size()) best.swap(p);
+    std::vector<std::vector<PassPlan>> cands;
+    for (int mode = 0; mode <= 2; ++mode) cands.push_back(partition(all, n, TB, RB, max_phases, max_ops, contig, mode, false));
+    if (lookahead) cands.push_back(partition(all, n, TB, RB, max_phases, max_ops, contig, 2, true));
+    if (lookahead && balance > 0.0) {
+        // where a pass is well above the balance point: partitions whose
+        // passes take at most 1.5, 1.75 or 2 times the average op count
+        // (lighter passes, possibly more of them)
+        const std::vector<PassPlan>& la = cands.back();
+        double heaviest = 0.0;
+        for (const PassPlan& P : la) heaviest = std::max(heaviest, pass_cost(P, all));
+        const double avg = (double)all.size() / std::max<size_t>(1, la.size());
+        if (heaviest > 1.25 * balance)
+            for (double f : {1.25, 1.4, 1.5, 1.6, 1.75, 2.0}) {
+                const int cap = (int)ceil(f * avg);
+                if (cap < max_ops) cands.push_back(partition(all, n, TB, RB, max_phases, cap, contig, 2, true));
+            }
     }
-    if (lookahead) {
-        std::vector<PassPlan> p = partition(all, n, TB, RB, max_phases, max_ops, contig, 2, true);
-        if (p.size() < best.size()) best.swap(p);
+    if (balance <= 0.0) {
+        // fewest passes; the later candidate on ties
+        size_t b = 0;
+        for (size_t i = 1; i < cands.size(); ++i)
+            if (cands[i].size() < cands[b].size() || (cands[i].size() == cands[b].size() && i < 3)) b = i;
+        return cands[b];
     }
-    rebalance(best, all, TB, RB, max_phases, contig, balance);
-    return best;
+    // with a balance point: the lowest estimated time, sum over passes of
+    // max(balance, arithmetic) plus a fifth of the smaller of the two (the
+    // overlap of streaming and arithmetic is not perfect), after balancing
+    // the three best distinct candidates
+    auto estimate = [&](const std::vector<PassPlan>& c) {
+        double t = 0.0;
+        for (const PassPlan& P : c) {
+            const double a = pass_cost(P, all);
+            t += std::max(balance, a) + 0.2 * std::min(balance, a);
+        }
+        return t;
+    };
+    auto same = [](const std::vector<PassPlan>& x, const std::vector<PassPlan>& y) {
+        if (x.size() != y.size()) return false;
+        for (size_t p = 0; p < x.size(); ++p)
+            if (x[p].S != y[p].S || x[p].ops != y[p].ops) return false;
+        return true;
+    };
+    std::vector<std::pair<double, size_t>> order;
+    for (size_t i = 0; i < cands.size(); ++i) {
+        bool dup = false;
+        for (auto& o : order) dup = dup || same(cands[o.second], cands[i]);
+        if (!dup) order.push_back({estimate(cands[i]), i});
+    }
+    std::sort(order.begin(), order.end());
+    size_t b = order[0].second;
+    double best = 1e300;
+    for (size_t r = 0; r < std::min<size_t>(3, order.size()); ++r) {
+        const size_t i = order[r].second;
+        rebalance(cands[i], all, TB, RB, max_phases, contig, balance);
+        const double t = estimate(cands[i]);
+        if (t < best - 1e-9) {
+            best = t;
+            b = i;
+        }
+    }
+    return cands[b];
 }
 
 namespace {
