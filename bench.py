@@ -420,7 +420,10 @@ def serving_leg(q, torch, log, count=200):
     density matrices of 8..13 qubits, log-uniform sizes, depth 5..40, every
     qubit measured at the end), admitted by HBM bytes against 256 GiB with 8
     concurrent slots: a closed-loop run (all requests at t = 0) gives the
-    capacity, then Poisson arrivals at 0.8 x that rate give the latencies."""
+    capacity, then Poisson arrivals at 0.8 x that rate give the latencies.
+    Each precision runs twice: every request on its own stream, and with
+    state vectors of up to 20 qubits batched through qs_batch
+    ('batched': batch jobs once 4 such requests wait)."""
     from paper_1802_08032_amd.serve import GpuExecutor, Request, Server
     from workloads import serving_requests
 
@@ -430,19 +433,21 @@ def serving_leg(q, torch, log, count=200):
 
     out = {'requests': count, 'budget_gib': 256, 'slots': 8}
     for name, prec in (('c128', q.C128), ('c64', q.C64)):
-        env = q.Env(0)
-        ex = GpuExecutor(env, prec, slots=8)
-        srv = Server(ex, budget_bytes=256 << 30, slots=8)
-        closed = srv.summary(srv.serve(reqs(0.0)))
-        rate = 0.8 * closed['circuits_per_s']
-        res = srv.serve(reqs(rate))
-        opened = dict(srv.summary(res), arrival_rate=rate)
-        out[name] = {'closed_loop': closed, 'open_loop': opened}
-        log(f"serving {name}: {closed['circuits_per_s']:.2f} circuits/s closed loop; open loop at "
-            f"{rate:.2f}/s: p50 {opened['latency_p50_s']:.3f} s, p99 {opened['latency_p99_s']:.3f} s")
-        del ex, srv
-        env.close()
-        torch.cuda.empty_cache()
+        for batched in (False, True):
+            env = q.Env(0)
+            ex = GpuExecutor(env, prec, slots=8, batch_max_qubits=20 if batched else 0)
+            srv = Server(ex, budget_bytes=256 << 30, slots=8, batch_min=4, batch_max=64)
+            closed = srv.summary(srv.serve(reqs(0.0)))
+            rate = 0.8 * closed['circuits_per_s']
+            res = srv.serve(reqs(rate))
+            opened = dict(srv.summary(res), arrival_rate=rate)
+            key = name + ('_batched' if batched else '')
+            out[key] = {'closed_loop': closed, 'open_loop': opened}
+            log(f"serving {key}: {closed['circuits_per_s']:.2f} circuits/s closed loop; open loop at "
+                f"{rate:.2f}/s: p50 {opened['latency_p50_s']:.3f} s, p99 {opened['latency_p99_s']:.3f} s")
+            del ex, srv
+            env.close()
+            torch.cuda.empty_cache()
     return out
 
 

@@ -58,6 +58,18 @@ hipError_t dev_alloc(void** p, size_t bytes)
     return hipMalloc(p, bytes);
 }
 
+// dev_alloc on a stream (stream-ordered; no device-wide synchronisation)
+hipError_t dev_alloc_async(void** p, size_t bytes, hipStream_t s)
+{
+    {
+        std::lock_guard<std::mutex> g(g_alloc_mu);
+        ++g_alloc_count;
+        const char* f = getenv("QS_FAULT_ALLOC");
+        if (f && atol(f) == g_alloc_count) return hipErrorOutOfMemory;
+    }
+    return hipMallocAsync(p, bytes, s);
+}
+
 bool valid_env(qs_env e) { return e && handle_live(e) && e->magic == kEnvMagic; }
 bool valid_reg(qs_reg r) { return r && handle_live(r) && r->magic == kRegMagic; }
 bool valid_circ(qs_circuit c) { return c && handle_live(c) && c->magic == kCircMagic; }
@@ -1259,11 +1271,14 @@ qs_status qs_circuit_pass_data(qs_circuit c, int n, int kind, int prec, int tile
 
 static void batch_free(qs_batch b)
 {
+    if (b->stream) (void)hipStreamSynchronize(b->stream);  // uploads read host buffers freed below
     qs::batch_plans_free(b->plans);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    if (b->dbuf) (void)hipFree(b->dbuf);
-    if (b->dprobs) (void)hipFree(b->dprobs);
+    // stream-ordered frees (the batch's own work is complete: callers
+    // synchronise its stream first)
+    if (b->dbuf) (void)(b->stream ? hipFreeAsync(b->dbuf, b->stream) : hipFree(b->dbuf));
+    if (b->dprobs) (void)(b->stream ? hipFreeAsync(b->dprobs, b->stream) : hipFree(b->dprobs));
     if (b->hprobs) (void)hipHostFree(b->hprobs);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
@@ -1306,8 +1321,7 @@ qs_status qs_batch_create(const qs_reg* regs, const qs_circuit* circuits, int co
     hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
-    if (e == hipSuccess) e = dev_alloc((void**)&b->dprobs, 2 * sizeof(double) * count);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&b->hprobs, 2 * sizeof(double) * count, hipHostMallocDefault);
+    if (e == hipSuccess) e = dev_alloc_async((void**)&b->dprobs, 2 * sizeof(double) * count, b->stream);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         batch_free(b);
@@ -1435,6 +1449,8 @@ qs_status qs_batch_probs(qs_batch b, int qubit, double* p0, double* total)
     if (s) return s;
     s = batch_profiled(b, [](qs_batch bb, int q) { return qs::batch_probs_launch(bb, q, bb->dprobs); }, qubit);
     if (s) return s;
+    if (!b->hprobs)  // pinned, on first use (batches that never read probabilities need none)
+        QS_HIP(hipHostMalloc((void**)&b->hprobs, 2 * sizeof(double) * b->count, hipHostMallocDefault));
     QS_HIP(hipMemcpyAsync(b->hprobs, b->dprobs, 2 * sizeof(double) * b->count, hipMemcpyDeviceToHost, b->stream));
     QS_HIP(hipStreamSynchronize(b->stream));
     for (int i = 0; i < b->count; ++i) {

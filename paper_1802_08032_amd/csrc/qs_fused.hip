@@ -1046,8 +1046,7 @@ qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
         b->reg_TB[i] = rc.TB;
         b->reg_RB[i] = rc.RB;
         std::vector<PassPlan> plan = plan_passes(*ops, regs[i]->n, rc.TB, rc.RB, kPhMax, 1 << 12, std::min(4, rc.TB));
-        const uint64_t ntiles = 1ull << (regs[i]->n - (rc.TB + rc.RB));
-        per_item[i] = std::max<uint64_t>(1, std::min<uint64_t>(16, ntiles));  // tiles per item
+        per_item[i] = 1ull << (regs[i]->n - (rc.TB + rc.RB));  // tile count, for now
         hr[i].amp = regs[i]->amp;
         hr[i].n = regs[i]->n;
         hr[i].pass0 = (uint32_t)hp.size();
@@ -1062,6 +1061,12 @@ qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
         bp->plans.push_back(std::move(plan));
         bp->placeholder.push_back(ops == &none);
     }
+    // tiles per work item: up to 16, fewer when the batch holds too few
+    // tiles to give the 256 CUs about 8 items each
+    uint64_t total_tiles = 0;
+    for (uint64_t t : per_item) total_tiles += t;
+    const uint64_t per = std::max<uint64_t>(1, std::min<uint64_t>(16, (total_tiles + 2047) / 2048));
+    for (uint64_t& t : per_item) t = std::min(t, per);
     if (hp.empty()) hp.push_back(FPass{});
     if (hops.empty()) hops.push_back(FOp{});
     b->circ_ops.assign(circs.begin(), circs.end());
@@ -1109,9 +1114,12 @@ qs_status batch_build(qs_batch_s* b, const std::vector<qs_reg>& regs,
     memcpy(host.data() + b->off_passes, hp.data(), hp.size() * sizeof(FPass));
     memcpy(host.data() + b->off_ops, hops.data(), hops.size() * sizeof(FOp));
     memcpy(host.data() + b->off_m4, m4b.data(), m4b.size());
-    hipError_t e = hipMalloc(&b->dbuf, total);
+    // stream-ordered allocation and upload: creating a batch does not wait
+    // for work on other streams (a plain free or a synchronous copy would)
+    b->host_plan = std::move(host);
+    hipError_t e = hipMallocAsync(&b->dbuf, total, b->stream);
     if (e != hipSuccess) return hip_error(e, "batch plan buffer");
-    e = hipMemcpy(b->dbuf, host.data(), total, hipMemcpyHostToDevice);
+    e = hipMemcpyAsync(b->dbuf, b->host_plan.data(), total, hipMemcpyHostToDevice, b->stream);
     if (e != hipSuccess) return hip_error(e, "batch plan upload");
     b->grid = b->launches.empty() ? 1 : b->launches.front().grid;
     b->passes_total = (int)hp.size();
@@ -1147,8 +1155,9 @@ qs_status batch_update(qs_batch_s* b)
                                   hipMemcpyHostToDevice, b->stream);
     if (e != hipSuccess) return hip_error(e, "batch parameter upload");
     if (!b->host_m4.empty()) {
-        const std::vector<char> m4b = m4_bytes(b->host_m4, b->prec);
-        e = hipMemcpyAsync((char*)b->dbuf + b->off_m4, m4b.data(), m4b.size(), hipMemcpyHostToDevice, b->stream);
+        b->host_m4b = m4_bytes(b->host_m4, b->prec);
+        e = hipMemcpyAsync((char*)b->dbuf + b->off_m4, b->host_m4b.data(), b->host_m4b.size(), hipMemcpyHostToDevice,
+                           b->stream);
         if (e != hipSuccess) return hip_error(e, "batch parameter upload");
     }
     return QS_OK;

@@ -109,6 +109,9 @@ struct qs_batch_s {
     std::vector<size_t> reg_op_begin, reg_op_count, reg_m4_begin, reg_m4_count;
     std::vector<char> host_ops;
     std::vector<double> host_m4;
+    // host sources of the asynchronous uploads on the batch stream (kept
+    // until the batch is destroyed)
+    std::vector<char> host_plan, host_m4b;
 };
 
 namespace qs {

@@ -7,12 +7,22 @@ admission counts the register's bytes (16 * 2^n, or 16 * 4^n for a density
 matrix, halved in complex64) against a budget.  Every admitted request runs
 on its own HIP stream in a worker thread, so requests that arrive while
 others are on the GPU start right away and their kernels overlap on the
-device.  Per request the loop records arrival, admission and completion
+device.  With batching on (GpuExecutor batch_max_qubits > 0), small
+state-vector requests are admitted together when a queue has formed: with
+at least `batch_min` of them pending, every pending one (up to `batch_max`)
+joins one batch job, which runs all their circuits through one qs_batch
+launch per pass level and tile shape on one slot.  Below that each runs
+alone, as a batch of one, so that its rounding is the same either way.
+Batching raises throughput under a backlog (fewer launches, one plan
+upload per job) and costs latency at light load (a job finishes with its
+slowest member, and a batch of one carries the batch set-up), so it is off
+by default.  Per request the loop records arrival, admission and completion
 times; `summary` gives p50 / p99 latency, circuits/s and the time-averaged
 HBM occupancy.
 
 The scheduling logic is independent of the executor, which only needs
-`nbytes(request)` and `run(request, slot)`.
+`nbytes(request)` and `run(request, slot)`; one that also has
+`batchable(request)` and `run_batch(requests, slot)` gets batch jobs.
 """
 from __future__ import annotations
 
@@ -61,24 +71,64 @@ _TB_OF = {9: 6, 10: 7, 11: 8, 12: 8, 13: 8, 14: 9}
 
 class GpuExecutor:
     """Runs one request: register on the slot's stream, |0..0>, the circuit
-    (fused through the generic pass kernel for state vectors of at least
-    `min_fused` qubits and for density matrices whose 2N-qubit vector holds a
-    tile of at least 9 qubits, one kernel per op otherwise), then measures
-    qubits 0..n-1 in order (one measure-all call: a histogram walk and a
-    single collapse)."""
+    (state vectors of 9..batch_max_qubits qubits through qs_batch; other
+    state vectors of at least `min_fused` qubits fused through the generic
+    pass kernel; density matrices whose 2N-qubit vector holds a tile of at
+    least 9 qubits through the generic kernel's tiles; one kernel per op
+    otherwise), then measures qubits 0..n-1 in order (one measure-all call:
+    a histogram walk and a single collapse)."""
 
     def __init__(self, env: Q.Env, prec: int = Q.C128, slots: int = 8, fusion: int = 12,
-                 min_fused: int = 12, keep_amps: bool = False):
+                 min_fused: int = 12, keep_amps: bool = False, batch_max_qubits: int = 0,
+                 batch_tile: int = 12):
         import torch
         self.torch = torch
         self.env, self.prec, self.fusion, self.min_fused = env, prec, fusion, min_fused
         self.keep_amps = keep_amps
+        # state vectors of 9..batch_max_qubits qubits go through qs_batch
+        # (0 turns batching off)
+        self.batch_max_qubits, self.batch_tile = batch_max_qubits, batch_tile
         self.streams = [torch.cuda.Stream(device=env.device) for _ in range(slots)]
+
+    def batchable(self, req: Request) -> bool:
+        return req.kind == Q.STATEVEC and 9 <= req.n <= self.batch_max_qubits
+
+    def run_batch(self, reqs, slot: int):
+        """All `reqs` (batchable) on one slot: their registers, one qs_batch
+        run from |0..0>, then each register's measure-all.  A register's
+        arithmetic depends only on its own circuit and the batch tile width,
+        so its result is the same in any batch."""
+        torch = self.torch
+        stream = self.streams[slot]
+        regs, circs, out = [], [], []
+        with torch.cuda.stream(stream):
+            try:
+                for r in reqs:
+                    regs.append(Q.Register(self.env, r.n, Q.STATEVEC, self.prec, stream=stream))
+                    circs.append(Q.Circuit(r.ops))
+                b = Q.Batch(regs, circs, self.batch_tile)
+                try:
+                    b.run(init_zero=True)
+                finally:
+                    b.close()
+                for r, reg in zip(reqs, regs):
+                    outs, probs = reg.measure_all(r.draws[:r.n])
+                    out.append((outs, probs, reg.get_amps() if self.keep_amps else None))
+            finally:
+                for c in circs:
+                    c.close()
+                for reg in regs:
+                    reg.close()
+        return out
 
     def nbytes(self, req: Request) -> int:
         return Q.reg_bytes(req.n, req.kind, self.prec)
 
     def run(self, req: Request, slot: int):
+        if self.batchable(req):
+            # a batch of one: the same kernels as in a batch job, so a
+            # request's result does not depend on whether it was batched
+            return self.run_batch([req], slot)[0]
         torch = self.torch
         stream = self.streams[slot]
         with torch.cuda.stream(stream):
@@ -106,6 +156,8 @@ class Server:
     executor: object
     budget_bytes: int = 256 << 30
     slots: int = 8
+    batch_min: int = 4   # pending small requests that make a batch job
+    batch_max: int = 64  # requests per batch job
     events: list = field(default_factory=list)  # (time, bytes in use)
 
     def serve(self, requests, clock=time.perf_counter) -> list:
@@ -118,6 +170,7 @@ class Server:
         nxt = 0
         t0 = clock()
         self.events = [(0.0, 0)]
+        can_batch = hasattr(self.executor, 'run_batch') and hasattr(self.executor, 'batchable')
         with cf.ThreadPoolExecutor(max_workers=self.slots) as pool:
             while nxt < len(reqs) or pending or inflight:
                 now = clock() - t0
@@ -135,6 +188,27 @@ class Server:
                         continue
                     if used + b > self.budget_bytes:
                         break
+                    if (can_batch and self.executor.batchable(r)
+                            and sum(1 for x in pending if self.executor.batchable(x)) >= self.batch_min):
+                        # the head and every other pending batchable request
+                        # that fits, in arrival order, as one job
+                        group, gb, rest = [], 0, collections.deque()
+                        while pending:
+                            x = pending.popleft()
+                            xb = self.executor.nbytes(x)
+                            if (len(group) < self.batch_max and self.executor.batchable(x)
+                                    and 0 < xb and used + gb + xb <= self.budget_bytes):
+                                group.append(x)
+                                gb += xb
+                            else:
+                                rest.append(x)
+                        pending = rest
+                        used += gb
+                        slot = free.pop()
+                        fut = pool.submit(self.executor.run_batch, group, slot)
+                        inflight[fut] = (group, now, gb, slot)
+                        self.events.append((now, used))
+                        continue
                     pending.popleft()
                     used += b
                     slot = free.pop()
@@ -156,11 +230,15 @@ class Server:
                     used -= b
                     free.append(slot)
                     self.events.append((t_end, used))
+                    group = r if isinstance(r, list) else [r]
                     try:
-                        outs, probs, amps = fut.result()
-                        results.append(Result(r.rid, outs, probs, r.arrival, t_adm, t_end, b, amps))
+                        outs = fut.result() if isinstance(r, list) else [fut.result()]
+                        for x, (o, p, amps) in zip(group, outs):
+                            results.append(Result(x.rid, o, p, x.arrival, t_adm, t_end, self.executor.nbytes(x), amps))
                     except Exception as e:  # reported per request; the loop keeps serving
-                        results.append(Result(r.rid, [], [], r.arrival, t_adm, t_end, b, error=str(e)))
+                        for x in group:
+                            results.append(Result(x.rid, [], [], x.arrival, t_adm, t_end, self.executor.nbytes(x),
+                                                  error=str(e)))
         return sorted(results, key=lambda x: x.rid)
 
     def summary(self, results) -> dict:

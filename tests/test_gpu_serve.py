@@ -23,14 +23,18 @@ def requests(count, rate, seed):
             for s in specs]
 
 
-@pytest.mark.parametrize('prec_name', ['C128', 'C64'])
-def test_each_result_same_alone_and_in_the_mix(q, prec_name):
+@pytest.mark.parametrize('prec_name,batch', [('C128', True), ('C128', False), ('C64', True)])
+def test_each_result_same_alone_and_in_the_mix(q, prec_name, batch):
+    """With batching, the state vectors (10..16 qubits) run as batch jobs
+    through qs_batch, alone as a batch of one; without, each on its own
+    stream through the generic fused kernel."""
     from paper_1802_08032_amd.serve import GpuExecutor, Server
     prec = getattr(q, prec_name)
     env = q.Env(0)
-    ex = GpuExecutor(env, prec, slots=6, fusion=12, min_fused=12, keep_amps=True)
+    ex = GpuExecutor(env, prec, slots=6, fusion=12, min_fused=12, keep_amps=True,
+                     batch_max_qubits=20 if batch else 0)
     reqs = requests(18, rate=400.0, seed=11)
-    log(f'serve mix {prec_name}')
+    log(f'serve mix {prec_name} batch={batch}')
     srv = Server(ex, slots=6)
     mix = srv.serve(reqs)
     assert all(r.error is None for r in mix), [r.error for r in mix if r.error]

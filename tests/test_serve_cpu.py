@@ -90,3 +90,56 @@ def test_oversized_request_is_rejected_not_hung():
     res = Server(OracleExecutor(0.0), budget_bytes=16 << 8, slots=2).serve(reqs + [big])
     errs = [r for r in res if r.error]
     assert any(r.rid == 99 for r in errs)
+
+
+class BatchingOracleExecutor(OracleExecutor):
+    """Also takes batch jobs: state vectors of 5..8 qubits."""
+
+    def __init__(self, delay=0.01):
+        super().__init__(delay)
+        self.jobs = []
+
+    def batchable(self, req):
+        return req.kind == 0 and 5 <= req.n <= 8
+
+    def run_batch(self, reqs, slot):
+        assert all(self.batchable(r) for r in reqs)
+        with self.lock:
+            self.jobs.append([r.rid for r in reqs])
+        return [self.run(r, slot) for r in reqs]
+
+
+def test_small_state_vectors_run_as_batch_jobs():
+    """Pending batchable requests are admitted together as one job per slot
+    (up to batch_max, within the byte budget) once batch_min of them wait;
+    the others run one by one; every request's outcomes are its own."""
+    from paper_1802_08032_amd.serve import Server
+    reqs = make_requests(40, rate=0.0, seed=5)
+    ex = BatchingOracleExecutor(0.0)
+    srv = Server(ex, slots=3, batch_min=2, batch_max=6)
+    res = srv.serve(reqs)
+    assert len(res) == 40 and all(r.error is None for r in res)
+    small = {r.rid for r in reqs if ex.batchable(r)}
+    assert small and any(len(j) > 1 for j in ex.jobs)
+    assert all(2 <= len(j) <= 6 for j in ex.jobs)
+    batched = sorted(rid for j in ex.jobs for rid in j)
+    assert len(set(batched)) == len(batched) and set(batched) <= small
+    for j in ex.jobs:
+        assert j == sorted(j)  # a job takes its requests in arrival order
+    for r, q in zip(res, reqs):
+        st = O.run_dm(q.n, q.ops) if q.kind == 1 else O.run_sv(q.n, q.ops)
+        for k in range(q.n):
+            o, p = (O.dm_measure if q.kind == 1 else O.sv_measure)(st, q.n, k, q.draws[k])
+            assert r.outcomes[k] == o and r.probs[k] == pytest.approx(p, abs=1e-15)
+    # the byte budget holds with batch jobs too
+    ex2 = BatchingOracleExecutor(0.0)
+    budget = 16 << 9
+    srv2 = Server(ex2, budget_bytes=budget, slots=3, batch_min=2, batch_max=64)
+    res2 = srv2.serve(reqs)
+    assert all(r.error is None for r in res2)
+    assert srv2.summary(res2)['hbm_peak_bytes'] <= budget
+    assert ex2.jobs and sum(ex2.nbytes(reqs[rid]) for rid in max(ex2.jobs, key=len)) <= budget
+    # one request at a time (no queue): nothing is batched
+    ex3 = BatchingOracleExecutor(0.0)
+    res3 = Server(ex3, slots=3, batch_min=2).serve(make_requests(6, rate=5.0, seed=5))
+    assert all(r.error is None for r in res3) and not ex3.jobs
