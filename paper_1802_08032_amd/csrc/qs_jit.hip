@@ -366,6 +366,19 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
         for (int r : regs) s << " qs_cm(fr, fi, " << vn(r) << ");";
         s << " }\n";
     };
+    // Phases whose controls are all thread or tile-index bits multiply a
+    // per-lane factor lfd instead of every register: lfd scales all of a
+    // lane's amplitudes alike, so it commutes with every op inside the
+    // lane's registers and is multiplied in before data leaves the lane (an
+    // LDS re-layout or the store).
+    bool lfd_active = false, lfd_declared = false;
+    auto flush_lfd = [&]() {
+        if (!lfd_active) return;
+        s << "        {";
+        for (int r = 0; r < E; ++r) s << " qs_cm(lfd.x, lfd.y, " << vn(r) << ");";
+        s << " }\n";
+        lfd_active = false;
+    };
     auto all_regs_with = [&](uint32_t bits) {
         std::vector<int> regs;
         for (int r = 0; r < E; ++r)
@@ -431,6 +444,7 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     size_t tcount = 0;
     auto emit_relayout = [&](size_t t) {
         const Trans& T = trans[t];
+        flush_lfd();
         // pair factors join register bits only: multiply in those whose
         // qubits leave the register bits
         for (int j = 0; j < K; ++j)
@@ -515,6 +529,27 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
             materialize(rmask);  // register controls are read as they stand
             // (kernel data offsets are taken right before an op's data is
             // appended: flushes of deferred factors append their own first)
+            if (op.kind == 2 && cond.empty() && __builtin_popcount(rmask) == 2) {
+                // a phase on two register qubits (both without a pending
+                // flip now): one more pair factor
+                const int j1 = L.reg[__builtin_ctz(rmask)], j2 = L.reg[31 - __builtin_clz(rmask)];
+                const Cx f = std::polar(1.0, op.angle) * (hasq[j1][j2] ? qmul[j1][j2] : Cx(1.0));
+                qmul[j1][j2] = qmul[j2][j1] = f;
+                hasq[j1][j2] = hasq[j2][j1] = true;
+                any_deferred = true;
+                continue;
+            }
+            if (op.kind == 2 && rmask == 0 && !cond.empty()) {
+                // a phase conditioned on thread or tile-index bits only: lfd
+                const size_t off = g.mats.size();
+                g.mats.insert(g.mats.end(), {cos(op.angle), sin(op.angle)});
+                if (!lfd_declared) s << "        V lfd;\n";
+                if (!lfd_active) s << "        lfd.x = (R)1;\n        lfd.y = (R)0;\n";
+                lfd_declared = lfd_active = true;
+                s << "        { const bool c = " << cond << "; R fr = mt[" << off << "], fi = mt[" << off + 1
+                  << "]; fr = c ? fr : (R)1; fi = c ? fi : (R)0; qs_cm(fr, fi, lfd); }\n";
+                continue;
+            }
             if (op.kind == 2) {  // phase on the registers whose masked bits are 1
                 const size_t off = g.mats.size();
                 g.mats.insert(g.mats.end(), {cos(op.angle), sin(op.angle), 0, 0, 0, 0, 0, 0});
@@ -1018,6 +1053,7 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
         }
         g.out.gsc = 1.0;
     }
+    flush_lfd();
     s << "        const unsigned long long bs = base + stt;\n";
     const std::string fx = flip_expr(streg, true);
     if (fx.empty()) {
