@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <complex>
+#include <unordered_set>
 #include <vector>
 
 #include "qs_plan.h"
@@ -305,6 +306,108 @@ std::vector<PassPlan> partition(const std::vector<OpRec>& all, int n, int TB, in
 
 double op_cost(const OpRec& op, int nregctrl);
 
+// Pass partition by beam search: keep the `width` partial partitions that
+// have applied the most ops after each pass, extending each by every
+// candidate tile set: S grown greedily, every run of K - contig qubits, and
+// every pair of runs of about half that length (a window split around a
+// region the pass does not need).  Partial partitions that applied the same
+// ops are merged (Zobrist hash of the set).  Returns an empty plan if a
+// pass's ops need more register layouts than allowed.
+std::vector<PassPlan> partition_beam(const std::vector<OpRec>& all, int n, int TB, int RB, int max_phases,
+                                     int max_ops, int contig, int width)
+{
+    const int K = TB + RB;
+    const uint64_t low = (1ull << contig) - 1;
+    const int w = K - contig;
+    auto run = [](int s0, int len) { return len > 0 ? ((1ull << len) - 1) << s0 : 0ull; };
+    std::vector<uint64_t> cands;
+    for (int s0 = contig; s0 + w <= n; ++s0) cands.push_back(low | run(s0, w));
+    for (int a = std::max(1, w / 2 - 1); a <= std::min(w - 1, w / 2 + 1); ++a)
+        for (int s1 = contig; s1 + a <= n; ++s1)
+            for (int s2 = s1 + a + 1; s2 + (w - a) <= n; ++s2) cands.push_back(low | run(s1, a) | run(s2, w - a));
+    std::vector<uint64_t> key(all.size());
+    uint64_t x = 0x9e3779b97f4a7c15ull;
+    for (uint64_t& k : key) {  // splitmix64
+        x += 0x9e3779b97f4a7c15ull;
+        uint64_t z = x;
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        k = z ^ (z >> 31);
+    }
+    struct Node {
+        std::vector<char> done;
+        size_t ndone = 0;
+        uint64_t hash = 0;
+        std::vector<uint64_t> S;
+        std::vector<std::vector<int>> takes;
+    };
+    struct Child {
+        size_t score;
+        size_t parent;
+        uint64_t S, hash;
+        std::vector<int> take;
+    };
+    std::vector<Node> beam(1);
+    beam[0].done.assign(all.size(), 0);
+    for (int step = 0; step < 4096; ++step) {
+        for (const Node& nd : beam) {
+            if (nd.ndone != all.size()) continue;
+            std::vector<PassPlan> out;
+            for (size_t p = 0; p < nd.S.size(); ++p) {
+                uint64_t S = nd.S[p];
+                int ssize = __builtin_popcountll(S);
+                for (int q = 0; q < n && ssize < K; ++q)
+                    if (!((S >> q) & 1)) {
+                        S |= 1ull << q;
+                        ++ssize;
+                    }
+                PassPlan P;
+                for (int q = 0; q < n; ++q)
+                    if ((S >> q) & 1) P.S.push_back(q);
+                P.ops = nd.takes[p];
+                plan_phases(P, all, TB, RB, max_phases, contig);
+                if (P.ops.size() != nd.takes[p].size()) return {};
+                out.push_back(std::move(P));
+            }
+            return out;
+        }
+        std::vector<Child> kids;
+        for (size_t b = 0; b < beam.size(); ++b) {
+            const Node& nd = beam[b];
+            size_t first = 0;
+            while (nd.done[first]) ++first;
+            auto expand = [&](uint64_t S0, bool grow) {
+                uint64_t S = S0;
+                int ssize = __builtin_popcountll(S0);
+                std::vector<int> take = scan_pass(all, nd.done, first, S, ssize, K, max_ops, grow);
+                if (take.empty()) return;
+                uint64_t h = nd.hash;
+                for (int i : take) h ^= key[i];
+                kids.push_back(Child{nd.ndone + take.size(), b, S, h, std::move(take)});
+            };
+            expand(low, true);
+            for (uint64_t c : cands) expand(c, false);
+        }
+        if (kids.empty()) return {};
+        std::stable_sort(kids.begin(), kids.end(), [](const Child& a, const Child& c) { return a.score > c.score; });
+        std::vector<Node> next;
+        std::unordered_set<uint64_t> seen;
+        for (Child& c : kids) {
+            if ((int)next.size() == width) break;
+            if (!seen.insert(c.hash).second) continue;
+            Node nd = beam[c.parent];
+            for (int i : c.take) nd.done[i] = 1;
+            nd.ndone = c.score;
+            nd.hash = c.hash;
+            nd.S.push_back(c.S);
+            nd.takes.push_back(std::move(c.take));
+            next.push_back(std::move(nd));
+        }
+        beam.swap(next);
+    }
+    return {};
+}
+
 // Estimated multiply-adds per amplitude of a pass's ops (controls inside
 // the tile counted as register controls), plus a charge per LDS re-layout
 // between register layouts (about two dense gates' worth of time where the
@@ -438,6 +541,12 @@ std::vector<PassPlan> plan_passes(const std::vector<OpRec>& all, int n, int TB, 
     std::vector<std::vector<PassPlan>> cands;
     for (int mode = 0; mode <= 2; ++mode) cands.push_back(partition(all, n, TB, RB, max_phases, max_ops, contig, mode, false));
     if (lookahead) cands.push_back(partition(all, n, TB, RB, max_phases, max_ops, contig, 2, true));
+    if (lookahead && balance > 0.0 && all.size() <= 1500) {
+        // a wider search for fewer passes (compiled plans are reused; the
+        // search costs about a millisecond per op)
+        std::vector<PassPlan> bm = partition_beam(all, n, TB, RB, max_phases, max_ops, contig, 16);
+        if (!bm.empty()) cands.push_back(std::move(bm));
+    }
     if (lookahead && balance > 0.0) {
         // where a pass is well above the balance point: partitions whose
         // passes take at most 1.5, 1.75 or 2 times the average op count
