@@ -92,6 +92,10 @@ __device__ __forceinline__ void qs_ap(const R (&m)[8], V& a, V& b)
 // LDS-only workgroup barrier: waits for this wave's LDS traffic, not for
 // its outstanding global loads (the prefetch of the next tile).
 #define QS_BAR() asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory")
+// Wave-level ordering for a re-layout whose data stays within each wave:
+// the LDS operations of one wave complete in order, so waiting for them is
+// enough.
+#define QS_WBAR() asm volatile("s_waitcnt lgkmcnt(0)\n" ::: "memory")
 // 4x4 complex matrix on (a, b, c, d) = index bit(t1) + 2 bit(t2).
 __device__ __forceinline__ void qs_ap4(const R (&m)[32], V& a, V& b, V& c, V& d)
 {
@@ -270,12 +274,40 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     const Layout& last = P.phases.back().lay;
     const bool final_t = !(last.reg == P.store.reg && last.thr == P.store.thr);
     if (final_t) trans.push_back({swizzle(last, P.store, K), &last, &P.store});
+    // A re-layout is wave-local when every wave reads back exactly the LDS
+    // addresses it wrote (the qubits of the wave-index bits stay in place):
+    // it then needs no workgroup barrier.  Checked here address by address.
+    std::vector<char> wave_local(trans.size(), 0);
     for (size_t t = 0; t < trans.size(); ++t) {
         std::vector<uint64_t> wi, ri;
         for (int b = 0; b < TB; ++b) wi.push_back(trans[t].img[trans[t].from->thr[b]]);
         for (int b = 0; b < TB; ++b) ri.push_back(trans[t].img[trans[t].to->thr[b]]);
         head << "    const unsigned tw" << t << " = " << tid_expr(wi, true, false) << ";\n";
         head << "    const unsigned tr" << t << " = " << tid_expr(ri, true, false) << ";\n";
+        std::vector<uint32_t> wr, rr;
+        for (int b = 0; b < RB; ++b) wr.push_back(trans[t].img[trans[t].from->reg[b]]);
+        for (int b = 0; b < RB; ++b) rr.push_back(trans[t].img[trans[t].to->reg[b]]);
+        auto addrs = [&](uint32_t tid0, uint32_t count, const std::vector<uint64_t>& timg, const std::vector<uint32_t>& rimg) {
+            std::vector<uint32_t> a;
+            for (uint32_t tid = tid0; tid < tid0 + count; ++tid) {
+                uint32_t tw = 0;
+                for (int b = 0; b < TB; ++b)
+                    if ((tid >> b) & 1) tw ^= (uint32_t)timg[b];
+                for (uint32_t r = 0; r < (1u << RB); ++r) {
+                    uint32_t x = tw;
+                    for (int b = 0; b < RB; ++b)
+                        if ((r >> b) & 1) x ^= rimg[b];
+                    a.push_back(x);
+                }
+            }
+            std::sort(a.begin(), a.end());
+            return a;
+        };
+        const uint32_t wave = std::min(64u, 1u << TB);
+        bool local_ok = true;
+        for (uint32_t w0 = 0; w0 < (1u << TB) && local_ok; w0 += wave)
+            local_ok = addrs(w0, wave, wi, wr) == addrs(w0, wave, ri, rr);
+        wave_local[t] = local_ok;
     }
 
     auto reg_off = [&](const std::vector<uint64_t>& img, int r, bool use_xor) {
@@ -476,11 +508,15 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
                 s << "        lds[twf" << t << " ^ " << hex32((uint32_t)reg_off(wreg, r, true)) << "] = " << vn(r) << ";\n";
             for (int b = 0; b < RB; ++b) pend[b].clear();
         }
-        s << "        QS_BAR();\n";
+        s << (wave_local[t] ? "        QS_WBAR();\n" : "        QS_BAR();\n");
         // read into fresh names so that no value is overwritten before it is stored
         for (int r = 0; r < E; ++r)
             s << "        const V w" << t << "_" << r << " = lds[" << addr("tr", (uint32_t)reg_off(rreg, r, true)) << "];\n";
-        s << "        QS_BAR();\n";
+        // the next re-layout may write where other waves still read unless
+        // both are wave-local; the last one of a tile is followed by the next
+        // tile's first, so it always waits for the whole workgroup
+        const bool next_local = t + 1 < trans.size() && wave_local[t] && wave_local[t + 1];
+        s << (next_local ? "        QS_WBAR();\n" : "        QS_BAR();\n");
         for (int r = 0; r < E; ++r) s << "        v" << r << " = w" << t << "_" << r << ";\n";
         for (int r = 0; r < E; ++r) name[r] = r;
         cur = T.to;
@@ -1314,7 +1350,10 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
         std::vector<PassPlan> plan =
             plan_passes(ops, nbits, cfg.TB, cfg.RB, cfg.max_phases, 1 << 12, cfg.contig, true, balance_point(dbl));
         std::vector<OpRec> ext(ops);
-        for (PassPlan& P : plan) merge_phase_ops(P, ext);
+        for (PassPlan& P : plan) {
+            assign_thread_positions(P, cfg.TB, cfg.contig);
+            merge_phase_ops(P, ext);
+        }
         std::vector<std::string> srcs;
         std::vector<double> mats;
         std::unique_ptr<JitPlan> nj(new JitPlan());
@@ -1419,7 +1458,10 @@ qs_status generate_sources(const std::vector<OpRec>& circuit_ops, int n, int kin
     std::vector<PassPlan> plan =
         plan_passes(ops, n, cfg.TB, cfg.RB, cfg.max_phases, 1 << 12, cfg.contig, true, balance_point(prec == QS_C128));
     std::vector<OpRec> ext(ops);
-    for (PassPlan& P : plan) merge_phase_ops(P, ext);
+    for (PassPlan& P : plan) {
+        assign_thread_positions(P, cfg.TB, cfg.contig);
+        merge_phase_ops(P, ext);
+    }
     out.clear();
     if (mats) mats->clear();
     Deferred carry;

@@ -42,6 +42,13 @@ bool coalesced(const Layout& L, int contig);
 // HBM), see rebalance().
 std::vector<PassPlan> plan_passes(const std::vector<OpRec>& all, int n, int TB, int RB, int max_phases,
                                   int max_ops, int contig, bool lookahead = false, double balance = 0.0);
+// Re-order the thread bits of every phase of P (register sets unchanged) so
+// that a re-layout keeps the qubits of the wave-index bits (thread bits 6
+// and up) in place wherever it can: such a re-layout moves data only
+// between lanes of one wave and needs no workgroup barrier.  The first
+// phase keeps qubits 0..contig-1 on thread bits 0..contig-1; the store
+// layout becomes the last phase's with qubits 0..contig-1 moved there.
+void assign_thread_positions(PassPlan& P, int TB, int contig);
 // Within every phase of P, replace runs of ops that act on at most two
 // register qubits and carry no thread or tile condition by their product
 // (a 2x2 dense op or a 4x4 kind-4 op), wherever that takes fewer

@@ -730,6 +730,65 @@ struct Block {
 
 }  // namespace
 
+void assign_thread_positions(PassPlan& P, int TB, int contig)
+{
+    const int kWave = 6;  // thread bits from here on index the wave within the workgroup
+    const size_t m = P.phases.size();
+    auto in = [](const std::vector<int>& v, int j) { return std::find(v.begin(), v.end(), j) != v.end(); };
+    // the next phase after phase i in which qubit j is a register qubit
+    auto next_reg = [&](size_t i, int j) {
+        for (size_t k = i + 1; k < m; ++k)
+            if (in(P.phases[k].lay.reg, j)) return k;
+        return m + 1;
+    };
+    std::vector<int> pos;  // pos[b]: qubit at thread bit b in the previous phase
+    for (size_t i = 0; i < m; ++i) {
+        Layout& L = P.phases[i].lay;
+        const std::vector<int> tset = L.thr;
+        std::vector<int> np(TB, -1);
+        // wave bits: keep their qubits while they stay thread qubits;
+        // otherwise (or in the first phase) give them the thread qubits
+        // that stay out of the registers longest
+        bool keep = i > 0;
+        for (int b = kWave; b < TB && keep; ++b) keep = in(tset, pos[b]);
+        if (keep) {
+            for (int b = kWave; b < TB; ++b) np[b] = pos[b];
+        } else if (TB > kWave) {
+            std::vector<int> cand;
+            for (int j : tset)
+                if (j >= contig) cand.push_back(j);
+            std::stable_sort(cand.begin(), cand.end(), [&](int a, int c) { return next_reg(i, a) > next_reg(i, c); });
+            for (int b = kWave, k = 0; b < TB && k < (int)cand.size(); ++b, ++k) np[b] = cand[k];
+        }
+        // lane bits can be permuted freely by any re-layout: qubits
+        // 0..contig-1 on their own lanes (coalesced loads and stores without
+        // a final re-layout), the others in ascending order
+        for (int j = 0; j < contig && j < TB; ++j)
+            if (in(tset, j) && !in(np, j) && np[j] < 0) np[j] = j;
+        std::vector<int> rest;
+        for (int j : tset)
+            if (!in(np, j)) rest.push_back(j);
+        std::sort(rest.begin(), rest.end());
+        for (int b = 0, k = 0; b < TB; ++b)
+            if (np[b] < 0) np[b] = rest[k++];
+        L.thr = np;
+        pos = np;
+    }
+    // store layout: the last phase with qubits 0..contig-1 on thread bits 0..contig-1
+    Layout st = P.phases.back().lay;
+    for (int b = 0; b < contig && b < TB; ++b) {
+        if (st.thr[b] == b) continue;
+        auto t = std::find(st.thr.begin(), st.thr.end(), b);
+        if (t != st.thr.end()) {
+            std::swap(*t, st.thr[b]);
+        } else {
+            auto r = std::find(st.reg.begin(), st.reg.end(), b);
+            std::swap(*r, st.thr[b]);
+        }
+    }
+    P.store = st;
+}
+
 void merge_phase_ops(PassPlan& P, std::vector<OpRec>& ops)
 {
     for (PhasePlan& ph : P.phases) {

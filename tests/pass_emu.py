@@ -3,7 +3,8 @@
 A generated pass is plain HIP C++ apart from a few device constructs.  This
 module compiles its source with the host clang++ under a small shim (one OS
 thread per GPU thread, a pthread barrier for the workgroup barrier, the LDS
-array shared by the threads of the one workgroup that runs at a time) and
+array shared by the threads of the one workgroup that runs at a time, a
+barrier per 64 threads for the wave-level ordering) and
 runs the workgroups one after another.  That executes exactly the
 arithmetic, register renames, LDS re-layouts and HBM addressing the
 generator wrote, so a pass set can be checked against the oracle without a
@@ -34,6 +35,9 @@ static thread_local QsEmuDim threadIdx, blockIdx;
 static QsEmuDim gridDim;
 static pthread_barrier_t qs_emu_bar;
 static inline void qs_emu_barrier() { pthread_barrier_wait(&qs_emu_bar); }
+// wave-level ordering: the 64 threads of one wave wait for each other only
+static pthread_barrier_t qs_emu_wbar[16];
+static inline void qs_emu_wave_barrier() { pthread_barrier_wait(&qs_emu_wbar[threadIdx.x / 64]); }
 #define __global__
 #define __device__
 #define __forceinline__ inline
@@ -48,6 +52,7 @@ extern "C" int qs_emu_run(V* amp, const R* mats, unsigned long long ntiles, unsi
     if (grid == 0 || grid > ntiles) return 1;
     gridDim.x = grid;
     pthread_barrier_init(&qs_emu_bar, nullptr, nthreads);
+    for (unsigned w = 0; w * 64 < nthreads; ++w) pthread_barrier_init(&qs_emu_wbar[w], nullptr, nthreads < 64 ? nthreads : 64);
     for (unsigned b = 0; b < grid; ++b) {
         std::vector<std::thread> th;
         for (unsigned t = 0; t < nthreads; ++t)
@@ -59,6 +64,7 @@ extern "C" int qs_emu_run(V* amp, const R* mats, unsigned long long ntiles, unsi
         for (std::thread& x : th) x.join();
     }
     pthread_barrier_destroy(&qs_emu_bar);
+    for (unsigned w = 0; w * 64 < nthreads; ++w) pthread_barrier_destroy(&qs_emu_wbar[w]);
     return 0;
 }
 '''
@@ -73,6 +79,7 @@ def available() -> bool:
 def compile_pass(src: str):
     """Build one generated pass as a host shared library (cached by source)."""
     body = re.sub(r'^#define QS_BAR\(\).*$', '#define QS_BAR() qs_emu_barrier()', src, flags=re.M)
+    body = re.sub(r'^#define QS_WBAR\(\).*$', '#define QS_WBAR() qs_emu_wave_barrier()', body, flags=re.M)
     if 'qs_emu_barrier()' not in body and 'QS_BAR' in src:
         raise RuntimeError('pass source has no QS_BAR definition to replace')
     # register-class hints (an empty asm pinning a value to scalar registers)
