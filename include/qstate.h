@@ -304,6 +304,13 @@ qs_status qs_circuit_destroy(qs_circuit c);
 qs_status qs_circuit_add_unitary(qs_circuit c, const int* controls, int n_controls, int target,
                                  const qs_cplx u[4]);
 qs_status qs_circuit_add_not(qs_circuit c, const int* controls, int n_controls, int target);
+/* Record a dense two-qubit unitary u (4x4 row-major, index = bit(target1) +
+ * 2 bit(target2), as qs_two_qubit_unitary; Sec. II.B.1 and, on a density
+ * matrix, Eq. 2's conj(u) on target1 + N, target2 + N).  In fused runs it is
+ * a 4x4 op of the pass that holds both targets.  QS_E_ARG for equal or
+ * negative targets or a non-finite entry, QS_E_NOT_UNITARY for
+ * max |u u^dagger - I| > 1e-10.  Not changed by qs_circuit_set_unitary. */
+qs_status qs_circuit_add_two_qubit_unitary(qs_circuit c, int target1, int target2, const qs_cplx u[16]);
 /* Change the parameters of recorded op `index` (0-based, in add order),
  * keeping its kind, target and controls: the matrix of a unitary, or the
  * angle of a phase.  QS_E_ARG if `index` holds another kind of op (or is out

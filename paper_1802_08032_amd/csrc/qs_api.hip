@@ -288,6 +288,11 @@ qs_status apply_op(qs_reg r, const OpRec& op)
     case 0: return dbl ? do_dense<double>(r, c, nc, op.target, op.u) : do_dense<float>(r, c, nc, op.target, op.u);
     case 1: return dbl ? do_not<double>(r, c, nc, op.target) : do_not<float>(r, c, nc, op.target);
     case 2: return dbl ? do_phase<double>(r, c, nc, op.angle) : do_phase<float>(r, c, nc, op.angle);
+    case 4: {  // a recorded two-qubit unitary
+        qs_cplx u[16];
+        for (int k = 0; k < 16; ++k) u[k] = qs_cplx{op.m4[2 * k], op.m4[2 * k + 1]};
+        return qs_two_qubit_unitary(r, op.target, op.target2, u);
+    }
     default:
         return dbl ? do_channel<double>(r, op.channel, op.target, op.p)
                    : do_channel<float>(r, op.channel, op.target, op.p);
@@ -1115,6 +1120,7 @@ static qs_status circuit_check(qs_reg r, qs_circuit c)
         }
         if (op.kind != 2) {
             qs_status s = check_target(op.target, r->n);
+            if (!s && op.kind == 4) s = check_target(op.target2, r->n);
             if (s) return s;
         }
         for (int q : op.ctrls)
@@ -1219,6 +1225,7 @@ qs_status generated_passes(qs_circuit c, int n, int kind, int prec, int tile_qub
     for (const OpRec& op : c->ops) {
         if (op.kind == 3 && kind != QS_DENSITY) return qs::set_error(QS_E_KIND, "channels need a density matrix");
         if (op.kind != 2 && op.target >= n) return qs::set_error(QS_E_ARG, "circuit qubit outside the register");
+        if (op.kind == 4 && op.target2 >= n) return qs::set_error(QS_E_ARG, "circuit qubit outside the register");
         for (int q : op.ctrls)
             if (q >= n) return qs::set_error(QS_E_ARG, "circuit qubit outside the register");
     }
@@ -1580,6 +1587,28 @@ qs_status qs_two_qubit_unitary(qs_reg r, int target1, int target2, const qs_cplx
 {
     const int t[2] = {target1, target2};
     return qs_multi_qubit_unitary(r, nullptr, 0, t, 2, u);
+}
+
+qs_status qs_circuit_add_two_qubit_unitary(qs_circuit c, int target1, int target2, const qs_cplx u[16])
+{
+    if (!valid_circ(c)) return qs::set_error(QS_E_HANDLE, "invalid circuit handle");
+    const int t[2] = {target1, target2};
+    qs_status s = check_qubits(t, 2, 64, -1, "targets");
+    if (s) return s;
+    if (!u) return qs::set_error(QS_E_ARG, "NULL matrix");
+    if ((s = check_finite(u, 16))) return s;
+    if (identity_error(u, 4, 1, false) > 1e-10) return qs::set_error(QS_E_NOT_UNITARY, "matrix is not unitary");
+    OpRec op{};
+    op.kind = 4;
+    op.target = target1;
+    op.target2 = target2;
+    op.m4.resize(32);
+    for (int k = 0; k < 16; ++k) {
+        op.m4[2 * k] = u[k].re;
+        op.m4[2 * k + 1] = u[k].im;
+    }
+    c->ops.push_back(op);
+    return QS_OK;
 }
 
 qs_status qs_mix_multi_kraus(qs_reg r, const int* targets, int n_targets, const qs_cplx* ops, int n_ops)

@@ -1050,6 +1050,14 @@ std::vector<OpRec> dm_vector_ops(const std::vector<OpRec>& ops, int N)
             out.push_back(b);
         } else if (op.kind == 3) {
             push_pair(op.target, channel_superop(op.channel, op.p));
+        } else if (op.kind == 4) {
+            // a two-qubit unitary: U on (t1, t2), conj(U) on (t1 + N, t2 + N)
+            OpRec a = op, b = op;
+            b.target = op.target + N;
+            b.target2 = op.target2 + N;
+            for (size_t k = 1; k < b.m4.size(); k += 2) b.m4[k] = -op.m4[k];
+            out.push_back(a);
+            out.push_back(b);
         }
     }
     return out;

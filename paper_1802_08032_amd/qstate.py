@@ -92,6 +92,7 @@ SIGNATURES = {
     'qs_circuit_destroy': (_i, [_vp]),
     'qs_circuit_add_unitary': (_i, [_vp, _vp, _i, _i, _vp]),
     'qs_circuit_add_not': (_i, [_vp, _vp, _i, _i]),
+    'qs_circuit_add_two_qubit_unitary': (_i, [_vp, _i, _i, _vp]),
     'qs_circuit_add_phase': (_i, [_vp, _vp, _i, _d]),
     'qs_circuit_add_channel': (_i, [_vp, _i, _i, _d]),
     'qs_circuit_size': (_i, [_vp, _PI]),
@@ -483,6 +484,18 @@ class Circuit:
         elif op.kind == 'phase':
             arr, k = _ints(op.qubits)
             _check(L.qs_circuit_add_phase(self.h, arr, k, float(op.angle)))
+        elif op.kind == 'unitary' and len(op.targets) == 1:
+            arr, k = _ints(op.controls)
+            _check(L.qs_circuit_add_unitary(self.h, arr, k, op.targets[0], _mat(op.u)))
+        elif op.kind == 'unitary' and len(op.targets) == 2 and not op.controls:
+            m, _ = _cplx_array(op.u)
+            if m.size != 16:
+                raise ValueError('a two-qubit unitary is 4x4')
+            _check(L.qs_circuit_add_two_qubit_unitary(self.h, op.targets[0], op.targets[1],
+                                                      C.c_void_p(m.ctypes.data)))
+        elif op.kind == 'unitary':
+            raise ValueError('circuits hold unitaries on one qubit (any controls) or on two qubits '
+                             '(no controls); apply wider ones to a register directly')
         else:
             ch = {'dephasing': DEPHASING, 'depolarising': DEPOLARISING, 'damping': DAMPING}[op.kind]
             _check(L.qs_circuit_add_channel(self.h, ch, op.target, float(op.p)))

@@ -300,3 +300,37 @@ def test_checkpoint_round_trip(q, env, tmp_path, kind_name, prec_name, n):
         reg.load_state(path)
     assert reg.get_amps()[0] == 1.0
     reg.close()
+
+
+@pytest.mark.parametrize('kind_name,n', [('STATEVEC', 15), ('DENSITY', 7)])
+def test_two_qubit_unitaries_in_circuits_every_path(q, env, kind_name, n):
+    """Recorded two-qubit unitaries mixed with one-qubit and controlled
+    gates, run one kernel per op, through the generic fused kernel and
+    through the run-time compiled passes (on ρ's 2N-qubit vector for a
+    density matrix), each against the oracle at 1e-12."""
+    from workloads import layered_circuit
+    kind = getattr(q, kind_name)
+    ops = (random_multi_ops(n, 24, 11, max_targets=2, max_controls=0) + layered_circuit(n, 2, 12)
+           + random_multi_ops(n, 12, 13, max_targets=1, max_controls=2))
+    if kind == q.DENSITY:
+        ref = O.run_dm(n, ops)
+    else:
+        ref = O.run_sv(n, ops)
+    c = q.Circuit(ops)
+    runs = {'per-op': lambda r: c.run(r, 0), 'fused': lambda r: c.run(r, 12)}
+    if kind == q.STATEVEC:
+        runs['tiled'] = lambda r: c.run_tiled(r, 12, 8)
+        runs['compiled'] = lambda r: c.run_compiled(r, 12, 8, 0, 4)
+    for name, fn in runs.items():
+        log(f'two-qubit circuit {kind_name} n={n} {name}')
+        reg = q.Register(env, n, kind, q.C128)
+        reg.init_zero()
+        fn(reg)
+        err = max_abs(reg.get_amps(), ref)
+        reg.close()
+        assert err <= 1e-12, (name, err)
+    c.close()
+    # a 4x4 that is not unitary is rejected when recorded
+    bad = Op('unitary', targets=(0, 1), u=2.0 * np.eye(4))
+    with pytest.raises(q.QStateError):
+        q.Circuit([bad])

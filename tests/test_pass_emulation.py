@@ -87,3 +87,28 @@ def test_density_matrix_passes():
     c.close()
     assert npass >= 1
     assert np.abs(amp - ref).max() <= 1e-12
+
+
+def test_two_qubit_unitaries_in_circuits():
+    """Recorded two-qubit unitaries (4x4 ops of the pass holding both
+    targets, unit-diagonal 4x4 cores) mixed with one-qubit gates, on a state
+    vector and on a density matrix (conj(U) on the column qubits)."""
+    import paper_1802_08032_amd as q
+    from workloads import random_multi_ops
+    n = 16
+    ops = (random_multi_ops(n, 40, 3, max_targets=2, max_controls=0) + layered_circuit(n, 2, 4)
+           + random_multi_ops(n, 20, 5, max_targets=1, max_controls=2))
+    err, npass = _run_sv(ops, n, q.C128, (12, 8, 4), 4)
+    assert npass >= 2
+    assert err <= 1e-12
+    N = 7
+    dops = random_multi_ops(N, 16, 6, max_targets=2, max_controls=0) + noisy_circuit(N, 1, 2)
+    rho0 = O.dm_pure(N, random_state(N, 4))
+    ref = rho0.copy()
+    for op in dops:
+        O.apply_dm(ref, N, op)
+    amp = rho0.astype(np.complex128).copy()
+    c = q.Circuit(dops)
+    pass_emu.run_passes(c, amp, 2 * N, q.C128, 12, 8, 4, q.DENSITY, grid_div=2)
+    c.close()
+    assert np.abs(amp - ref).max() <= 1e-12
