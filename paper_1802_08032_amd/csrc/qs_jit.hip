@@ -1351,6 +1351,7 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
             plan_passes(ops, nbits, cfg.TB, cfg.RB, cfg.max_phases, 1 << 12, cfg.contig, true, balance_point(dbl));
         std::vector<OpRec> ext(ops);
         for (PassPlan& P : plan) {
+            replan_phases_beam(P, ops, cfg.TB, cfg.RB, cfg.max_phases, cfg.contig, 8);
             assign_thread_positions(P, cfg.TB, cfg.contig);
             merge_phase_ops(P, ext);
         }
@@ -1459,6 +1460,7 @@ qs_status generate_sources(const std::vector<OpRec>& circuit_ops, int n, int kin
         plan_passes(ops, n, cfg.TB, cfg.RB, cfg.max_phases, 1 << 12, cfg.contig, true, balance_point(prec == QS_C128));
     std::vector<OpRec> ext(ops);
     for (PassPlan& P : plan) {
+        replan_phases_beam(P, ops, cfg.TB, cfg.RB, cfg.max_phases, cfg.contig, 8);
         assign_thread_positions(P, cfg.TB, cfg.contig);
         merge_phase_ops(P, ext);
     }

@@ -49,6 +49,11 @@ std::vector<PassPlan> plan_passes(const std::vector<OpRec>& all, int n, int TB, 
 // phase keeps qubits 0..contig-1 on thread bits 0..contig-1; the store
 // layout becomes the last phase's with qubits 0..contig-1 moved there.
 void assign_thread_positions(PassPlan& P, int TB, int contig);
+// Plan P's phases again by a beam search over register sets (the `width`
+// partial plans that leave the fewest ops survive each phase); replaces
+// P's phases and returns true only if that needs fewer phases than P has.
+bool replan_phases_beam(PassPlan& P, const std::vector<OpRec>& all, int TB, int RB, int max_phases, int contig,
+                        int width);
 // Within every phase of P, replace runs of ops that act on at most two
 // register qubits and carry no thread or tile condition by their product
 // (a 2x2 dense op or a 4x4 kind-4 op), wherever that takes fewer

@@ -730,6 +730,122 @@ struct Block {
 
 }  // namespace
 
+bool replan_phases_beam(PassPlan& P, const std::vector<OpRec>& all, int TB, int RB, int max_phases, int contig,
+                        int width)
+{
+    const int K = TB + RB;
+    std::vector<int> local(64, -1);
+    for (int j = 0; j < K; ++j) local[P.S[j]] = j;
+    auto ltargets = [&](const OpRec& op) -> uint32_t {
+        if (op.kind == 2) return 0;
+        uint32_t m = 1u << local[op.target];
+        if (op.kind == 4) m |= 1u << local[op.target2];
+        return m;
+    };
+    auto lmask = [&](const OpRec& op) {
+        uint32_t m = 0;
+        for (int q : op.ctrls)
+            if (local[q] >= 0) m |= 1u << local[q];
+        return m | ltargets(op);
+    };
+    std::vector<uint32_t> sets;  // every RB-subset of the tile qubits
+    for (uint32_t x = 0; x < (1u << K); ++x)
+        if (__builtin_popcount(x) == RB) sets.push_back(x);
+    const uint32_t low = (1u << contig) - 1;
+    struct St {
+        std::vector<int> rem;
+        std::vector<uint32_t> regs;
+        std::vector<std::vector<int>> ops;
+    };
+    // ops a phase with register qubits regm takes from rem, and what is left
+    auto split = [&](const std::vector<int>& rem, uint32_t regm, std::vector<int>& take, std::vector<int>& left) {
+        uint32_t blocked = 0;
+        for (int idx : rem) {
+            const uint32_t m = lmask(all[idx]);
+            if (!(m & blocked) && (ltargets(all[idx]) & ~regm) == 0)
+                take.push_back(idx);
+            else {
+                blocked |= m;
+                left.push_back(idx);
+            }
+        }
+    };
+    std::vector<St> beam(1);
+    beam[0].rem = P.ops;
+    const size_t best_known = P.phases.size();
+    for (int step = 0; step < max_phases; ++step) {
+        struct Kid {
+            size_t left;
+            size_t parent;
+            uint32_t regm;
+        };
+        std::vector<Kid> kids;
+        for (size_t b = 0; b < beam.size(); ++b)
+            for (uint32_t x : sets) {
+                if (step == 0 && (x & low)) continue;  // coalesced loads
+                uint32_t blocked = 0;
+                size_t left = 0, took = 0;
+                for (int idx : beam[b].rem) {
+                    const uint32_t m = lmask(all[idx]);
+                    if (!(m & blocked) && (ltargets(all[idx]) & ~x) == 0)
+                        ++took;
+                    else {
+                        blocked |= m;
+                        ++left;
+                    }
+                }
+                if (took) kids.push_back(Kid{left, b, x});
+            }
+        if (kids.empty()) return false;
+        std::stable_sort(kids.begin(), kids.end(), [](const Kid& a, const Kid& c) { return a.left < c.left; });
+        std::vector<St> next;
+        std::vector<std::vector<int>> seen;
+        for (const Kid& k : kids) {
+            if ((int)next.size() == width) break;
+            St st = beam[k.parent];
+            std::vector<int> take, left;
+            split(st.rem, k.regm, take, left);
+            if (std::find(seen.begin(), seen.end(), left) != seen.end()) continue;
+            seen.push_back(left);
+            st.rem = left;
+            st.regs.push_back(k.regm);
+            st.ops.push_back(take);
+            if (left.empty()) {
+                if (st.regs.size() >= best_known) return false;
+                // keep qubits 0..contig-1 out of the last phase's registers
+                // where that admits the same ops (a store without re-layout)
+                uint32_t& last = st.regs.back();
+                if (last & low)
+                    for (uint32_t x : sets)
+                        if (!(x & low)) {
+                            std::vector<int> t2, l2;
+                            const std::vector<int>& before = st.regs.size() > 1 ? beam[k.parent].rem : P.ops;
+                            split(before, x, t2, l2);
+                            if (l2.empty()) {
+                                last = x;
+                                break;
+                            }
+                        }
+                P.phases.clear();
+                for (size_t i = 0; i < st.regs.size(); ++i) {
+                    std::vector<int> regs;
+                    for (int j = 0; j < K; ++j)
+                        if ((st.regs[i] >> j) & 1) regs.push_back(j);
+                    PhasePlan ph;
+                    ph.lay = make_layout(TB, RB, regs);
+                    ph.ops = st.ops[i];
+                    P.phases.push_back(ph);
+                }
+                P.store = coalesced(P.phases.back().lay, contig) ? P.phases.back().lay : P.phases.front().lay;
+                return true;
+            }
+            next.push_back(std::move(st));
+        }
+        beam.swap(next);
+    }
+    return false;
+}
+
 void assign_thread_positions(PassPlan& P, int TB, int contig)
 {
     const int kWave = 6;  // thread bits from here on index the wave within the workgroup
