@@ -278,6 +278,7 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     // addresses it wrote (the qubits of the wave-index bits stay in place):
     // it then needs no workgroup barrier.  Checked here address by address.
     std::vector<char> wave_local(trans.size(), 0);
+    std::vector<std::vector<std::vector<uint32_t>>> read_set(trans.size());
     for (size_t t = 0; t < trans.size(); ++t) {
         std::vector<uint64_t> wi, ri;
         for (int b = 0; b < TB; ++b) wi.push_back(trans[t].img[trans[t].from->thr[b]]);
@@ -305,10 +306,17 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
         };
         const uint32_t wave = std::min(64u, 1u << TB);
         bool local_ok = true;
-        for (uint32_t w0 = 0; w0 < (1u << TB) && local_ok; w0 += wave)
-            local_ok = addrs(w0, wave, wi, wr) == addrs(w0, wave, ri, rr);
+        for (uint32_t w0 = 0; w0 < (1u << TB); w0 += wave) {
+            read_set[t].push_back(addrs(w0, wave, ri, rr));
+            local_ok = local_ok && addrs(w0, wave, wi, wr) == read_set[t].back();
+        }
         wave_local[t] = local_ok;
     }
+    // The next re-layout may follow without a workgroup barrier when both are
+    // wave-local and every wave then writes the addresses it has just read.
+    std::vector<char> local_next(trans.size(), 0);
+    for (size_t t = 0; t + 1 < trans.size(); ++t)
+        local_next[t] = wave_local[t] && wave_local[t + 1] && read_set[t] == read_set[t + 1];
 
     auto reg_off = [&](const std::vector<uint64_t>& img, int r, bool use_xor) {
         uint64_t o = 0;
@@ -513,9 +521,10 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
         for (int r = 0; r < E; ++r)
             s << "        const V w" << t << "_" << r << " = lds[" << addr("tr", (uint32_t)reg_off(rreg, r, true)) << "];\n";
         // the next re-layout may write where other waves still read unless
-        // both are wave-local; the last one of a tile is followed by the next
-        // tile's first, so it always waits for the whole workgroup
-        const bool next_local = t + 1 < trans.size() && wave_local[t] && wave_local[t + 1];
+        // both are wave-local over the same per-wave address sets; the last
+        // one of a tile is followed by the next tile's first, so it always
+        // waits for the whole workgroup
+        const bool next_local = t + 1 < trans.size() && local_next[t];
         s << (next_local ? "        QS_WBAR();\n" : "        QS_BAR();\n");
         for (int r = 0; r < E; ++r) s << "        v" << r << " = w" << t << "_" << r << ";\n";
         for (int r = 0; r < E; ++r) name[r] = r;
