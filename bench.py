@@ -7,7 +7,9 @@ CNOT brick, one phase gate with 3 controls + 1 target), 485 gates.  One step
 amplitude tiles by run-time compiled pass kernels, the first of which forms
 |0..0> instead of reading the register; 12-qubit tiles of 256 threads by
 default, or the autotuner's choice with --tile auto) + total probability +
-probability of an outcome + one measurement.  Inputs are seeded and synthetic; the register is resident
+probability of an outcome (both summed by the last pass as it stores the
+final state) + one measurement of qubit 0 (its probabilities from the same
+sums, then the collapse pass).  Inputs are seeded and synthetic; the register is resident
 in HBM before the timed region starts.
 
 Prints one JSON line (metric, value = gates/s, roofline of the dominant
@@ -508,12 +510,18 @@ def main():
         tuned = None
     log(f'tile: {K} qubits, {1 << TB} threads, {L} contiguous qubits')
 
+    readouts = []
+
     def step(i):
-        # |0..0> is formed inside the first fused pass (no separate init pass)
-        passes = circ.run_compiled(reg, K, TB, 0, L, init_basis=0)
-        reg.calc_total_prob()
-        reg.calc_prob_of_outcome(n - 1, 0)
-        reg.measure(0, float(draws[i]))
+        # |0..0> is formed inside the first fused pass (no separate init
+        # pass), and the last pass sums the total probability and P(q = 0)
+        # of every qubit as it stores the final state (no separate reduction
+        # passes); the measurement of qubit 0 takes its probabilities from
+        # there and runs the collapse pass
+        passes, probs = circ.run_compiled_probs(reg, K, TB, 0, L, init_basis=0)
+        total, p_top0, p0 = probs[0], probs[n], probs[1]
+        reg.measure_given_probs(0, p0, total - p0, float(draws[i]))
+        readouts.append((total, p_top0))
         return passes
 
     passes = 0
@@ -585,6 +593,9 @@ def main():
             'fused_passes_per_step': passes, 'parallelism': 'single GPU',
         },
         'circuits_per_s': args.steps / dt,
+        # readouts the last pass summed in the timed steps
+        'step_total_prob_max_error': max(abs(t - 1.0) for t, _ in readouts[args.warmup:]),
+        'step_prob_top_qubit_0': readouts[-1][1],
         # the paper's one-pass-per-gate bytes over the fused step time: what
         # an unfused engine would need to sustain; above the HBM peak, so it
         # is not a roofline fraction

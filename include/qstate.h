@@ -260,6 +260,16 @@ qs_status qs_calc_prob_of_outcome(qs_reg r, int qubit, int outcome, double* out)
  * (the probabilities are read back); the collapse is queued on the
  * register's stream, so every later call sees the collapsed state. */
 qs_status qs_measure(qs_reg r, int qubit, double u01, int* outcome, double* prob);
+/* qs_measure with P(qubit = 0) = p0 and P(qubit = 1) = p1 supplied by the
+ * caller instead of summed from the state: the probabilities the last pass
+ * of qs_circuit_run_compiled_probs returns for the state it stored (p0 =
+ * probs[1 + qubit], p1 = probs[0] - p0).  The outcome is (u01 < clamp(p0,
+ * 0, 1)) ? 0 : 1 and the kept branch is scaled by 1/sqrt(p) (state vector)
+ * or 1/p (density matrix) with p the supplied probability of that outcome.
+ * QS_E_ARG for a negative or non-finite probability, a draw outside [0, 1)
+ * or an outcome of probability 0.  Asynchronous: nothing is read back. */
+qs_status qs_measure_given_probs(qs_reg r, int qubit, double p0, double p1, double u01, int* outcome,
+                                 double* prob);
 /* Measure every qubit, 0..n-1 in order, with draws u01[0..n-1] in [0, 1):
  * the result is that of n successive qs_measure calls (each qubit's
  * probability taken on the state its predecessors left; the outcomes are
@@ -374,10 +384,25 @@ qs_status qs_circuit_run_compiled(qs_reg r, qs_circuit c, int tile_qubits, int t
 qs_status qs_circuit_run_compiled_from_basis(qs_reg r, qs_circuit c, int tile_qubits, int thread_bits,
                                              int max_phases, int contig_qubits, uint64_t basis_index,
                                              int* n_passes);
+/* qs_circuit_run_compiled (basis_index NULL) or
+ * qs_circuit_run_compiled_from_basis (*basis_index) on a state vector whose
+ * last pass also sums, as it stores the final state, the readouts of
+ * Sec. II.B.1: probs[0] = sum of |alpha|^2 (calcTotalProb) and probs[1 + q]
+ * = P(qubit q = 0) (calcProbOfOutcome) for q = 0..n-1, so that they cost no
+ * further pass over the state.  Each lane adds |alpha|^2 in double
+ * precision, the workgroups' sums are added in a fixed order with
+ * compensation (results are reproducible run to run; they may differ from
+ * qs_calc_total_prob / qs_calc_prob_of_outcome by rounding).  probs holds n
+ * + 1 doubles; synchronous.  QS_E_KIND for a density matrix.  For an empty
+ * circuit the sums come from the reduction kernels. */
+qs_status qs_circuit_run_compiled_probs(qs_reg r, qs_circuit c, int tile_qubits, int thread_bits, int max_phases,
+                                        int contig_qubits, const uint64_t* basis_index, double* probs,
+                                        int* n_passes);
 /* Host-only: the generated HIP source of pass `pass` for an n-qubit
  * register of kind `kind` and precision `prec` (copied into buf,
  * NUL-terminated, truncated to cap - 1 bytes; *len gets the full length,
- * *n_passes the pass count).  Needs no GPU. */
+ * *n_passes the pass count); pass -1 gives the last pass in the form
+ * qs_circuit_run_compiled_probs runs (state vectors).  Needs no GPU. */
 qs_status qs_circuit_source(qs_circuit c, int n, int kind, int prec, int tile_qubits, int thread_bits,
                             int max_phases, int contig_qubits, int pass, char* buf, size_t cap,
                             size_t* len, int* n_passes);

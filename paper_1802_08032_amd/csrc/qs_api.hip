@@ -790,14 +790,11 @@ qs_status qs_calc_prob_of_outcome(qs_reg r, int qubit, int outcome, double* out)
     return QS_OK;
 }
 
-qs_status qs_measure(qs_reg r, int qubit, double u01, int* outcome, double* prob)
+// The outcome from the draw and the probabilities v = {P(0), P(1)}, then
+// the collapse onto it.
+static qs_status measure_with(qs_reg r, int qubit, const double v[2], double u01, int* outcome, double* prob)
 {
-    QS_CHECK_REG(r);
-    qs_status s = check_target(qubit, r->n);
-    if (s) return s;
-    if (!(u01 >= 0.0 && u01 < 1.0)) return qs::set_error(QS_E_ARG, "draw must lie in [0, 1)");
-    double v[2];
-    if ((s = probs(r, qubit, v))) return s;
+    qs_status s = QS_OK;
     double p0 = v[0];
     if (p0 < 0.0) p0 = 0.0;
     if (p0 > 1.0) p0 = 1.0;
@@ -822,6 +819,29 @@ qs_status qs_measure(qs_reg r, int qubit, double u01, int* outcome, double* prob
     if (outcome) *outcome = o;
     if (prob) *prob = p;
     return QS_OK;
+}
+
+qs_status qs_measure(qs_reg r, int qubit, double u01, int* outcome, double* prob)
+{
+    QS_CHECK_REG(r);
+    qs_status s = check_target(qubit, r->n);
+    if (s) return s;
+    if (!(u01 >= 0.0 && u01 < 1.0)) return qs::set_error(QS_E_ARG, "draw must lie in [0, 1)");
+    double v[2];
+    if ((s = probs(r, qubit, v))) return s;
+    return measure_with(r, qubit, v, u01, outcome, prob);
+}
+
+qs_status qs_measure_given_probs(qs_reg r, int qubit, double p0, double p1, double u01, int* outcome, double* prob)
+{
+    QS_CHECK_REG(r);
+    qs_status s = check_target(qubit, r->n);
+    if (s) return s;
+    if (!(u01 >= 0.0 && u01 < 1.0)) return qs::set_error(QS_E_ARG, "draw must lie in [0, 1)");
+    if (!(p0 >= 0.0 && p1 >= 0.0 && std::isfinite(p0) && std::isfinite(p1)))
+        return qs::set_error(QS_E_ARG, "outcome probabilities must be finite and non-negative");
+    const double v[2] = {p0, p1};
+    return measure_with(r, qubit, v, u01, outcome, prob);
 }
 
 // Measure qubits 0..n-1 in turn.  Step k's numbers are those qs_measure
@@ -1196,6 +1216,22 @@ qs_status qs_circuit_run_compiled(qs_reg r, qs_circuit c, int tile_qubits, int t
     return qs::run_compiled_sv(r, c, cfg, n_passes);
 }
 
+qs_status qs_circuit_run_compiled_probs(qs_reg r, qs_circuit c, int tile_qubits, int thread_bits, int max_phases,
+                                        int contig_qubits, const uint64_t* basis_index, double* probs_out,
+                                        int* n_passes)
+{
+    qs_status s = circuit_check(r, c);
+    if (s) return s;
+    if (r->kind != QS_STATEVEC) return qs::set_error(QS_E_KIND, "readouts of compiled passes need a state vector");
+    if (!probs_out) return qs::set_error(QS_E_ARG, "NULL output");
+    if ((s = check_compiled_shape(r->prec, r->nbits, tile_qubits, thread_bits, max_phases, contig_qubits))) return s;
+    if (basis_index && r->n < 64 && *basis_index >= (1ull << r->n))
+        return qs::set_error(QS_E_ARG, "basis index out of range");
+    qs::FusedConfig cfg{thread_bits, tile_qubits - thread_bits, max_phases};
+    cfg.contig = contig_qubits ? contig_qubits : std::min(6, r->nbits);
+    return qs::run_compiled_sv(r, c, cfg, n_passes, basis_index, probs_out);
+}
+
 qs_status qs_circuit_run_compiled_from_basis(qs_reg r, qs_circuit c, int tile_qubits, int thread_bits,
                                              int max_phases, int contig_qubits, uint64_t basis_index,
                                              int* n_passes)
@@ -1214,7 +1250,7 @@ namespace {
 // The generated pass set of `c` for an n-qubit register (sources and kernel data).
 qs_status generated_passes(qs_circuit c, int n, int kind, int prec, int tile_qubits, int thread_bits,
                            int max_phases, int contig_qubits, std::vector<std::string>& srcs,
-                           std::vector<std::vector<double>>& mats)
+                           std::vector<std::vector<double>>& mats, bool readout = false)
 {
     if (!valid_circ(c)) return qs::set_error(QS_E_HANDLE, "invalid circuit handle");
     if (prec != QS_C64 && prec != QS_C128) return qs::set_error(QS_E_ARG, "unknown precision");
@@ -1231,7 +1267,7 @@ qs_status generated_passes(qs_circuit c, int n, int kind, int prec, int tile_qub
     }
     qs::FusedConfig cfg{thread_bits, tile_qubits - thread_bits, max_phases};
     cfg.contig = contig_qubits ? contig_qubits : std::min(6, nbits);
-    return qs::generate_sources(c->ops, n, kind, prec, cfg, srcs, &mats);
+    return qs::generate_sources(c->ops, n, kind, prec, cfg, srcs, &mats, readout);
 }
 
 }  // namespace
@@ -1242,9 +1278,11 @@ qs_status qs_circuit_source(qs_circuit c, int n, int kind, int prec, int tile_qu
 {
     std::vector<std::string> srcs;
     std::vector<std::vector<double>> mats;
-    qs_status s = generated_passes(c, n, kind, prec, tile_qubits, thread_bits, max_phases, contig_qubits, srcs, mats);
+    qs_status s = generated_passes(c, n, kind, prec, tile_qubits, thread_bits, max_phases, contig_qubits, srcs, mats,
+                                   pass == -1);
     if (s) return s;
     if (n_passes) *n_passes = (int)srcs.size();
+    if (pass == -1) pass = (int)srcs.size() - 1;
     if (pass < 0 || pass >= (int)srcs.size()) return qs::set_error(QS_E_ARG, "no such pass");
     const std::string& src = srcs[pass];
     if (len) *len = src.size();

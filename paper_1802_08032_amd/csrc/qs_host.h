@@ -168,10 +168,15 @@ std::vector<OpRec> dm_vector_ops(const std::vector<OpRec>& ops, int N);
 // Run-time compiled passes (qs_jit.hip).
 // init_index != nullptr: the first pass forms the basis state |*init_index>
 // (|j><j| for a density matrix) instead of reading the register.
+// readout != nullptr (state vectors): the last pass also sums the total
+// probability and P(q = 0) for every qubit q into readout[0], readout[1 + q]
+// (synchronous).
 qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passes,
-                          const uint64_t* init_index = nullptr);
+                          const uint64_t* init_index = nullptr, double* readout = nullptr);
+// readout: the last source is that pass with the readout sums.
 qs_status generate_sources(const std::vector<OpRec>& ops, int n, int kind, int prec, FusedConfig cfg,
-                           std::vector<std::string>& out, std::vector<std::vector<double>>* mats = nullptr);
+                           std::vector<std::string>& out, std::vector<std::vector<double>>* mats = nullptr,
+                           bool readout = false);
 // Per-operation execution of one recorded op (qs_api.hip).
 qs_status apply_op(qs_reg r, const OpRec& op);
 

@@ -63,6 +63,9 @@ template <typename T> hipError_t launch_prob_half_sv(const Launch& L, const void
                                                      int outcome, double* partials, double* dev_out);
 template <typename T> hipError_t launch_prob_dm(const Launch& L, const void* rho, int N, int q,
                                                 double* partials, double* dev_out);
+// out[j] = sum of part[i * cols + j] over rows i = 0..rows-1 (compensated,
+// in row order).
+hipError_t launch_sum_columns(const Launch& L, const double* part, int rows, int cols, double* out);
 template <typename T> hipError_t launch_collapse_sv(const Launch& L, void* amp, int nbits, int q,
                                                     int outcome, double scale);
 template <typename T> hipError_t launch_collapse_dm(const Launch& L, void* rho, int N, int q,

@@ -231,9 +231,12 @@ using Cx = std::complex<double>;
 
 // `in`: factors deferred by earlier passes.  `last_pass`: multiply every
 // deferred factor in before storing (otherwise the per-qubit factors are
-// handed on in GenOut::out).
+// handed on in GenOut::out).  `readout_n` > 0 (last pass of an n-qubit state
+// vector): the pass also sums, as it stores the final state, the total
+// probability and P(qubit q = 0) for every q, per workgroup into
+// part[blockIdx.x * (n + 1) + 0 .. n] (the total first).
 GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB, bool dbl, bool init,
-                const Deferred& in, bool last_pass)
+                const Deferred& in, bool last_pass, int readout_n)
 {
     const int K = TB + RB, E = 1 << RB;
     GenOut g;
@@ -243,7 +246,8 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     head << kPrelude;
     head << "extern \"C\" __global__ void __launch_bounds__(" << (1 << TB)
          << ") qs_pass(V* __restrict__ amp, const R* __restrict__ mats, unsigned long long ntiles"
-         << (init ? ", unsigned long long init_index" : "") << ")\n{\n";
+         << (init ? ", unsigned long long init_index" : "") << (readout_n > 0 ? ", double* __restrict__ part" : "")
+         << ")\n{\n";
     head << "    __shared__ V lds[" << (1 << K) << "];\n";
     head << "    const unsigned tid = threadIdx.x;\n";
 
@@ -1111,9 +1115,88 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
         for (int r = 0; r < E; ++r)
             s << "        qs_stnt(" << vn(r) << ", &amp[bs + (" << hex64(reg_off(streg, r, false)) << " ^ sf)]);\n";
     }
+    // Readouts of the stored state (Sec. II.B.1 probabilities): the lane's
+    // |amplitude|^2 in double precision, their sum t, and for each register
+    // bit b the sum s0 over registers with bit b clear; a lane whose flip on
+    // bit b is pending stored those at bit b set, so it counts t - s0.
+    // Thread-bit qubits are fixed per lane (taken from ro_t at the end);
+    // qubits outside the tile by the tile's bit in the store address.
+    const int nv = readout_n + 1;
+    std::vector<int> ro_global;
+    if (readout_n > 0) {
+        for (int q = 0; q < readout_n; ++q)
+            if (local[q] < 0) ro_global.push_back(q);
+        s << "        {\n";
+        for (int r = 0; r < E; ++r) {
+            const std::string a = vn(r);
+            s << "            const double p" << r << " = (double)" << a << ".x * (double)" << a << ".x + (double)" << a
+              << ".y * (double)" << a << ".y;\n";
+        }
+        auto sum_of = [&](const std::vector<int>& rs) {
+            // pairwise, so that the rounding does not grow with the count
+            std::vector<std::string> t;
+            for (int r : rs) t.push_back("p" + std::to_string(r));
+            while (t.size() > 1) {
+                std::vector<std::string> u;
+                for (size_t i = 0; i + 1 < t.size(); i += 2) u.push_back("(" + t[i] + " + " + t[i + 1] + ")");
+                if (t.size() & 1) u.push_back(t.back());
+                t.swap(u);
+            }
+            return t[0];
+        };
+        std::vector<int> all_r;
+        for (int r = 0; r < E; ++r) all_r.push_back(r);
+        s << "            const double t = " << sum_of(all_r) << ";\n";
+        s << "            ro_t += t;\n";
+        for (int b = 0; b < RB; ++b) {
+            std::vector<int> rs;
+            for (int r = 0; r < E; ++r)
+                if (!((r >> b) & 1)) rs.push_back(r);
+            if (pend[b].empty())
+                s << "            ro_r" << b << " += " << sum_of(rs) << ";\n";
+            else
+                s << "            { const double s0 = " << sum_of(rs) << "; ro_r" << b << " += (" << pend[b]
+                  << ") ? t - s0 : s0; }\n";
+        }
+        for (int q : ro_global) s << "            ro_g" << q << " += ((bs >> " << q << ") & 1ull) ? 0.0 : t;\n";
+        s << "        }\n";
+    }
     s << "        if (!more) break;\n";
     for (int r = 0; r < E; ++r) s << "        v" << r << " = n" << r << ";\n";
-    s << "        tile = ntile;\n        base = ins(tile);\n    }\n}\n";
+    s << "        tile = ntile;\n        base = ins(tile);\n    }\n";
+    if (readout_n > 0) {
+        // Workgroup sums through the LDS (free after the last re-layout), a
+        // chunk of values at a time: thread tid writes its value j to row j,
+        // then thread j adds row j in thread order (rows padded by one
+        // double, so the readers hit distinct banks).
+        const int nt = 1 << TB;
+        const int lds_doubles = (1 << K) * (dbl ? 2 : 1);
+        const int rows = lds_doubles / (nt + 1);
+        auto value = [&](int j) -> std::string {
+            if (j == 0) return "ro_t";
+            const int q = j - 1, l = local[q];
+            if (l < 0) return "ro_g" + std::to_string(q);
+            for (int b = 0; b < RB; ++b)
+                if (P.store.reg[b] == l) return "ro_r" + std::to_string(b);
+            for (int b = 0; b < TB; ++b)
+                if (P.store.thr[b] == l) return "(((tid >> " + std::to_string(b) + ") & 1u) ? 0.0 : ro_t)";
+            g.bad = true;
+            return "0.0";
+        };
+        s << "    {\n        double* ld = (double*)lds;\n        QS_BAR();\n";
+        for (int c0 = 0; c0 < nv; c0 += rows) {
+            const int cnt = std::min(rows, nv - c0);
+            for (int j = c0; j < c0 + cnt; ++j)
+                s << "        ld[" << (j - c0) * (nt + 1) << " + tid] = " << value(j) << ";\n";
+            s << "        QS_BAR();\n";
+            s << "        if (tid < " << cnt << "u) {\n            double a = 0.0;\n";
+            s << "            for (unsigned i = 0; i < " << nt << "u; ++i) a += ld[tid * " << nt + 1 << "u + i];\n";
+            s << "            part[(unsigned long long)blockIdx.x * " << nv << "ull + " << c0 << "ull + tid] = a;\n";
+            s << "        }\n        QS_BAR();\n";
+        }
+        s << "    }\n";
+    }
+    s << "}\n";
 
     // Tile loop with a one-tile prefetch: tile t + gridDim.x is loaded while
     // tile t is computed.  The matrix pointer is made to depend
@@ -1122,7 +1205,18 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     std::ostringstream loop;
     loop << pro.str();
     loop << "    unsigned long long tile = blockIdx.x;\n";
-    loop << "    if (tile >= ntiles) return;\n";
+    if (readout_n > 0) {
+        loop << "    if (tile >= ntiles) {\n";
+        loop << "        for (unsigned j = tid; j < " << nv << "u; j += " << (1 << TB) << "u) part[(unsigned long long)blockIdx.x * "
+             << nv << "ull + j] = 0.0;\n";
+        loop << "        return;\n    }\n";
+        loop << "    double ro_t = 0.0";
+        for (int b = 0; b < RB; ++b) loop << ", ro_r" << b << " = 0.0";
+        for (int q : ro_global) loop << ", ro_g" << q << " = 0.0";
+        loop << ";\n";
+    } else {
+        loop << "    if (tile >= ntiles) return;\n";
+    }
     loop << "    auto ins = [](unsigned long long t) -> unsigned long long {\n";
     loop << "        unsigned long long b = t;\n";
     for (int j = 0; j < K; ++j) {
@@ -1320,20 +1414,33 @@ struct JitPlan {
     std::string init_src;
     hipFunction_t init_fn = nullptr;
     int init_blocks_per_cu = 1;
+    // the last pass also summing the readouts (state vectors), compiled on
+    // first use: [0] reads its tiles, [1] forms them (a one-pass plan run
+    // from a basis state)
+    std::string ro_src[2];
+    hipFunction_t ro_fn[2] = {nullptr, nullptr};
+    int ro_blocks_per_cu[2] = {1, 1};
+    double* ro_part = nullptr;  // per-workgroup sums, grid x (n + 1)
+    size_t ro_part_rows = 0;
+    double* ro_dev = nullptr;   // n + 1 sums
+    double* ro_host = nullptr;  // pinned copy
 };
 
 void jit_plan_free(JitPlan* p)
 {
     if (!p) return;
-    if (p->dmats) {
-        (void)hipSetDevice(p->device);
-        (void)hipFree(p->dmats);
-    }
+    if (p->dmats || p->ro_part || p->ro_dev) (void)hipSetDevice(p->device);
+    if (p->dmats) (void)hipFree(p->dmats);
+    if (p->ro_part) (void)hipFree(p->ro_part);
+    if (p->ro_dev) (void)hipFree(p->ro_dev);
+    if (p->ro_host) (void)hipHostFree(p->ro_host);
     delete p;
 }
 
-qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passes_out, const uint64_t* init_index)
+qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passes_out, const uint64_t* init_index,
+                          double* readout)
 {
+    if (readout && r->kind != QS_STATEVEC) return set_error(QS_E_KIND, "readouts of compiled passes need a state vector");
     // a density matrix runs as its 2N-qubit vector (Eq. 2)
     std::vector<OpRec> dm_ops;
     if (r->kind == QS_DENSITY) dm_ops = dm_vector_ops(c->ops, r->n);
@@ -1370,9 +1477,14 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
         Deferred carry;
         for (size_t p = 0; p < plan.size(); ++p) {
             const bool lastp = p + 1 == plan.size();
-            GenOut go = generate(plan[p], ext, cfg.TB, cfg.RB, dbl, false, carry, lastp);
+            GenOut go = generate(plan[p], ext, cfg.TB, cfg.RB, dbl, false, carry, lastp, 0);
             if (go.bad) return set_error(QS_E_ARG, "internal: relayout swizzle outside address bits 0..2");
-            if (p == 0) nj->init_src = generate(plan[p], ext, cfg.TB, cfg.RB, dbl, true, carry, lastp).src;
+            if (p == 0) nj->init_src = generate(plan[p], ext, cfg.TB, cfg.RB, dbl, true, carry, lastp, 0).src;
+            // the last pass with the readouts (state vectors; compiled on first use)
+            if (lastp && r->kind == QS_STATEVEC) {
+                nj->ro_src[0] = generate(plan[p], ext, cfg.TB, cfg.RB, dbl, false, carry, true, nbits).src;
+                if (p == 0) nj->ro_src[1] = generate(plan[p], ext, cfg.TB, cfg.RB, dbl, true, carry, true, nbits).src;
+            }
             carry = go.out;
             nj->mat_off.push_back(mats.size());
             mats.insert(mats.end(), go.mats.begin(), go.mats.end());
@@ -1438,19 +1550,79 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
             J->init_fn = f[0];
         }
     }
-    for (size_t p = 0; p < J->fns.size(); ++p) {
+    // the last pass with the readout sums
+    const size_t np = J->fns.size();
+    const int ro_var = init_index && np == 1 ? 1 : 0;
+    const int nv = nbits + 1;
+    unsigned ro_grid = 0;
+    if (readout && np > 0) {
+        if (!J->ro_fn[ro_var]) {
+            std::vector<hipFunction_t> f;
+            qs_status s = load_all(r->env->device, {J->ro_src[ro_var]}, f);
+            if (s) return s;
+            int nb = 0;
+            hipError_t e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f[0], 1 << cfg.TB, 0);
+            if (e != hipSuccess) return hip_error(e, "occupancy query");
+            J->ro_blocks_per_cu[ro_var] = std::max(1, nb);
+            J->ro_fn[ro_var] = f[0];
+        }
+        ro_grid = (unsigned)std::min<unsigned long long>(ntiles, 256ull * J->ro_blocks_per_cu[ro_var]);
+        if (J->ro_part_rows < ro_grid) {
+            if (J->ro_part) {
+                (void)hipStreamSynchronize(r->stream);  // an earlier run may still write it
+                (void)hipFree(J->ro_part);
+                J->ro_part = nullptr;
+                J->ro_part_rows = 0;
+            }
+            hipError_t e = hipMalloc(&J->ro_part, (size_t)ro_grid * nv * sizeof(double));
+            if (e != hipSuccess) return hip_error(e, "readout partial sums");
+            J->ro_part_rows = ro_grid;
+        }
+        if (!J->ro_dev) {
+            hipError_t e = hipMalloc(&J->ro_dev, nv * sizeof(double));
+            if (e == hipSuccess) e = hipHostMalloc(&J->ro_host, nv * sizeof(double), hipHostMallocDefault);
+            if (e != hipSuccess) return hip_error(e, "readout buffers");
+        }
+    }
+    for (size_t p = 0; p < np; ++p) {
         void* amp = r->amp;
         const void* mp = (const char*)J->dmats + J->mat_off[p] * esz_of(r->prec);
         const bool first_init = init_index && p == 0;
-        void* args[] = {&amp, &mp, &ntiles, &init_at};
-        const hipFunction_t fn = first_init ? J->init_fn : J->fns[p];
-        const int bpc = first_init ? J->init_blocks_per_cu : J->blocks_per_cu[p];
+        const bool ro = readout && p + 1 == np;
+        double* part = J->ro_part;
+        void* args[] = {&amp, &mp, &ntiles, &init_at, &part};
+        void* args_ro[] = {&amp, &mp, &ntiles, &part};
+        hipFunction_t fn = first_init ? J->init_fn : J->fns[p];
+        int bpc = first_init ? J->init_blocks_per_cu : J->blocks_per_cu[p];
+        if (ro) {
+            fn = J->ro_fn[ro_var];
+            bpc = J->ro_blocks_per_cu[ro_var];
+        }
         // a persistent grid: the workgroups that fit on the 256 CUs at once
         const unsigned grid = (unsigned)std::min<unsigned long long>(ntiles, 256ull * bpc);
+        void** kargs = ro && !first_init ? args_ro : args;
         qs_status s = profiled(r, QS_K_FUSED, [&](int*) {
-            return hipModuleLaunchKernel(fn, grid, 1, 1, 1u << cfg.TB, 1, 1, 0, r->stream, args, nullptr);
+            return hipModuleLaunchKernel(fn, grid, 1, 1, 1u << cfg.TB, 1, 1, 0, r->stream, kargs, nullptr);
         });
         if (s) return s;
+    }
+    if (readout) {
+        if (np == 0) {
+            // no pass to fold the sums into: the reduction kernels
+            qs_status s = qs_calc_total_prob(r, &readout[0]);
+            for (int q = 0; q < nbits && s == QS_OK; ++q) s = qs_calc_prob_of_outcome(r, q, 0, &readout[1 + q]);
+            if (s) return s;
+        } else {
+            const Launch L{r->stream, r->env->device};
+            qs_status s = profiled(r, QS_K_REDUCE, [&](int*) {
+                return launch_sum_columns(L, J->ro_part, (int)ro_grid, nv, J->ro_dev);
+            });
+            if (s) return s;
+            hipError_t e = hipMemcpyAsync(J->ro_host, J->ro_dev, nv * sizeof(double), hipMemcpyDeviceToHost, r->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+            if (e != hipSuccess) return hip_error(e, "readout copy");
+            memcpy(readout, J->ro_host, nv * sizeof(double));
+        }
     }
     if (passes_out) *passes_out = (int)J->fns.size();
     return QS_OK;
@@ -1458,8 +1630,9 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
 
 // Source of the specialised kernels for one circuit (inspection / tests).
 qs_status generate_sources(const std::vector<OpRec>& circuit_ops, int n, int kind, int prec, FusedConfig cfg,
-                           std::vector<std::string>& out, std::vector<std::vector<double>>* mats)
+                           std::vector<std::string>& out, std::vector<std::vector<double>>* mats, bool readout)
 {
+    if (readout && kind != QS_STATEVEC) return set_error(QS_E_KIND, "readouts of compiled passes need a state vector");
     if (cfg.max_phases <= 0 || cfg.max_phases > kPhMax) cfg.max_phases = kPhMax;
     std::vector<OpRec> dm_ops;
     if (kind == QS_DENSITY) dm_ops = dm_vector_ops(circuit_ops, n);
@@ -1477,7 +1650,8 @@ qs_status generate_sources(const std::vector<OpRec>& circuit_ops, int n, int kin
     if (mats) mats->clear();
     Deferred carry;
     for (size_t p = 0; p < plan.size(); ++p) {
-        GenOut go = generate(plan[p], ext, cfg.TB, cfg.RB, prec == QS_C128, false, carry, p + 1 == plan.size());
+        GenOut go = generate(plan[p], ext, cfg.TB, cfg.RB, prec == QS_C128, false, carry, p + 1 == plan.size(),
+                             readout && p + 1 == plan.size() ? n : 0);
         if (go.bad) return set_error(QS_E_ARG, "internal: relayout swizzle outside address bits 0..2");
         carry = go.out;
         out.push_back(go.src);

@@ -508,6 +508,18 @@ __global__ __launch_bounds__(kBlock) void k_prob_dm(const typename C2<T>::type* 
     block_store2(s0, s1, partials);
 }
 
+// out[j] = sum over rows i of part[i * cols + j], in row order (one thread
+// per column, compensated): the fused readouts' per-workgroup sums.
+__global__ __launch_bounds__(64) void k_sum_columns(const double* __restrict__ part, int rows, int cols,
+                                                    double* __restrict__ out)
+{
+    const int j = blockIdx.x * 64 + threadIdx.x;
+    if (j >= cols) return;
+    NSum a = {0.0, 0.0};
+    for (int i = 0; i < rows; ++i) nadd(a, part[(size_t)i * cols + j]);
+    out[j] = a.s + a.c;
+}
+
 __global__ __launch_bounds__(kBlock) void k_reduce_final(const double* __restrict__ partials,
                                                          int nblocks, double* out)
 {
@@ -1293,5 +1305,12 @@ hipError_t launch_fid_dm(const Launch& L, const void* rho, int N, const void* ps
 
 QS_INSTANTIATE(double)
 QS_INSTANTIATE(float)
+
+hipError_t launch_sum_columns(const Launch& L, const double* part, int rows, int cols, double* out)
+{
+    if (rows < 1 || cols < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sum_columns, dim3((cols + 63) / 64), dim3(64), 0, L.stream, part, rows, cols, out);
+    return hipGetLastError();
+}
 
 }  // namespace qs

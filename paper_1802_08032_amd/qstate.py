@@ -71,6 +71,7 @@ SIGNATURES = {
     'qs_calc_total_prob': (_i, [_vp, _PD]),
     'qs_calc_prob_of_outcome': (_i, [_vp, _i, _i, _PD]),
     'qs_measure': (_i, [_vp, _i, _d, _PI, _PD]),
+    'qs_measure_given_probs': (_i, [_vp, _i, _d, _d, _d, _PI, _PD]),
     'qs_measure_all': (_i, [_vp, _PD, _PI, _PD]),
     'qs_circuit_set_unitary': (_i, [_vp, _i, _vp]),
     'qs_circuit_set_phase': (_i, [_vp, _i, _d]),
@@ -100,6 +101,7 @@ SIGNATURES = {
     'qs_circuit_run_tiled': (_i, [_vp, _vp, _i, _i, _i, _PI]),
     'qs_circuit_run_compiled': (_i, [_vp, _vp, _i, _i, _i, _i, _PI]),
     'qs_circuit_run_compiled_from_basis': (_i, [_vp, _vp, _i, _i, _i, _i, _u64, _PI]),
+    'qs_circuit_run_compiled_probs': (_i, [_vp, _vp, _i, _i, _i, _i, _vp, _PD, _PI]),
     'qs_circuit_source': (_i, [_vp, _i, _i, _i, _i, _i, _i, _i, _i, C.c_char_p, _sz, C.POINTER(_sz), _PI]),
     'qs_circuit_pass_data': (_i, [_vp, _i, _i, _i, _i, _i, _i, _i, _i, _PD, _sz, C.POINTER(_sz), _PI]),
     'qs_batch_create': (_i, [_vp, _vp, _i, _i, C.POINTER(_vp)]),
@@ -430,6 +432,14 @@ class Register:
         _check(lib().qs_measure(self.h, qubit, float(u01), C.byref(o), C.byref(p)))
         return o.value, p.value
 
+    def measure_given_probs(self, qubit: int, p0: float, p1: float, u01: float):
+        """measure() with P(0) and P(1) supplied (e.g. from
+        Circuit.run_compiled_probs) instead of summed from the state."""
+        o, p = C.c_int(), C.c_double()
+        _check(lib().qs_measure_given_probs(self.h, qubit, float(p0), float(p1), float(u01), C.byref(o),
+                                            C.byref(p)))
+        return o.value, p.value
+
     def measure_all(self, draws):
         """Measure qubits 0..n-1 in order with one draw each; returns
         (outcomes, probabilities) as lists."""
@@ -528,6 +538,19 @@ class Circuit:
             _check(lib().qs_circuit_run_compiled_from_basis(reg.h, self.h, tile_qubits, thread_bits, max_phases,
                                                             contig_qubits, init_basis, C.byref(passes)))
         return passes.value
+
+    def run_compiled_probs(self, reg: Register, tile_qubits: int, thread_bits: int, max_phases: int = 0,
+                           contig_qubits: int = 0, init_basis: int | None = None):
+        """run_compiled whose last pass also sums the readouts: returns
+        (passes, probs) with probs[0] the total probability and probs[1 + q]
+        = P(qubit q = 0), as a float64 array of n + 1."""
+        passes = C.c_int()
+        out = np.zeros(reg.n + 1, dtype=np.float64)
+        idx = C.c_uint64(init_basis) if init_basis is not None else None
+        _check(lib().qs_circuit_run_compiled_probs(reg.h, self.h, tile_qubits, thread_bits, max_phases,
+                                                   contig_qubits, C.byref(idx) if idx is not None else None,
+                                                   out.ctypes.data_as(_PD), C.byref(passes)))
+        return passes.value, out
 
     def source(self, n: int, prec: int, tile_qubits: int, thread_bits: int, pass_index: int = 0,
                max_phases: int = 0, contig_qubits: int = 0, kind: int = STATEVEC):

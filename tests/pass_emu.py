@@ -47,7 +47,8 @@ static inline void qs_emu_wave_barrier() { pthread_barrier_wait(&qs_emu_wbar[thr
 '''
 
 _TAIL = r'''
-extern "C" int qs_emu_run(V* amp, const R* mats, unsigned long long ntiles, unsigned grid, unsigned nthreads)
+extern "C" int qs_emu_run(V* amp, const R* mats, unsigned long long ntiles, unsigned grid, unsigned nthreads,
+                          double* part)
 {
     if (grid == 0 || grid > ntiles) return 1;
     gridDim.x = grid;
@@ -59,7 +60,7 @@ extern "C" int qs_emu_run(V* amp, const R* mats, unsigned long long ntiles, unsi
             th.emplace_back([=] {
                 threadIdx.x = t;
                 blockIdx.x = b;
-                qs_pass(amp, mats, ntiles);
+                qs_pass(amp, mats, ntiles QS_EMU_PART);
             });
         for (std::thread& x : th) x.join();
     }
@@ -86,7 +87,9 @@ def compile_pass(src: str):
     body = re.sub(r'asm\(""\s*:\s*"\+s"\((\w+)\)\);', '', body)
     if re.search(r'\basm\b', body):
         raise RuntimeError('pass source holds inline asm the emulator does not model')
-    full = _HEAD + body + _TAIL
+    # the last pass in its readout form takes the per-workgroup sums buffer
+    part = 'double* __restrict__ part)' in body
+    full = _HEAD + ('#define QS_EMU_PART , part\n' if part else '#define QS_EMU_PART\n') + body + _TAIL
     key = hashlib.sha1(full.encode()).hexdigest()[:20]
     os.makedirs(_CACHE, exist_ok=True)
     so = os.path.join(_CACHE, key + '.so')
@@ -102,17 +105,19 @@ def compile_pass(src: str):
         os.replace(tmp, so)
     lib = C.CDLL(so)
     lib.qs_emu_run.restype = C.c_int
-    lib.qs_emu_run.argtypes = [C.c_void_p, C.c_void_p, C.c_ulonglong, C.c_uint, C.c_uint]
+    lib.qs_emu_run.argtypes = [C.c_void_p, C.c_void_p, C.c_ulonglong, C.c_uint, C.c_uint, C.c_void_p]
     return lib
 
 
 def run_passes(circuit, amp: np.ndarray, nbits: int, prec: int, tile_qubits: int, thread_bits: int,
-               contig: int, kind: int, grid_div: int = 1) -> int:
+               contig: int, kind: int, grid_div: int = 1, readout: bool = False):
     """Apply every generated pass of `circuit` to `amp` (complex128 for
     QS_C128, complex64 for QS_C64; 2^nbits entries) in place.  Each pass runs
     on ntiles / grid_div workgroups, so grid_div > 1 exercises the tile loop
     and its prefetch.  For a density matrix pass nbits = 2N and kind =
-    DENSITY; `circuit.source` / `pass_data` take N.  Returns the pass count."""
+    DENSITY; `circuit.source` / `pass_data` take N.  Returns the pass count;
+    with readout (state vectors) the last pass runs in its readout form and
+    (pass count, per-workgroup sums of shape (grid, nbits + 1)) is returned."""
     from paper_1802_08032_amd import qstate as Q
     n_arg = nbits // 2 if kind == Q.DENSITY else nbits
     _, npass = circuit.source(n_arg, prec, tile_qubits, thread_bits, 0, 0, contig, kind=kind)
@@ -120,14 +125,17 @@ def run_passes(circuit, amp: np.ndarray, nbits: int, prec: int, tile_qubits: int
     grid = max(1, ntiles // grid_div)
     assert amp.flags.c_contiguous and amp.size == 1 << nbits
     assert amp.dtype == (np.complex128 if prec == Q.C128 else np.complex64)
+    part = np.full((grid, nbits + 1), np.nan)
     for p in range(npass):
-        src, _ = circuit.source(n_arg, prec, tile_qubits, thread_bits, p, 0, contig, kind=kind)
+        ro = readout and p == npass - 1
+        src, _ = circuit.source(n_arg, prec, tile_qubits, thread_bits, -1 if ro else p, 0, contig, kind=kind)
         mats = circuit.pass_data(n_arg, prec, tile_qubits, thread_bits, p, 0, contig, kind=kind)
         m = np.ascontiguousarray(mats if prec == Q.C128 else mats.astype(np.float32))
         if m.size == 0:
             m = np.zeros(1, dtype=m.dtype)
         lib = compile_pass(src)
-        rc = lib.qs_emu_run(amp.ctypes.data, m.ctypes.data, ntiles, grid, 1 << thread_bits)
+        rc = lib.qs_emu_run(amp.ctypes.data, m.ctypes.data, ntiles, grid, 1 << thread_bits,
+                            part.ctypes.data if ro else None)
         if rc:
             raise RuntimeError('emulated launch rejected its grid')
-    return npass
+    return (npass, part) if readout else npass

@@ -112,3 +112,38 @@ def test_two_qubit_unitaries_in_circuits():
     pass_emu.run_passes(c, amp, 2 * N, q.C128, 12, 8, 4, q.DENSITY, grid_div=2)
     c.close()
     assert np.abs(amp - ref).max() <= 1e-12
+
+
+@pytest.mark.parametrize('prec_name,shape,n,grid_div', [('C128', (12, 8, 4), 17, 4), ('C64', (12, 8, 4), 17, 2),
+                                                        ('C128', (11, 8, 4), 15, 1)])
+def test_readout_sums_of_the_last_pass(prec_name, shape, n, grid_div):
+    """The last pass in its readout form: each workgroup's sums of
+    |alpha|^2 in total and over bit q = 0 for every qubit (register bits
+    with pending flips, thread bits, tile-index bits), added over the
+    workgroups, against the oracle's total probability and outcome
+    probabilities of its final state (Sec. II.B.1); the stored state is
+    unchanged by the readout."""
+    import paper_1802_08032_amd as q
+    prec = getattr(q, prec_name)
+    K, TB, L = shape
+    from workloads.circuits import Op
+    ops = layered_circuit(n, 3, 11, mcphase=True) + random_gate_ops(n, 40, 5, max_controls=2)
+    # NOTs conditioned on tile-index qubits: flips still pending at the store
+    ops += [Op('x', target=t, controls=(n - 1,)) for t in range(4, 9)] + [Op('x', target=2, controls=(n - 2, 1))]
+    psi = random_state(n, 3)
+    ref = psi.astype(np.complex128).copy()
+    for op in ops:
+        O.apply_sv(ref, n, op)
+    amp = psi.astype(np.complex128 if prec == q.C128 else np.complex64).copy()
+    c = q.Circuit(ops)
+    if (prec_name, n) == ('C64', 17):
+        assert '? t - s0 : s0' in c.source(n, prec, K, TB, -1, 0, L)[0]
+    npass, part = pass_emu.run_passes(c, amp, n, prec, K, TB, L, q.STATEVEC, grid_div=grid_div, readout=True)
+    c.close()
+    assert npass >= 2
+    assert not np.isnan(part).any()
+    got = part.sum(axis=0)
+    want = np.array([O.sv_total_prob(ref, n)] + [O.sv_prob_outcome(ref, n, k, 0) for k in range(n)])
+    tol = 1e-12 if prec == q.C128 else 2e-5
+    assert np.abs(got - want).max() <= tol
+    assert np.abs(amp.astype(np.complex128) - ref).max() <= tol
