@@ -30,7 +30,8 @@
  *     (qs_measure* return once the outcome is known; the collapse that
  *     follows is queued on the stream like a gate).
  *   - The library is thread-safe across different registers; calls on one
- *     register must not overlap.
+ *     register must not overlap, nor calls that run one circuit handle (it
+ *     keeps its compiled plan).
  */
 #ifndef QSTATE_H
 #define QSTATE_H

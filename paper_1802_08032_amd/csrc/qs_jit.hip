@@ -1420,20 +1420,15 @@ struct JitPlan {
     std::string ro_src[2];
     hipFunction_t ro_fn[2] = {nullptr, nullptr};
     int ro_blocks_per_cu[2] = {1, 1};
-    double* ro_part = nullptr;  // per-workgroup sums, grid x (n + 1)
-    size_t ro_part_rows = 0;
-    double* ro_dev = nullptr;   // n + 1 sums
-    double* ro_host = nullptr;  // pinned copy
 };
 
 void jit_plan_free(JitPlan* p)
 {
     if (!p) return;
-    if (p->dmats || p->ro_part || p->ro_dev) (void)hipSetDevice(p->device);
-    if (p->dmats) (void)hipFree(p->dmats);
-    if (p->ro_part) (void)hipFree(p->ro_part);
-    if (p->ro_dev) (void)hipFree(p->ro_dev);
-    if (p->ro_host) (void)hipHostFree(p->ro_host);
+    if (p->dmats) {
+        (void)hipSetDevice(p->device);
+        (void)hipFree(p->dmats);
+    }
     delete p;
 }
 
@@ -1555,6 +1550,16 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
     const int ro_var = init_index && np == 1 ? 1 : 0;
     const int nv = nbits + 1;
     unsigned ro_grid = 0;
+    double* ro_buf = nullptr;
+    // releases the readout buffer once the work queued before it is done
+    struct RoFree {
+        double*& p;
+        hipStream_t s;
+        ~RoFree()
+        {
+            if (p) (void)hipFreeAsync(p, s);
+        }
+    } ro_free{ro_buf, r->stream};
     if (readout && np > 0) {
         if (!J->ro_fn[ro_var]) {
             std::vector<hipFunction_t> f;
@@ -1567,29 +1572,16 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
             J->ro_fn[ro_var] = f[0];
         }
         ro_grid = (unsigned)std::min<unsigned long long>(ntiles, 256ull * J->ro_blocks_per_cu[ro_var]);
-        if (J->ro_part_rows < ro_grid) {
-            if (J->ro_part) {
-                (void)hipStreamSynchronize(r->stream);  // an earlier run may still write it
-                (void)hipFree(J->ro_part);
-                J->ro_part = nullptr;
-                J->ro_part_rows = 0;
-            }
-            hipError_t e = hipMalloc(&J->ro_part, (size_t)ro_grid * nv * sizeof(double));
-            if (e != hipSuccess) return hip_error(e, "readout partial sums");
-            J->ro_part_rows = ro_grid;
-        }
-        if (!J->ro_dev) {
-            hipError_t e = hipMalloc(&J->ro_dev, nv * sizeof(double));
-            if (e == hipSuccess) e = hipHostMalloc(&J->ro_host, nv * sizeof(double), hipHostMallocDefault);
-            if (e != hipSuccess) return hip_error(e, "readout buffers");
-        }
+        // per call and stream-ordered: the workgroups' rows, then the sums
+        hipError_t e = hipMallocAsync((void**)&ro_buf, ((size_t)ro_grid + 1) * nv * sizeof(double), r->stream);
+        if (e != hipSuccess) return hip_error(e, "readout sums");
     }
     for (size_t p = 0; p < np; ++p) {
         void* amp = r->amp;
         const void* mp = (const char*)J->dmats + J->mat_off[p] * esz_of(r->prec);
         const bool first_init = init_index && p == 0;
         const bool ro = readout && p + 1 == np;
-        double* part = J->ro_part;
+        double* part = ro_buf;
         void* args[] = {&amp, &mp, &ntiles, &init_at, &part};
         void* args_ro[] = {&amp, &mp, &ntiles, &part};
         hipFunction_t fn = first_init ? J->init_fn : J->fns[p];
@@ -1614,14 +1606,14 @@ qs_status run_compiled_sv(qs_reg r, qs_circuit_s* c, FusedConfig cfg, int* passe
             if (s) return s;
         } else {
             const Launch L{r->stream, r->env->device};
+            double* sums = ro_buf + (size_t)ro_grid * nv;
             qs_status s = profiled(r, QS_K_REDUCE, [&](int*) {
-                return launch_sum_columns(L, J->ro_part, (int)ro_grid, nv, J->ro_dev);
+                return launch_sum_columns(L, ro_buf, (int)ro_grid, nv, sums);
             });
             if (s) return s;
-            hipError_t e = hipMemcpyAsync(J->ro_host, J->ro_dev, nv * sizeof(double), hipMemcpyDeviceToHost, r->stream);
+            hipError_t e = hipMemcpyAsync(readout, sums, nv * sizeof(double), hipMemcpyDeviceToHost, r->stream);
             if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
             if (e != hipSuccess) return hip_error(e, "readout copy");
-            memcpy(readout, J->ro_host, nv * sizeof(double));
         }
     }
     if (passes_out) *passes_out = (int)J->fns.size();
