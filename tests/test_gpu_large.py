@@ -144,3 +144,32 @@ def test_c64_33q_fidelity_against_c128_reference(q, env):
     c.close()
     del cur, ref
     release()
+
+
+def test_bench_step_readouts_32q(q, env):
+    """The bench step at full size: the bench circuit from |0..0> with the
+    readouts summed by its last pass.  The circuit is unitary, so the total
+    is 1; each qubit's P(q = 0) must equal what the reduction kernels sum
+    from the stored state (an independent path over the same amplitudes);
+    P(qubit q = 0) of the inverse-appended circuit is 1 for every q."""
+    n = 32
+    K, TB, L = BENCH_TILE
+    ops = layered_circuit(n, 10, 1, mcphase=True)
+    log('large readouts n=32 (bench circuit)')
+    reg = q.Register(env, n)
+    c = q.Circuit(ops)
+    passes, probs = c.run_compiled_probs(reg, K, TB, 0, L, init_basis=0)
+    c.close()
+    assert passes >= 2
+    assert abs(probs[0] - 1.0) <= 1e-12
+    for k in (0, 1, 5, 11, 12, 20, 31):
+        assert abs(probs[1 + k] - reg.calc_prob_of_outcome(k, 0)) <= 1e-13, k
+    assert np.all((probs[1:] >= 0.0) & (probs[1:] <= probs[0] + 1e-12))
+    ops2 = layered_circuit(n, 2, 9, mcphase=True)
+    c = q.Circuit(ops2 + inverse(ops2))
+    _, probs = c.run_compiled_probs(reg, K, TB, 0, L, init_basis=0)
+    c.close()
+    assert np.max(np.abs(probs - 1.0)) <= 1e-12
+    reg.close()
+    del reg
+    release()
