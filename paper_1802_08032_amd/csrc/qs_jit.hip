@@ -347,6 +347,9 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     // HBM write address, into a later gate on bit b, or applied with selects
     // when an op needs bit b as a control or as a 4x4 target.
     std::vector<std::string> pend(RB);
+    // pend_uni[b]: the flip's condition is the same on every lane of a wave
+    // (tile-index bits and wave-index thread bits only)
+    std::vector<char> pend_uni(RB, 1);
     int nflip = 0;
 
     // Deferred diagonal factors.  The true state is
@@ -388,6 +391,18 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     auto materialize = [&](uint32_t bits) {
         for (int b = 0; b < RB; ++b) {
             if (!((bits >> b) & 1) || pend[b].empty()) continue;
+            if (pend_uni[b]) {
+                // the same on the whole wave: a branch around plain swaps
+                s << "        if (__builtin_amdgcn_readfirstlane((int)(" << pend[b] << "))) {\n";
+                for (int r0 = 0; r0 < E; ++r0) {
+                    if ((r0 >> b) & 1) continue;
+                    const std::string A = vn(r0), B = vn(r0 | (1 << b));
+                    s << "            { const V t = " << A << "; " << A << " = " << B << "; " << B << " = t; }\n";
+                }
+                s << "        }\n";
+                pend[b].clear();
+                continue;
+            }
             s << "        {\n            const bool c = " << pend[b] << ";\n";
             for (int r0 = 0; r0 < E; ++r0) {
                 if ((r0 >> b) & 1) continue;
@@ -753,6 +768,8 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
                         const std::string f = "f" + std::to_string(nflip++);
                         s << "        const bool " << f << " = " << (pend[b].empty() ? "" : "(" + pend[b] + ") != ")
                           << "(" << cond << ");\n";
+                        const bool uni = (tmask & ((1u << std::min(TB, 6)) - 1)) == 0;
+                        pend_uni[b] = (pend[b].empty() ? 1 : pend_uni[b]) && uni;
                         pend[b] = f;
                     } else {
                         s << "        {\n            const bool c = " << cond << ";\n";

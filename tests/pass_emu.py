@@ -44,6 +44,7 @@ static inline void qs_emu_wave_barrier() { pthread_barrier_wait(&qs_emu_wbar[thr
 #define __launch_bounds__(x)
 #define __shared__ static
 #define __builtin_amdgcn_s_waitcnt(x) ((void)0)
+#define __builtin_amdgcn_readfirstlane(x) (x)
 '''
 
 _TAIL = r'''
