@@ -91,3 +91,23 @@ def test_circuit_parameter_setters_validate_on_the_host():
             bad()
     c.set_unitary(0, H)  # still usable
     c.close()
+
+
+def test_readout_source_is_the_last_pass_with_sums():
+    """qs_circuit_source with pass -1 (host only): the last pass in the form
+    qs_circuit_run_compiled_probs runs, with the per-workgroup sums buffer;
+    the ordinary form of the same pass has none, and a density matrix has
+    no readout form."""
+    import paper_1802_08032_amd as q
+    from workloads import layered_circuit
+    c = q.Circuit(layered_circuit(16, 3, seed=1, mcphase=True))
+    ro, npass = c.source(16, q.C128, 12, 8, -1, 0, 4)
+    last, _ = c.source(16, q.C128, 12, 8, npass - 1, 0, 4)
+    assert npass >= 2
+    assert 'double* __restrict__ part' in ro and 'ro_t += t' in ro
+    assert 'double* __restrict__ part' not in last and 'ro_t' not in last
+    with pytest.raises(q.QStateError, match='QS_E_KIND'):
+        c.source(8, q.C128, 12, 8, -1, 0, 4, kind=q.DENSITY)
+    with pytest.raises(q.QStateError, match='QS_E_ARG'):
+        c.source(16, q.C128, 12, 8, -2, 0, 4)
+    c.close()
