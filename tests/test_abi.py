@@ -106,8 +106,10 @@ def test_readout_source_is_the_last_pass_with_sums():
     assert npass >= 2
     assert 'double* __restrict__ part' in ro and 'ro_t += t' in ro
     assert 'double* __restrict__ part' not in last and 'ro_t' not in last
+    d = q.Circuit(layered_circuit(7, 1, seed=1))
     with pytest.raises(q.QStateError, match='QS_E_KIND'):
-        c.source(8, q.C128, 12, 8, -1, 0, 4, kind=q.DENSITY)
+        d.source(7, q.C128, 12, 8, -1, 0, 4, kind=q.DENSITY)
+    d.close()
     with pytest.raises(q.QStateError, match='QS_E_ARG'):
         c.source(16, q.C128, 12, 8, -2, 0, 4)
     c.close()
