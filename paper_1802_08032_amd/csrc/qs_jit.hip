@@ -1215,18 +1215,13 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     }
     s << "}\n";
 
-    // Tile loop with a one-tile prefetch: the workgroup's next tile is loaded
-    // while its current one is computed.  The matrix pointer is made to depend
+    // Tile loop with a one-tile prefetch: tile t + gridDim.x is loaded while
+    // tile t is computed.  The matrix pointer is made to depend
     // on the tile (the added term is always 0) so that the scalar matrix loads
     // stay in the loop instead of being hoisted out of it.
     std::ostringstream loop;
     loop << pro.str();
-    // each workgroup takes a contiguous range of tile indices: consecutive
-    // tiles of one workgroup differ in the lowest qubits outside the tile,
-    // so they cover neighbouring runs of the same DRAM pages
-    loop << "    const unsigned long long per_wg = (ntiles + gridDim.x - 1) / gridDim.x;\n";
-    loop << "    unsigned long long tile = (unsigned long long)blockIdx.x * per_wg;\n";
-    loop << "    const unsigned long long tile_end = tile + per_wg < ntiles ? tile + per_wg : ntiles;\n";
+    loop << "    unsigned long long tile = blockIdx.x;\n";
     if (readout_n > 0) {
         loop << "    if (tile >= ntiles) {\n";
         loop << "        for (unsigned j = tid; j < " << nv << "u; j += " << (1 << TB) << "u) part[(unsigned long long)blockIdx.x * "
@@ -1258,8 +1253,8 @@ GenOut generate(const PassPlan& P, const std::vector<OpRec>& all, int TB, int RB
     // next to their use instead of being hoisted and held in registers.
     loop << "        const unsigned z = (unsigned)(tile >> 62);\n";
     loop << "        const R* mt = mats + z;\n";
-    loop << "        const unsigned long long ntile = tile + 1;\n";
-    loop << "        const bool more = ntile < tile_end;\n";
+    loop << "        const unsigned long long ntile = tile + gridDim.x;\n";
+    loop << "        const bool more = ntile < ntiles;\n";
     for (int r = 0; r < E; ++r) loop << "        V n" << r << ";\n";
     loop << "        if (more) {\n";
     loop << "            const unsigned long long nb = ins(ntile);\n";
